@@ -1,0 +1,237 @@
+"""FP64 CPU reference ("oracle") for the conductance-LIF partition step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library (``paper_2308_01241_amd``) and never imports it;
+both consume the seeded inputs of ``netgen``.
+
+Contents
+--------
+* ``dtb_oracle.c`` (wrapped here as :class:`OracleNet`): the step iteration of
+  the paper's model (Sec. III-B Eq. (1); in-step order of Sec. V-B / VI-C;
+  forward Euler at 1 ms, Sec. VI-A) in FP64, Philox4x64-10 background draws
+  and the Poisson inversion table.
+* ``brute.py``: a dense-tensor formulation of the same step for tiny nets,
+  used to pin the sparse gather and the delay ring.
+* ``bold.py``: Balloon-Windkessel hemodynamics (the BOLD model the paper's
+  assimilation uses, Sec. V-E) in FP64.
+* ``mlp.py``: FP64 forward/backward of the surrogate MLP.
+
+Parity status of each function is listed in its docstring ("pinned by ...").
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dtb_oracle.c")
+_LIB = os.path.join(_HERE, "_oracle.so")
+_lib = None
+
+FIELDS = {"V": 0, "j_AMPA": 1, "j_NMDA": 2, "j_GABAa": 3, "j_GABAb": 4, "ref": 5}
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-fno-fast-math", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Input(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_regions", ctypes.c_int32), ("max_delay", ctypes.c_int32),
+                ("n_ptypes", ctypes.c_int32), ("member", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("delay", ctypes.c_void_p), ("is_inh", ctypes.c_void_p), ("region", ctypes.c_void_p),
+                ("ptype", ctypes.c_void_p), ("ptypes", ctypes.c_void_p), ("V0", ctypes.c_void_p),
+                ("E", ctypes.c_double * 4), ("tau_ms", ctypes.c_double * 4), ("dt_ms", ctypes.c_double),
+                ("bg_lambda", ctypes.c_double), ("bg_w", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("gain", ctypes.c_void_p)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.ora_create.argtypes = [ctypes.POINTER(_Input)]
+        lib.ora_create.restype = P
+        lib.ora_destroy.argtypes = [P]
+        lib.ora_step.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, P]
+        lib.ora_step.restype = ctypes.c_int
+        lib.ora_get.argtypes = [P, ctypes.c_int, P]
+        lib.ora_set.argtypes = [P, ctypes.c_int, P]
+        lib.ora_set_gain.argtypes = [P, P]
+        lib.ora_time.argtypes = [P]
+        lib.ora_time.restype = ctypes.c_int64
+        lib.ora_philox4x64_10.argtypes = [P, P, P]
+        lib.ora_poisson_table.argtypes = [ctypes.c_double, P, ctypes.c_int]
+        lib.ora_poisson_table.restype = ctypes.c_int
+        lib.ora_bg_uniform.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        lib.ora_bg_uniform.restype = ctypes.c_uint32
+        lib.ora_poisson_K.argtypes = [P]
+        lib.ora_poisson_K.restype = ctypes.c_int
+        lib.ora_decay.argtypes = [P, ctypes.c_int]
+        lib.ora_decay.restype = ctypes.c_double
+        lib.ora_max_threads.restype = ctypes.c_int
+        lib.ora_set_threads.argtypes = [ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def philox4x64_10(ctr, key) -> np.ndarray:
+    """Philox4x64 with 10 rounds (Salmon et al., SC'11).  Pinned bit-exactly
+    against numpy's ``random.Philox`` in the tests."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    _load().ora_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def poisson_table(lam: float, cap: int = 512) -> np.ndarray:
+    """Inversion thresholds T_k = floor(F(k) 2^32) while below 2^32-1.
+    Pinned against scipy's Poisson CDF in the tests."""
+    T = np.zeros(cap, dtype=np.uint32)
+    K = _load().ora_poisson_table(float(lam), _p(T), cap)
+    if K < 0:
+        raise ValueError("lambda out of range for the table")
+    return T[:K].copy()
+
+
+def bg_uniform(seed: int, t: int, i: int, member: int = 0) -> int:
+    return int(_load().ora_bg_uniform(seed, t, i, member))
+
+
+def max_threads() -> int:
+    return int(_load().ora_max_threads())
+
+
+def set_threads(n: int) -> None:
+    _load().ora_set_threads(int(n))
+
+
+class OracleNet:
+    """FP64 reference simulation of one network (borrows the Network arrays)."""
+
+    def __init__(self, net, gain=None):
+        lib = _load()
+        self.net = net
+        self._keep = []
+
+        def keep(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        inp = _Input()
+        inp.n = net.n
+        inp.n_regions = net.n_regions
+        inp.max_delay = net.max_delay
+        inp.n_ptypes = int(net.ptypes.shape[0])
+        inp.member = int(net.member)
+        inp.row_ptr = _p(keep(net.row_ptr, np.int64))
+        inp.col = _p(keep(net.col, np.int32))
+        inp.w = _p(keep(net.w, np.float32))
+        inp.delay = _p(keep(net.delay, np.uint8))
+        inp.is_inh = _p(keep(net.is_inh, np.uint8))
+        inp.region = _p(keep(net.region, np.int32))
+        inp.ptype = _p(keep(net.ptype, np.uint16))
+        inp.ptypes = _p(keep(net.ptypes, np.float32))
+        inp.V0 = _p(keep(net.V0, np.float32))
+        for u in range(4):
+            inp.E[u] = float(net.E[u])
+            inp.tau_ms[u] = float(net.tau_ms[u])
+        inp.dt_ms = float(net.dt_ms)
+        inp.bg_lambda = float(net.bg_lambda)
+        inp.bg_w = float(net.bg_w)
+        inp.seed = int(net.seed)
+        inp.gain = _p(keep(gain, np.float64)) if gain is not None else None
+        self._inp = inp
+        h = lib.ora_create(ctypes.byref(inp))
+        if not h:
+            raise ValueError("oracle: invalid network or out of memory")
+        self._h = ctypes.c_void_p(h)
+        self._lib = lib
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ora_destroy(h)
+            self._h = None
+
+    @property
+    def t(self) -> int:
+        return int(self._lib.ora_time(self._h))
+
+    def decay(self, u: int) -> float:
+        return float(self._lib.ora_decay(self._h, u))
+
+    def poisson_K(self) -> int:
+        return int(self._lib.ora_poisson_K(self._h))
+
+    def set_gain(self, gain) -> None:
+        g = np.ascontiguousarray(gain, dtype=np.float64).reshape(self.net.n_regions, 4)
+        self._lib.ora_set_gain(self._h, _p(g))
+
+    def step(self, forced=None, rows=None, want_margin=False):
+        """Advance one step.  Returns dict(spikes, margin, counts, ev_rec, ev_bg)."""
+        n = self.net.n
+        spikes = np.zeros(n, dtype=np.uint8)
+        margin = np.full(n, np.nan) if want_margin else None
+        counts = np.zeros(self.net.n_regions, dtype=np.int64)
+        er = ctypes.c_int64(0)
+        eb = ctypes.c_int64(0)
+        f = None if forced is None else np.ascontiguousarray(forced, dtype=np.uint8)
+        r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+        rc = self._lib.ora_step(self._h, _p(f), _p(r), 0 if r is None else len(r), _p(spikes),
+                                _p(margin), _p(counts), ctypes.byref(er), ctypes.byref(eb))
+        if rc != 0:
+            raise ValueError("oracle step: a row subset needs a forced raster")
+        return {"spikes": spikes, "margin": margin, "counts": counts,
+                "ev_rec": int(er.value), "ev_bg": int(eb.value)}
+
+    def get(self, field: str) -> np.ndarray:
+        out = np.empty(self.net.n, dtype=np.float64)
+        self._lib.ora_get(self._h, FIELDS[field], _p(out))
+        return out
+
+    def set(self, field: str, values) -> None:
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        self._lib.ora_set(self._h, FIELDS[field], _p(v))
+
+    def state(self) -> dict:
+        return {k: self.get(k) for k in FIELDS}
+
+    def run(self, n_steps: int, forced=None, want_state=False, want_margin=False):
+        """Run n steps; returns raster [n_steps, n] (uint8), counts [n_steps, R],
+        ev_rec/ev_bg [n_steps], optionally per-step states and margins."""
+        n = self.net.n
+        raster = np.zeros((n_steps, n), dtype=np.uint8)
+        counts = np.zeros((n_steps, self.net.n_regions), dtype=np.int64)
+        ev = np.zeros((n_steps, 2), dtype=np.int64)
+        states = [] if want_state else None
+        margins = np.full((n_steps, n), np.nan) if want_margin else None
+        for s in range(n_steps):
+            o = self.step(None if forced is None else forced[s], want_margin=want_margin)
+            raster[s] = o["spikes"]
+            counts[s] = o["counts"]
+            ev[s] = (o["ev_rec"], o["ev_bg"])
+            if want_margin:
+                margins[s] = o["margin"]
+            if want_state:
+                states.append(self.state())
+        return {"raster": raster, "counts": counts, "ev_rec": ev[:, 0], "ev_bg": ev[:, 1],
+                "states": states, "margins": margins}

@@ -1,0 +1,321 @@
+/*
+ * dtb_oracle.c - plain FP64 CPU reference of one partition step of the
+ * conductance-based LIF network.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the simulator's product path links,
+ * loads or calls this file; only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no code with the GPU library.
+ *
+ * What it computes (paper: Sec. III-B Eq. (1) for the neuron, Sec. V-B and
+ * the time anchors of Sec. VI-C for the order inside a step, Sec. VI-A for
+ * forward Euler with a 1 ms step):
+ *
+ *   state before step t: V^t, gates j_u^t (u = AMPA, NMDA, GABAa, GABAb),
+ *   refractory counter ref^t, and the spikes s^{t'} of all t' < t.
+ *
+ *   1. if ref^t > 0:  V^{t+1} = V_reset, ref^{t+1} = ref^t - 1, s^t = 0
+ *      else:          Vt = V^t + dt/C [ -gL (V^t - EL)
+ *                                       + sum_u g_u gain_u j_u^t (E_u - V^t) + Iext ]
+ *                     s^t = [Vt >= Vth]; spike -> V^{t+1} = V_reset,
+ *                     ref^{t+1} = n_ref = round(T_ref / dt); else V^{t+1} = Vt.
+ *   2. the spikes s^t enter the delay ring buffer.
+ *   3. pull over the in-edges k of row i, in CSR order:
+ *        dE_i = sum_{k: m_k exc} w_k s^{t-d_k+1}_{m_k} + w_bg c_i^t
+ *        dI_i = sum_{k: m_k inh} w_k s^{t-d_k+1}_{m_k}
+ *      (a spike sent at step e through delay d is gathered in step e+d-1 and
+ *      first moves V in step e+d; d = 1 is the paper's one-step exchange).
+ *      c_i^t is the background Poisson count standing in for the spikes of
+ *      other partitions (J_inter of Sec. V-B).
+ *   4. gates: jump and exponential decay (Sec. III-B), exact between jumps:
+ *        j_u^{t+1} = exp(-dt/tau_u) j_u^t + dE_i (AMPA, NMDA) or dI_i (GABAs).
+ *   5. per-region spike counts of step t.
+ *
+ * Background draws: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), key
+ * (seed, 0), counter (t, i, member, 0); the high 32 bits u of output word 0
+ * are turned into a Poisson(lambda) count by inversion against the table
+ * T_k = floor(F(k) 2^32) (F the Poisson CDF, entries kept while below
+ * 2^32 - 1): c = #{k : u >= T_k}.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ Philox */
+
+static inline void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+void ora_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; r++) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(M0, x0, &hi0, &lo0);
+    mulhilo64(M1, x2, &hi1, &lo1);
+    uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/*
+ * Poisson(lambda) inversion table T_k = floor(F(k) 2^32), k = 0, 1, ...,
+ * kept while T_k < 2^32 - 1 (the first saturated entry ends the table, so a
+ * draw u counts c = #{k < K : u >= T_k}; lambda = 0 gives K = 0, c = 0).
+ * F(k) is accumulated from p_0 = exp(-lambda), p_k = p_{k-1} lambda / k.
+ * Returns K, or -1 if cap entries are not enough.
+ */
+int ora_poisson_table(double lambda, uint32_t* T, int cap) {
+  if (!(lambda >= 0.0) || !(lambda < 700.0) || cap < 1) return -1;
+  const double two32 = 4294967296.0;
+  double p = exp(-lambda), F = p;
+  for (int k = 0; k < cap; k++) {
+    double x = floor(F * two32);
+    if (x >= 4294967295.0) return k;
+    T[k] = (uint32_t)x;
+    p = p * lambda / (double)(k + 1);
+    F = F + p;
+  }
+  return -1;
+}
+
+static inline int poisson_count(uint32_t u, const uint32_t* T, int K) {
+  int c = 0;
+  while (c < K && u >= T[c]) c++;
+  return c;
+}
+
+uint32_t ora_bg_uniform(uint64_t seed, int64_t t, int64_t i, int64_t member) {
+  uint64_t ctr[4] = {(uint64_t)t, (uint64_t)i, (uint64_t)member, 0};
+  uint64_t key[2] = {seed, 0};
+  uint64_t out[4];
+  ora_philox4x64_10(ctr, key, out);
+  return (uint32_t)(out[0] >> 32);
+}
+
+/* ------------------------------------------------------------- network */
+
+typedef struct {
+  int64_t n;
+  int32_t n_regions, max_delay, n_ptypes, member;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* w;
+  const uint8_t* delay;
+  const uint8_t* is_inh;
+  const int32_t* region;
+  const uint16_t* ptype;
+  const float* ptypes; /* [n_ptypes][11]: C gL EL Vth Vreset tref Iext gA gN gGa gGb */
+  const float* V0;
+  double E[4], tau_ms[4], dt_ms;
+  double bg_lambda, bg_w;
+  uint64_t seed;
+  const double* gain; /* [n_regions][4] or NULL (all ones) */
+} ora_input;
+
+typedef struct {
+  ora_input in;
+  double a[4];
+  /* per parameter type */
+  double *C, *gL, *EL, *Vth, *Vreset, *Iext, *g; /* g: [n_ptypes][4] */
+  int32_t* nref;
+  uint32_t T[512];
+  int K;
+  /* state */
+  int64_t t;
+  double* V;
+  double* j; /* [4][n] */
+  int32_t* ref;
+  uint8_t* ring; /* [max_delay][n] */
+  double* gain;  /* [n_regions][4] */
+} ora_net;
+
+void ora_destroy(ora_net* h) {
+  if (!h) return;
+  free(h->C); free(h->gL); free(h->EL); free(h->Vth); free(h->Vreset); free(h->Iext);
+  free(h->g); free(h->nref); free(h->V); free(h->j); free(h->ref); free(h->ring); free(h->gain);
+  free(h);
+}
+
+/* returns NULL on invalid input or allocation failure */
+ora_net* ora_create(const ora_input* in) {
+  if (!in || in->n <= 0 || in->n_regions <= 0 || in->max_delay < 1 || in->n_ptypes < 1 ||
+      !(in->dt_ms > 0.0))
+    return NULL;
+  ora_net* h = (ora_net*)calloc(1, sizeof(ora_net));
+  if (!h) return NULL;
+  h->in = *in;
+  const int64_t n = in->n;
+  const int P = in->n_ptypes;
+  for (int u = 0; u < 4; u++) h->a[u] = exp(-in->dt_ms / in->tau_ms[u]);
+  h->C = malloc(sizeof(double) * P); h->gL = malloc(sizeof(double) * P);
+  h->EL = malloc(sizeof(double) * P); h->Vth = malloc(sizeof(double) * P);
+  h->Vreset = malloc(sizeof(double) * P); h->Iext = malloc(sizeof(double) * P);
+  h->g = malloc(sizeof(double) * P * 4); h->nref = malloc(sizeof(int32_t) * P);
+  h->V = malloc(sizeof(double) * n); h->j = calloc((size_t)n * 4, sizeof(double));
+  h->ref = calloc((size_t)n, sizeof(int32_t));
+  h->ring = calloc((size_t)n * in->max_delay, 1);
+  h->gain = malloc(sizeof(double) * in->n_regions * 4);
+  if (!h->C || !h->gL || !h->EL || !h->Vth || !h->Vreset || !h->Iext || !h->g || !h->nref ||
+      !h->V || !h->j || !h->ref || !h->ring || !h->gain) {
+    ora_destroy(h);
+    return NULL;
+  }
+  for (int p = 0; p < P; p++) {
+    const float* r = in->ptypes + 11 * p;
+    h->C[p] = r[0]; h->gL[p] = r[1]; h->EL[p] = r[2]; h->Vth[p] = r[3]; h->Vreset[p] = r[4];
+    h->nref[p] = (int32_t)lround((double)r[5] / in->dt_ms);
+    h->Iext[p] = r[6];
+    for (int u = 0; u < 4; u++) h->g[4 * p + u] = r[7 + u];
+  }
+  for (int r = 0; r < in->n_regions; r++)
+    for (int u = 0; u < 4; u++) h->gain[4 * r + u] = in->gain ? in->gain[4 * r + u] : 1.0;
+  h->K = ora_poisson_table(in->bg_lambda, h->T, 512);
+  if (h->K < 0) { ora_destroy(h); return NULL; }
+  for (int64_t i = 0; i < n; i++) h->V[i] = in->V0[i];
+  h->t = 0;
+  return h;
+}
+
+int64_t ora_time(const ora_net* h) { return h->t; }
+
+int ora_set_gain(ora_net* h, const double* gain) {
+  for (int r = 0; r < h->in.n_regions; r++)
+    for (int u = 0; u < 4; u++) h->gain[4 * r + u] = gain[4 * r + u];
+  return 0;
+}
+
+/*
+ * One step.  forced: optional [n] spike raster of this step that replaces the
+ * threshold test (teacher forcing: the forced bit decides spike, reset and
+ * ring entry).  rows/n_rows: optional subset of neurons whose state is
+ * advanced (requires forced, since the spikes of the others are unknown).
+ * Outputs (each optional): spikes [n], margin [n] = |Vt - Vth| for
+ * non-refractory neurons (NAN otherwise), region_counts [n_regions],
+ * ev_rec / ev_bg (delivered recurrent / background events of the rows).
+ */
+int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_rows,
+             uint8_t* spikes, double* margin, int64_t* region_counts, int64_t* ev_rec,
+             int64_t* ev_bg) {
+  const ora_input* in = &h->in;
+  const int64_t n = in->n;
+  const int D = in->max_delay;
+  const int64_t t = h->t;
+  if (rows && !forced) return -1;
+  const int64_t nr = rows ? n_rows : n;
+  uint8_t* slot_now = h->ring + (size_t)(t % D) * n;
+
+  /* 1. neuron update (all neurons, or the subset) */
+#pragma omp parallel for schedule(static) if (nr > 16384)
+  for (int64_t q = 0; q < nr; q++) {
+    const int64_t i = rows ? rows[q] : q;
+    const int p = in->ptype[i];
+    const int reg = in->region[i];
+    const double V = h->V[i];
+    const int r = h->ref[i];
+    double Vt = NAN;
+    if (r <= 0) {
+      double I = h->Iext[p];
+      for (int u = 0; u < 4; u++)
+        I += h->g[4 * p + u] * h->gain[4 * reg + u] * h->j[(size_t)u * n + i] * (in->E[u] - V);
+      Vt = V + in->dt_ms / h->C[p] * (-h->gL[p] * (V - h->EL[p]) + I);
+    }
+    int s;
+    if (forced) s = forced[i] ? 1 : 0;
+    else s = (r <= 0 && Vt >= h->Vth[p]) ? 1 : 0;
+    if (s) { h->V[i] = h->Vreset[p]; h->ref[i] = h->nref[p]; }
+    else if (r > 0) { h->V[i] = h->Vreset[p]; h->ref[i] = r - 1; }
+    else { h->V[i] = Vt; h->ref[i] = 0; }
+    if (margin) margin[i] = (r <= 0) ? fabs(Vt - h->Vth[p]) : NAN;
+    if (!forced) slot_now[i] = (uint8_t)s;
+  }
+  /* 2. spikes of this step into the ring (teacher forcing: the given raster) */
+  if (forced) {
+#pragma omp parallel for schedule(static) if (n > 16384)
+    for (int64_t i = 0; i < n; i++) slot_now[i] = forced[i] ? 1 : 0;
+  }
+  if (spikes) memcpy(spikes, slot_now, (size_t)n);
+
+  /* 3.-4. pull gather over in-edges in CSR order, background, gate update */
+  int64_t er = 0, eb = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : er, eb) if (nr > 1024)
+  for (int64_t q = 0; q < nr; q++) {
+    const int64_t i = rows ? rows[q] : q;
+    double dE = 0.0, dI = 0.0;
+    for (int64_t k = in->row_ptr[i]; k < in->row_ptr[i + 1]; k++) {
+      const int32_t m = in->col[k];
+      const int64_t te = t - (int64_t)in->delay[k] + 1;
+      const int64_t sl = ((te % D) + D) % D;
+      if (h->ring[(size_t)sl * n + m]) {
+        if (in->is_inh[m]) dI += (double)in->w[k];
+        else dE += (double)in->w[k];
+        er++;
+      }
+    }
+    const int c = poisson_count(ora_bg_uniform(in->seed, t, i, in->member), h->T, h->K);
+    dE += in->bg_w * (double)c;
+    eb += c;
+    h->j[0 * (size_t)n + i] = h->a[0] * h->j[0 * (size_t)n + i] + dE;
+    h->j[1 * (size_t)n + i] = h->a[1] * h->j[1 * (size_t)n + i] + dE;
+    h->j[2 * (size_t)n + i] = h->a[2] * h->j[2 * (size_t)n + i] + dI;
+    h->j[3 * (size_t)n + i] = h->a[3] * h->j[3 * (size_t)n + i] + dI;
+  }
+  if (ev_rec) *ev_rec = er;
+  if (ev_bg) *ev_bg = eb;
+
+  /* 5. region spike counts of step t */
+  if (region_counts) {
+    memset(region_counts, 0, sizeof(int64_t) * in->n_regions);
+    for (int64_t i = 0; i < n; i++) region_counts[in->region[i]] += slot_now[i];
+  }
+  h->t = t + 1;
+  return 0;
+}
+
+/* field: 0 = V, 1..4 = gates AMPA NMDA GABAa GABAb, 5 = refractory counter */
+int ora_get(const ora_net* h, int field, double* out) {
+  const int64_t n = h->in.n;
+  if (field == 0) memcpy(out, h->V, sizeof(double) * n);
+  else if (field >= 1 && field <= 4) memcpy(out, h->j + (size_t)(field - 1) * n, sizeof(double) * n);
+  else if (field == 5) for (int64_t i = 0; i < n; i++) out[i] = h->ref[i];
+  else return -1;
+  return 0;
+}
+
+int ora_set(ora_net* h, int field, const double* src) {
+  const int64_t n = h->in.n;
+  if (field == 0) memcpy(h->V, src, sizeof(double) * n);
+  else if (field >= 1 && field <= 4) memcpy(h->j + (size_t)(field - 1) * n, src, sizeof(double) * n);
+  else if (field == 5) for (int64_t i = 0; i < n; i++) h->ref[i] = (int32_t)src[i];
+  else return -1;
+  return 0;
+}
+
+int ora_poisson_K(const ora_net* h) { return h->K; }
+double ora_decay(const ora_net* h, int u) { return h->a[u]; }
+
+int ora_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void ora_set_threads(int nt) {
+#ifdef _OPENMP
+  if (nt > 0) omp_set_num_threads(nt);
+#else
+  (void)nt;
+#endif
+}
