@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark: one GPU's partition of the conductance-LIF network.
+
+Workload (default): 20,000,000 neurons in 90 log-normally sized regions,
+in-degree 100 (2e9 synapses), delays 1-20 steps, dt = 1 ms, background
+drive tuned to ~7 / 15 / 30 Hz.  A "step" is one pass of the whole hot path
+(membrane update + spike bitmap + compaction + pull gather through the delay
+ring + background + gate update + counters).  Inputs are synthetic and
+seeded (netgen), resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is synaptic events/s of the plain FP32 path
+at the 7 Hz point; the other rates, the realtime factor, the gather roofline
+and the FP64 reference timed on the host (a bounded sample) ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "synaptic events/s & realtime factor, plain vs BF16/batched; surrogate err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gather_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) -> float:
+    """Algorithmic bytes of one gather launch: 5 B of index + delay per
+    synapse, the weight of each delivered event, the four gates read and
+    written (32 B per neuron) and the D+1 delayed spike bits per neuron."""
+    return 5.0 * nnz + w_bytes * events + 32.0 * n + n * (max_delay + 1) / 8.0
+
+
+def run_rate(net, rate, lam, steps, warmup, wtype):
+    import torch
+    import paper_2308_01241_amd as dtb
+
+    net.bg_lambda = lam
+    t0 = time.time()
+    g = dtb.Net(net, wtype=wtype, record_steps=max(steps, 16), stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    log(f"[bench] {rate} Hz: created in {time.time() - t0:.1f}s; warmup {warmup}")
+    g.step(warmup)
+    g.sync()
+    c0 = g.counters()
+    g.read_timing()
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    tic = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tic
+    g.set_timing(False)
+    kt = g.read_timing()
+    g.sync()
+    c1 = g.counters()
+    ev = c1["ev_rec"] - c0["ev_rec"]
+    spikes = c1["spikes"] - c0["spikes"]
+    rates = g.region_rates(g.t - min(steps, g.record_steps), g.t)
+    g.close()
+    del g
+    torch.cuda.synchronize()
+    return {"rate_target_hz": rate, "bg_lambda": lam, "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+            "events": ev, "events_per_s": ev / wall, "rtf": wall / (steps * net.dt_ms * 1e-3),
+            "mean_rate_hz": spikes / (net.n * steps * net.dt_ms * 1e-3),
+            "region_rate_spread": [float(np.min(rates)), float(np.max(rates))],
+            "bg_events_per_s": (c1["ev_bg"] - c0["ev_bg"]) / wall, "kernels": kt}
+
+
+def cpu_baseline(net, rate_hz: float, frac: float = 0.02, warm: int = 20, timed: int = 10):
+    """FP64 reference on the host cores: a random `frac` of the rows of the
+    same partition, teacher-forced by a seeded synthetic raster at rate_hz
+    (the first `warm` steps fill the delay ring, the next `timed` are timed)."""
+    import oracle
+
+    o = oracle.OracleNet(net)
+    rng = np.random.default_rng(777)
+    rows = np.sort(rng.choice(net.n, size=max(1, int(frac * net.n)), replace=False)).astype(np.int64)
+    p = rate_hz * net.dt_ms * 1e-3
+    ev = 0
+    el = 0.0
+    for s in range(warm + timed):
+        forced = (rng.random(net.n) < p).astype(np.uint8)
+        tic = time.perf_counter()
+        out = o.step(forced=forced, rows=rows)
+        dt = time.perf_counter() - tic
+        if s >= warm:
+            ev += out["ev_rec"]
+            el += dt
+    cores = oracle.max_threads()
+    step_s = el / timed
+    return {"value": ev / el, "unit": "synaptic events/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{len(rows)} random rows ({frac:.0%}) of the {net.n}-neuron partition, "
+                       f"{warm} ring-filling + {timed} timed teacher-forced steps at {rate_hz} Hz "
+                       f"(synthetic seeded raster)"),
+            "rtf_extrapolated": step_s / frac / (net.dt_ms * 1e-3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=20_000_000)
+    ap.add_argument("--rates", type=str, default="7,15,30")
+    ap.add_argument("--wtype", type=str, default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU's partition; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU exchange is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import netgen
+    import paper_2308_01241_amd as dtb
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dtb.load()
+    rates = [int(x) for x in args.rates.split(",")]
+    t0 = time.time()
+    net = netgen.make_network(netgen.partition_spec(n=args.n, rate_hz=rates[0]))
+    log(f"[bench] generated n={net.n} nnz={net.nnz} in {time.time() - t0:.1f}s")
+    res = {}
+    for r in rates:
+        res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype)
+        log(f"[bench] {r} Hz: {json.dumps({k: v for k, v in res[r].items() if k != 'kernels'})}")
+        log(f"[bench] {r} Hz kernels: {res[r]['kernels']}")
+    head = res[rates[0]]
+    wb = 2 if args.wtype == "bf16" else 4
+    kg = head["kernels"]["gather"]
+    g_ms = kg["ms"] / max(1, kg["launches"])
+    ev_step = head["events"] / args.steps
+    B = gather_bytes(net.nnz, net.n, net.max_delay, ev_step, wb)
+    achieved = B / (g_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_gather",
+            "algorithmic_bytes_per_launch": B, "avg_launch_ms": g_ms}
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] cpu baseline (FP64 reference, bounded sample)")
+        cpu = cpu_baseline(net, float(rates[0]))
+        log(f"[bench] cpu: {cpu}")
+    out = {"metric": METRIC, "value": head["events_per_s"], "unit": "synaptic events/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.wtype, "data": "synthetic",
+           "config": {"workload": f"partition_net: {net.n} neurons, {net.nnz} synapses, 90 regions, "
+                                  f"in-degree 100, delays 1-{net.max_delay}, dt 1 ms, {rates[0]} Hz",
+                      "global_batch": 1, "seq_len": args.steps, "parallelism": "single-gpu"},
+           "rtf": head["rtf"], "roofline": roof, "cpu_baseline": cpu,
+           "rates": {str(r): {k: v for k, v in res[r].items() if k != "kernels"} for r in rates},
+           "kernels_ms_per_step": {k: v["ms"] / max(1, v["launches"]) for k, v in head["kernels"].items()}}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * dtb.h - C ABI of the MI355X partition simulator for the conductance-based
+ * leaky integrate-and-fire network of "Digital Twin Brain" (arXiv 2308.01241).
+ *
+ * One handle holds one partition of the network on one GPU: the neuron
+ * property table and connection table of Sec. V-D, the neuron state of
+ * Sec. III-B Eq. (1), and the integer delay ring that carries spikes between
+ * steps.  A step is the computing cycle of Sec. V-B / VI-C: membrane update
+ * and spike collection, then the weighted sum over presynaptic spikes
+ * (J_intra) with the spikes of other partitions (J_inter) replaced by a seeded
+ * Poisson count, then the gate update.  Time stepping is forward Euler with
+ * dt = 1 ms (Sec. VI-A); gates jump and decay exponentially (Sec. III-B),
+ * integrated exactly between jumps.
+ *
+ * Conventions shared by every entry point
+ *  - No C++ types or exceptions cross this boundary; every call returns a
+ *    dtb_status and never aborts.  dtb_last_error() describes the last
+ *    failure of the calling thread.
+ *  - Input arrays are borrowed only for the duration of the call that takes
+ *    them and are deep-copied; the library never keeps or frees caller memory.
+ *  - All GPU work is enqueued on the hipStream_t given at creation (a
+ *    void* here; NULL = the legacy default stream).  Reads into device
+ *    memory are stream-ordered; reads into host memory synchronize the stream.
+ *  - Neuron ids are 0..n-1.  Spike bitmaps hold neuron i at bit (i & 31) of
+ *    32-bit word (i >> 5); a step's bitmap has dtb_bitmap_words(n) words.
+ *  - Errors found while validating inputs return DTB_ERR_INVALID with a
+ *    message naming the first offending index.  A failing HIP call returns
+ *    DTB_ERR_HIP and makes the handle's error sticky: every later call on it
+ *    returns DTB_ERR_STATE until it is destroyed.
+ */
+#ifndef DTB_H
+#define DTB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DTB_ABI_VERSION 1
+
+typedef enum {
+  DTB_OK = 0,
+  DTB_ERR_INVALID = -1,     /* an argument or an input array failed validation */
+  DTB_ERR_OOM = -2,         /* device or host allocation failed */
+  DTB_ERR_HIP = -3,         /* a HIP runtime call failed (handle becomes sticky-failed) */
+  DTB_ERR_STATE = -4,       /* call not valid in the handle's current state */
+  DTB_ERR_NUMERIC = -5,     /* non-finite membrane potential or gate detected */
+  DTB_ERR_UNSUPPORTED = -6  /* valid request outside what this build implements */
+} dtb_status;
+
+typedef enum { DTB_W_F32 = 0, DTB_W_BF16 = 1 } dtb_wtype;
+
+typedef enum {
+  DTB_V = 0,        /* membrane potential, mV (float32) */
+  DTB_J_AMPA = 1,   /* gating variables j_u of Eq. (1) (float32) */
+  DTB_J_NMDA = 2,
+  DTB_J_GABAA = 3,
+  DTB_J_GABAB = 4,
+  DTB_REF = 5       /* remaining refractory steps (returned as float32) */
+} dtb_field;
+
+/* One row of the neuron property table (Sec. V-D): the configurable
+ * parameters of Eq. (1).  Units: C in the same unit as the conductances
+ * times ms, potentials in mV, tref in ms. */
+typedef struct dtb_ptype {
+  float C, gL, EL, Vth, Vreset, tref_ms, Iext;
+  float g[4]; /* channel conductances g_u: AMPA, NMDA, GABAa, GABAb */
+} dtb_ptype;
+
+/* Network description.  The connection table of Sec. V-D is given as an
+ * in-edge CSR (rows = post-synaptic neurons of this partition, a pull
+ * layout); the order of a row's entries is the fixed order in which the
+ * step sums that row. */
+typedef struct dtb_desc {
+  int64_t n;                 /* neurons, 1 .. 2^26-1 */
+  int32_t n_regions;         /* populations whose spike counts are reported, >= 1 */
+  int32_t max_delay;         /* D, largest synaptic delay in steps, 1 .. 31 */
+  int32_t n_ptypes;          /* rows of the property table, 1 .. 65536 */
+  int32_t member;            /* ensemble member id (enters the background counter) */
+  int64_t nnz;               /* synapses, 0 .. 2^31-1; must equal row_ptr[n] */
+  const int64_t* row_ptr;    /* [n+1], row_ptr[0] = 0, non-decreasing */
+  const int32_t* col;        /* [nnz] presynaptic neuron, 0 .. n-1 */
+  const float* w;            /* [nnz] weight (jump of the post gates), finite, >= 0 */
+  const uint8_t* delay;      /* [nnz] delay d in steps, 1 .. max_delay; a spike of step e
+                                is summed in step e+d-1 and first moves V in step e+d */
+  const uint8_t* is_inh;     /* [n] 0 = excitatory (drives AMPA, NMDA), 1 = inhibitory
+                                (drives GABAa, GABAb) */
+  const int32_t* region;     /* [n] population id, 0 .. n_regions-1 */
+  const uint16_t* ptype;     /* [n] row of the property table */
+  const dtb_ptype* ptypes;   /* [n_ptypes]: C > 0, gL >= 0, Vreset < Vth, tref >= 0, g >= 0 */
+  const float* V0;           /* [n] initial membrane potential */
+  float E[4];                /* reversal potentials E_u (mV) */
+  float tau_ms[4];           /* gate decay constants tau_u (ms), > 0 */
+  float dt_ms;               /* time step (ms), > 0 */
+  float bg_w;                /* weight of one background event (excitatory), >= 0 */
+  double bg_lambda;          /* mean background Poisson count per neuron-step, 0 .. 400 */
+  uint64_t seed;             /* background seed: Philox4x64-10 key (seed, 0) */
+  int32_t wtype;             /* dtb_wtype: storage precision of w (accumulation is FP32) */
+  int32_t record_steps;      /* steps of raster / counts history kept on device, >= 1 */
+} dtb_desc;
+
+/* ------------------------------------------------------------ library */
+
+int dtb_abi_version(void);
+
+/* Text of the last failure on the calling thread; valid until the next call
+ * on that thread.  Never NULL. */
+const char* dtb_last_error(void);
+
+/* Words in one step's spike bitmap: ceil(n / 32). */
+int64_t dtb_bitmap_words(int64_t n);
+
+/* --------------------------------------------------------- partition */
+
+typedef struct dtb_net dtb_net;
+
+/* Build a partition from the property and connection tables (Sec. V-D) and
+ * initialise it (steps (2)-(3) of Sec. VI-A): V = V0, gates 0, no refractory
+ * neuron, empty delay ring, t = 0.  Copies every input.  hip_stream: the
+ * hipStream_t all work of this handle is enqueued on.
+ * Errors: DTB_ERR_INVALID (validation), DTB_ERR_OOM, DTB_ERR_HIP. */
+dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out);
+
+/* Advance n_steps steps of the computing cycle of Sec. V-B / VI-C
+ * (asynchronous on the handle's stream).  n_steps >= 0. */
+dtb_status dtb_step(dtb_net* net, int32_t n_steps);
+
+/* Teacher forcing (a test hook for the accuracy check of Sec. VII-B): the
+ * next n_steps steps take their spikes from bits (host, [n_steps] bitmaps
+ * of dtb_bitmap_words(n) words) instead of the threshold test.  A forced bit
+ * decides the spike, the reset and the ring entry; an unforced neuron that
+ * is not refractory keeps the integrated V even above threshold.  Queues
+ * after any forcing still pending; at most record_steps pending steps. */
+dtb_status dtb_force_spikes(dtb_net* net, const uint32_t* bits, int32_t n_steps);
+
+/* Spike bitmaps of steps [t0, t1) (the "spikes sequence" of Sec. V-B),
+ * [t1-t0][dtb_bitmap_words(n)] uint32 into dst.  Requires
+ * now - record_steps <= t0 <= t1 <= now (now = steps taken). */
+dtb_status dtb_read_spikes(dtb_net* net, int64_t t0, int64_t t1, uint32_t* dst,
+                           int dst_on_device);
+
+/* Ascending ids of the neurons that spiked in the most recent step (the
+ * compacted spike list that a partition would send, Sec. V-B), at most cap
+ * of them into ids; *count receives the total (may exceed cap). Host dst. */
+dtb_status dtb_read_spike_ids(dtb_net* net, int32_t* ids, int64_t cap, int64_t* count);
+
+/* Current value of one state field for all n neurons (float32 [n]). */
+dtb_status dtb_read_state(dtb_net* net, int32_t field, float* dst, int dst_on_device);
+
+/* Per-population spike counts of steps [t0, t1): int32 [t1-t0][n_regions],
+ * host dst.  Same window rule as dtb_read_spikes. */
+dtb_status dtb_read_region_counts(dtb_net* net, int64_t t0, int64_t t1, int32_t* dst);
+
+/* Population firing rates over [t0, t1) (the population-wise rates that feed
+ * the BOLD model of Sec. V-E): hz[r] = spikes of r / (n_r (t1-t0) dt / 1000);
+ * float32 [n_regions], host dst.  Empty populations report 0. */
+dtb_status dtb_read_region_rates(dtb_net* net, int64_t t0, int64_t t1, float* hz);
+
+/* Per-step delivered recurrent events and background events of steps
+ * [t0, t1): int64 [t1-t0] each (either pointer may be NULL), host dst. */
+dtb_status dtb_read_step_events(dtb_net* net, int64_t t0, int64_t t1, int64_t* ev_rec,
+                                int64_t* ev_bg);
+
+/* Totals since creation: steps taken, spikes, delivered recurrent synaptic
+ * events (a spike crossing one synapse), background events.  Any pointer may
+ * be NULL.  Synchronizes the stream. */
+dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int64_t* ev_rec,
+                             int64_t* ev_bg);
+
+/* Kernel timing (a measurement aid for the statistics interface of
+ * Sec. VI-C): while enabled, every kernel launch of dtb_step is bracketed by
+ * a pair of hipEvents recorded on the handle's stream.  dtb_read_timing
+ * synchronizes, returns the summed durations in ms and the number of timed
+ * launches per kernel, in the order neuron update, compaction, gather,
+ * finalize (double [4], int64 [4]; either may be NULL), and clears them. */
+dtb_status dtb_set_timing(dtb_net* net, int enable);
+dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches);
+
+/* Wait for the handle's stream; report asynchronous failures (DTB_ERR_NUMERIC
+ * when a non-finite V or gate was produced since the last check). */
+dtb_status dtb_sync(dtb_net* net);
+
+/* Release everything the handle owns.  NULL-safe. */
+void dtb_destroy(dtb_net* net);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTB_H */

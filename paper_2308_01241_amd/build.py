@@ -1,0 +1,39 @@
+"""Build libdtb.so (the C-ABI library of include/dtb.h) for gfx950 with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libdtb.so")
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dtb_api.cpp", "dtb_kernels.hip")]
+ARCH = os.environ.get("DTB_OFFLOAD_ARCH", "gfx950")
+
+# -ffp-contract=off: every fused multiply-add in the kernels is explicit.
+# The packed-FP32 feature is switched off for all device code.
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", *FLAGS, "-o", tmp, *SOURCES, "-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building libdtb.so")
+    noise = [l for l in (r.stderr or "").splitlines()
+             if l.strip() and "packed-fp32-ops" not in l and "not a recognized feature" not in l]
+    if verbose and noise:
+        sys.stderr.write("\n".join(noise) + "\n")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

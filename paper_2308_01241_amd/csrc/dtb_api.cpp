@@ -1,0 +1,629 @@
+// dtb_api.cpp - host side of the C ABI declared in include/dtb.h:
+// validation, the device layout of the property and connection tables
+// (Sec. V-D), handle lifetime, step sequencing and reads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "dtb_internal.h"
+
+using namespace dtb;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_err;
+
+dtb_status fail(dtb_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      return fail(DTB_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    }                                                                                   \
+  } while (0)
+
+// parallel loop over [0, n) in contiguous chunks on host threads
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 65536) nt = 1;
+  if (nt == 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned q = 0; q < nt; ++q) {
+    const int64_t a = q * chunk, b = std::min<int64_t>(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([=, &fn] { fn(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// first index in [0, n) for which bad(i) holds, or -1 (parallel scan)
+int64_t find_first(int64_t n, const std::function<bool(int64_t)>& bad) {
+  std::atomic<int64_t> first(INT64_MAX);
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; ++i) {
+      if (i >= first.load(std::memory_order_relaxed)) return;
+      if (bad(i)) {
+        int64_t cur = first.load();
+        while (i < cur && !first.compare_exchange_weak(cur, i)) {
+        }
+        return;
+      }
+    }
+  });
+  const int64_t f = first.load();
+  return f == INT64_MAX ? -1 : f;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Poisson(lambda) inversion thresholds T_k = floor(F(k) 2^32) while below
+// 2^32 - 1, with F accumulated from p_0 = exp(-lambda), p_k = p_{k-1} lambda / k.
+int poisson_thresholds(double lambda, uint32_t* T, int cap) {
+  const double two32 = 4294967296.0;
+  double pk = std::exp(-lambda), F = pk;
+  for (int k = 0; k < cap; ++k) {
+    const double x = std::floor(F * two32);
+    if (x >= 4294967295.0) return k;
+    T[k] = uint32_t(x);
+    pk = pk * lambda / double(k + 1);
+    F = F + pk;
+  }
+  return -1;
+}
+
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+bool finite_f(float x) { return std::isfinite(x); }
+}  // namespace
+
+struct dtb_net {
+  DeviceNet d;
+  hipStream_t stream = nullptr;
+  int64_t t = 0;                 // steps taken (host mirror of the device step)
+  float dt_ms = 1.f;
+  bool failed = false;           // sticky HIP failure
+  int64_t force_head = 0;        // step index of the first pending forced bitmap
+  int64_t force_pending = 0;     // forced steps not yet consumed
+  std::vector<int64_t> region_n; // neurons per population
+  std::vector<void*> allocs;
+  // kernel timing: event pairs per kernel kind, reused after each read
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[4];
+  size_t ev_used[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+dtb_status check_net(dtb_net* net) {
+  if (!net) return fail(DTB_ERR_INVALID, "null handle");
+  if (net->failed) return fail(DTB_ERR_STATE, "handle is in a failed state after an earlier HIP error");
+  return DTB_OK;
+}
+
+dtb_status hip_fail(dtb_net* net, hipError_t e, const char* what) {
+  net->failed = true;
+  return fail(DTB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+dtb_status dalloc(dtb_net* net, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(1, count * sizeof(T));
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? DTB_ERR_OOM : DTB_ERR_HIP,
+                "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
+  }
+  net->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return DTB_OK;
+}
+
+dtb_status validate(const dtb_desc* s) {
+  if (!s) return fail(DTB_ERR_INVALID, "desc is NULL");
+  if (s->n < 1 || s->n > kMaxNeurons)
+    return fail(DTB_ERR_INVALID, "n must be in [1, " + std::to_string(kMaxNeurons) + "]");
+  if (s->n_regions < 1) return fail(DTB_ERR_INVALID, "n_regions must be >= 1");
+  if (s->max_delay < 1 || s->max_delay > kMaxDelay)
+    return fail(DTB_ERR_INVALID, "max_delay must be in [1, 31]");
+  if (s->n_ptypes < 1 || s->n_ptypes > 65536) return fail(DTB_ERR_INVALID, "n_ptypes must be in [1, 65536]");
+  if (s->nnz < 0 || s->nnz > INT32_MAX) return fail(DTB_ERR_INVALID, "nnz must be in [0, 2^31-1]");
+  if (!s->row_ptr || !s->is_inh || !s->region || !s->ptype || !s->ptypes || !s->V0)
+    return fail(DTB_ERR_INVALID, "a required array pointer is NULL");
+  if (s->nnz > 0 && (!s->col || !s->w || !s->delay))
+    return fail(DTB_ERR_INVALID, "col/w/delay must be non-NULL when nnz > 0");
+  if (s->wtype != DTB_W_F32 && s->wtype != DTB_W_BF16) return fail(DTB_ERR_INVALID, "unknown wtype");
+  if (s->record_steps < 1) return fail(DTB_ERR_INVALID, "record_steps must be >= 1");
+  if (!(s->dt_ms > 0.f) || !finite_f(s->dt_ms)) return fail(DTB_ERR_INVALID, "dt_ms must be finite and > 0");
+  for (int u = 0; u < 4; ++u) {
+    if (!(s->tau_ms[u] > 0.f) || !finite_f(s->tau_ms[u]))
+      return fail(DTB_ERR_INVALID, "tau_ms[" + std::to_string(u) + "] must be finite and > 0");
+    if (!finite_f(s->E[u])) return fail(DTB_ERR_INVALID, "E[" + std::to_string(u) + "] must be finite");
+  }
+  if (!(s->bg_w >= 0.f) || !finite_f(s->bg_w)) return fail(DTB_ERR_INVALID, "bg_w must be finite and >= 0");
+  if (!(s->bg_lambda >= 0.0) || !(s->bg_lambda <= 400.0))
+    return fail(DTB_ERR_INVALID, "bg_lambda must be in [0, 400]");
+  if (s->row_ptr[0] != 0) return fail(DTB_ERR_INVALID, "row_ptr[0] must be 0");
+  if (s->row_ptr[s->n] != s->nnz) return fail(DTB_ERR_INVALID, "row_ptr[n] must equal nnz");
+  const int64_t n = s->n;
+  int64_t bad = find_first(n, [&](int64_t i) { return s->row_ptr[i + 1] < s->row_ptr[i]; });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "row_ptr decreases at row " + std::to_string(bad));
+  bad = find_first(s->nnz, [&](int64_t k) { return s->col[k] < 0 || int64_t(s->col[k]) >= n; });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "col out of range at synapse " + std::to_string(bad));
+  bad = find_first(s->nnz, [&](int64_t k) { return s->delay[k] < 1 || s->delay[k] > s->max_delay; });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "delay out of [1, max_delay] at synapse " + std::to_string(bad));
+  bad = find_first(s->nnz, [&](int64_t k) { return !(s->w[k] >= 0.f) || !finite_f(s->w[k]); });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "weight not finite and >= 0 at synapse " + std::to_string(bad));
+  bad = find_first(n, [&](int64_t i) {
+    return s->is_inh[i] > 1 || s->region[i] < 0 || s->region[i] >= s->n_regions ||
+           int(s->ptype[i]) >= s->n_ptypes || !finite_f(s->V0[i]);
+  });
+  if (bad >= 0)
+    return fail(DTB_ERR_INVALID, "neuron " + std::to_string(bad) + ": is_inh, region, ptype or V0 invalid");
+  for (int p = 0; p < s->n_ptypes; ++p) {
+    const dtb_ptype& q = s->ptypes[p];
+    const float vals[] = {q.C, q.gL, q.EL, q.Vth, q.Vreset, q.tref_ms, q.Iext, q.g[0], q.g[1], q.g[2], q.g[3]};
+    for (float v : vals)
+      if (!finite_f(v)) return fail(DTB_ERR_INVALID, "ptype " + std::to_string(p) + " has a non-finite field");
+    if (!(q.C > 0.f) || q.gL < 0.f || !(q.Vreset < q.Vth) || q.tref_ms < 0.f || q.g[0] < 0.f ||
+        q.g[1] < 0.f || q.g[2] < 0.f || q.g[3] < 0.f)
+      return fail(DTB_ERR_INVALID, "ptype " + std::to_string(p) +
+                                       ": need C > 0, gL >= 0, Vreset < Vth, tref >= 0, g >= 0");
+    if (std::lround(double(q.tref_ms) / double(s->dt_ms)) > 255)
+      return fail(DTB_ERR_INVALID, "ptype " + std::to_string(p) + ": tref / dt must be <= 255 steps");
+  }
+  return DTB_OK;
+}
+
+dtb_status upload(dtb_net* net, void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, net->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy H2D");
+  return DTB_OK;
+}
+
+// CSR (row order = summation order) -> SELL-64: slice s holds rows
+// [64 s, 64 s + 64); entry k of lane l sits at slice_off[s] + 64 k + l.
+dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
+  DeviceNet& d = net->d;
+  const int64_t ns = d.n_slices;
+  std::vector<int32_t> slen(ns), rlen(d.n_pad, 0);
+  std::vector<int64_t> soff(ns);
+  for (int64_t i = 0; i < s->n; ++i) rlen[i] = int32_t(s->row_ptr[i + 1] - s->row_ptr[i]);
+  int64_t off = 0;
+  for (int64_t q = 0; q < ns; ++q) {
+    int32_t L = 0;
+    for (int l = 0; l < kSlice; ++l) L = std::max(L, rlen[q * kSlice + l]);
+    slen[q] = L;
+    soff[q] = off;
+    off += int64_t(L) * kSlice;
+  }
+  d.total_slots = off;
+  dtb_status st;
+  if ((st = dalloc(net, &d.slice_off, ns)) || (st = dalloc(net, &d.slice_len, ns)) ||
+      (st = dalloc(net, &d.row_len, d.n_pad)) || (st = dalloc(net, &d.syn, std::max<int64_t>(1, off))))
+    return st;
+  const size_t wsz = d.wtype == DTB_W_BF16 ? 2 : 4;
+  {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(1, size_t(off) * wsz));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DTB_ERR_OOM, "hipMalloc of weights failed");
+    }
+    net->allocs.push_back(q);
+    d.wts = q;
+  }
+  if ((st = upload(net, d.slice_off, soff.data(), ns * sizeof(int64_t))) ||
+      (st = upload(net, d.slice_len, slen.data(), ns * sizeof(int32_t))) ||
+      (st = upload(net, d.row_len, rlen.data(), d.n_pad * sizeof(int32_t))))
+    return st;
+  // pack in chunks of whole slices so host staging stays bounded
+  const int64_t chunk_target = int64_t(1) << 26;  // entries per chunk (256 MB of words)
+  std::vector<uint32_t> hw;
+  std::vector<uint8_t> hwt;
+  int64_t q0 = 0;
+  while (q0 < ns) {
+    int64_t q1 = q0, cnt = 0;
+    while (q1 < ns && (cnt == 0 || cnt + int64_t(slen[q1]) * kSlice <= chunk_target)) {
+      cnt += int64_t(slen[q1]) * kSlice;
+      ++q1;
+    }
+    if (cnt > 0) {
+      hw.assign(size_t(cnt), 0u);
+      hwt.assign(size_t(cnt) * wsz, 0);
+      const int64_t base = soff[q0];
+      parallel_for(q1 - q0, [&](int64_t a, int64_t b) {
+        for (int64_t q = q0 + a; q < q0 + b; ++q) {
+          for (int l = 0; l < kSlice; ++l) {
+            const int64_t i = q * kSlice + l;
+            if (i >= s->n) break;
+            const int64_t r0 = s->row_ptr[i];
+            for (int32_t k = 0; k < rlen[i]; ++k) {
+              const int32_t m = s->col[r0 + k];
+              const uint32_t word = uint32_t(m) | (uint32_t(s->delay[r0 + k] - 1) << kColBits) |
+                                    (uint32_t(s->is_inh[m] ? 1 : 0) << 31);
+              const int64_t idx = soff[q] - base + int64_t(k) * kSlice + l;
+              hw[idx] = word;
+              if (wsz == 4) std::memcpy(&hwt[idx * 4], &s->w[r0 + k], 4);
+              else {
+                const uint16_t b16 = f32_to_bf16_rne(s->w[r0 + k]);
+                std::memcpy(&hwt[idx * 2], &b16, 2);
+              }
+            }
+          }
+        }
+      });
+      if ((st = upload(net, d.syn + base, hw.data(), size_t(cnt) * 4)) ||
+          (st = upload(net, static_cast<uint8_t*>(d.wts) + base * wsz, hwt.data(), size_t(cnt) * wsz)))
+        return st;
+    }
+    q0 = q1;
+  }
+  return DTB_OK;
+}
+
+// launch `fn`, bracketed by a pair of events when timing is on
+template <typename F>
+hipError_t timed(dtb_net* net, int kind, F fn) {
+  if (!net->timing) return fn();
+  auto& pool = net->ev_pool[kind];
+  if (net->ev_used[kind] == pool.size()) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    pool.emplace_back(a, b);
+  }
+  auto& pr = pool[net->ev_used[kind]++];
+  hipError_t e = hipEventRecord(pr.first, net->stream);
+  if (e == hipSuccess) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(pr.second, net->stream);
+  return e;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+int dtb_abi_version(void) { return DTB_ABI_VERSION; }
+
+const char* dtb_last_error(void) { return g_err.c_str(); }
+
+int64_t dtb_bitmap_words(int64_t n) { return n <= 0 ? 0 : (n + 31) / 32; }
+
+void dtb_destroy(dtb_net* net) {
+  if (!net) return;
+  (void)hipStreamSynchronize(net->stream);
+  for (auto& pool : net->ev_pool)
+    for (auto& pr : pool) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (void* p : net->allocs) (void)hipFree(p);
+  delete net;
+}
+
+dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
+  if (!out) return fail(DTB_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  dtb_status st = validate(desc);
+  if (st) return st;
+  dtb_net* net = new (std::nothrow) dtb_net();
+  if (!net) return fail(DTB_ERR_OOM, "host allocation failed");
+  net->stream = static_cast<hipStream_t>(hip_stream);
+  net->dt_ms = desc->dt_ms;
+  DeviceNet& d = net->d;
+  d.n = desc->n;
+  d.n_pad = round_up(desc->n, kNeuronPad);
+  d.words = dtb_bitmap_words(desc->n);
+  d.words_pad = d.n_pad / 32;
+  d.n_slices = d.n_pad / kSlice;
+  d.n_regions = desc->n_regions;
+  d.max_delay = desc->max_delay;
+  d.n_ptypes = desc->n_ptypes;
+  d.member = desc->member;
+  d.wtype = desc->wtype;
+  d.rec = desc->record_steps;
+  d.bg_w = desc->bg_w;
+  d.seed = desc->seed;
+  d.compact_blocks = (d.words_pad + 2 * kCompactBlock - 1) / (2 * kCompactBlock);
+  for (int u = 0; u < 4; ++u) {
+    d.a[u] = float(std::exp(-double(desc->dt_ms) / double(desc->tau_ms[u])));
+    d.E[u] = desc->E[u];
+  }
+  std::vector<uint32_t> T(kMaxPoisson);
+  d.poisson_K = poisson_thresholds(desc->bg_lambda, T.data(), kMaxPoisson);
+  if (d.poisson_K < 0) {
+    delete net;
+    return fail(DTB_ERR_INVALID, "bg_lambda needs more than 512 inversion-table entries");
+  }
+  const int64_t slots = int64_t(d.rec) + 1;
+  if ((st = dalloc(net, &d.V, d.n_pad)) || (st = dalloc(net, &d.j, 4 * d.n_pad)) ||
+      (st = dalloc(net, &d.ref, d.n_pad)) || (st = dalloc(net, &d.ptype, d.n_pad)) ||
+      (st = dalloc(net, &d.region, d.n_pad)) || (st = dalloc(net, &d.ring, d.n_pad)) ||
+      (st = dalloc(net, &d.ptab, d.n_ptypes)) || (st = dalloc(net, &d.gain, 4 * d.n_regions)) ||
+      (st = dalloc(net, &d.poisson, std::max(1, d.poisson_K))) ||
+      (st = dalloc(net, &d.raster, slots * d.words_pad)) ||
+      (st = dalloc(net, &d.counts, slots * d.n_regions)) || (st = dalloc(net, &d.ev, slots * kStripes * 2)) ||
+      (st = dalloc(net, &d.totals, 4)) || (st = dalloc(net, &d.ids, d.n_pad)) ||
+      (st = dalloc(net, &d.id_count, 1)) || (st = dalloc(net, &d.cstatus, d.compact_blocks)) ||
+      (st = dalloc(net, &d.cticket, 1)) || (st = dalloc(net, &d.force, slots * d.words_pad)) ||
+      (st = dalloc(net, &d.bad, 1))) {
+    dtb_destroy(net);
+    return st;
+  }
+  auto zero = [&](void* p, size_t bytes) { return hipMemsetAsync(p, 0, bytes, net->stream); };
+  hipError_t e = hipSuccess;
+  for (auto pr : std::vector<std::pair<void*, size_t>>{
+           {d.j, 4 * d.n_pad * sizeof(float)}, {d.ref, size_t(d.n_pad)}, {d.ring, d.n_pad * 4},
+           {d.raster, slots * d.words_pad * 4}, {d.counts, slots * d.n_regions * 4},
+           {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32}, {d.id_count, 4},
+           {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.ptype, d.n_pad * 2},
+           {d.region, d.n_pad * 4}, {d.V, d.n_pad * 4}}) {
+    if (e == hipSuccess) e = zero(pr.first, pr.second);
+  }
+  if (e != hipSuccess) {
+    st = fail(DTB_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    dtb_destroy(net);
+    return st;
+  }
+  // property table: derived per-type constants
+  std::vector<PType> pt(d.n_ptypes);
+  for (int p = 0; p < d.n_ptypes; ++p) {
+    const dtb_ptype& q = desc->ptypes[p];
+    pt[p].dtC = float(double(desc->dt_ms) / double(q.C));
+    pt[p].gL = q.gL;
+    pt[p].EL = q.EL;
+    pt[p].Vth = q.Vth;
+    pt[p].Vreset = q.Vreset;
+    pt[p].Iext = q.Iext;
+    for (int u = 0; u < 4; ++u) pt[p].g[u] = q.g[u];
+    pt[p].nref = int32_t(std::lround(double(q.tref_ms) / double(desc->dt_ms)));
+    pt[p].pad = 0;
+  }
+  std::vector<float> gain(4 * d.n_regions, 1.0f);
+  net->region_n.assign(d.n_regions, 0);
+  for (int64_t i = 0; i < d.n; ++i) net->region_n[desc->region[i]]++;
+  if ((st = upload(net, d.ptab, pt.data(), pt.size() * sizeof(PType))) ||
+      (st = upload(net, d.gain, gain.data(), gain.size() * 4)) ||
+      (st = upload(net, d.poisson, T.data(), std::max(1, d.poisson_K) * 4)) ||
+      (st = upload(net, d.V, desc->V0, d.n * 4)) || (st = upload(net, d.ptype, desc->ptype, d.n * 2)) ||
+      (st = upload(net, d.region, desc->region, d.n * 4)) || (st = build_connections(net, desc))) {
+    dtb_destroy(net);
+    return st;
+  }
+  *out = net;
+  return DTB_OK;
+}
+
+dtb_status dtb_set_timing(dtb_net* net, int enable) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  net->timing = enable != 0;
+  return DTB_OK;
+}
+
+dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  hipError_t e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipStreamSynchronize");
+  for (int k = 0; k < 4; ++k) {
+    double sum = 0.0;
+    for (size_t q = 0; q < net->ev_used[k]; ++q) {
+      float x = 0.f;
+      e = hipEventElapsedTime(&x, net->ev_pool[k][q].first, net->ev_pool[k][q].second);
+      if (e != hipSuccess) return hip_fail(net, e, "hipEventElapsedTime");
+      sum += x;
+    }
+    if (ms) ms[k] = sum;
+    if (launches) launches[k] = int64_t(net->ev_used[k]);
+    net->ev_used[k] = 0;
+  }
+  return DTB_OK;
+}
+
+dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (n_steps < 0) return fail(DTB_ERR_INVALID, "n_steps must be >= 0");
+  DeviceNet& d = net->d;
+  for (int32_t q = 0; q < n_steps; ++q) {
+    const int64_t t = net->t;
+    const uint32_t* forced = nullptr;
+    if (net->force_pending > 0) {
+      forced = d.force + (net->force_head % (d.rec + 1)) * d.words_pad;
+      net->force_head++;
+      net->force_pending--;
+    }
+    hipError_t e = timed(net, 0, [&] { return launch_neuron_update(d, t, forced, net->stream); });
+    if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, t, net->stream); });
+    if (e == hipSuccess) e = timed(net, 2, [&] { return launch_gather(d, t, net->stream); });
+    if (e == hipSuccess) e = timed(net, 3, [&] { return launch_finalize(d, t, net->stream); });
+    if (e != hipSuccess) return hip_fail(net, e, "kernel launch");
+    net->t = t + 1;
+  }
+  return DTB_OK;
+}
+
+dtb_status dtb_force_spikes(dtb_net* net, const uint32_t* bits, int32_t n_steps) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (n_steps < 0 || (n_steps > 0 && !bits)) return fail(DTB_ERR_INVALID, "bad bits / n_steps");
+  DeviceNet& d = net->d;
+  if (net->force_pending + n_steps > d.rec)
+    return fail(DTB_ERR_INVALID, "more forced steps pending than record_steps");
+  if (net->force_pending == 0) net->force_head = 0;
+  std::vector<uint32_t> row(d.words_pad, 0u);
+  for (int32_t q = 0; q < n_steps; ++q) {
+    std::memcpy(row.data(), bits + size_t(q) * d.words, d.words * 4);
+    const int64_t slot = (net->force_head + net->force_pending) % (d.rec + 1);
+    hipError_t e = hipMemcpyAsync(d.force + slot * d.words_pad, row.data(), d.words_pad * 4,
+                                  hipMemcpyHostToDevice, net->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy forced spikes");
+    net->force_pending++;
+  }
+  return DTB_OK;
+}
+
+static dtb_status window(dtb_net* net, int64_t t0, int64_t t1) {
+  if (t0 < 0 || t1 < t0 || t1 > net->t || t0 < net->t - net->d.rec)
+    return fail(DTB_ERR_INVALID, "window [" + std::to_string(t0) + ", " + std::to_string(t1) +
+                                     ") outside the recorded steps");
+  return DTB_OK;
+}
+
+static dtb_status copy_out(dtb_net* net, void* dst, const void* src, size_t bytes, int on_device) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                net->stream);
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy read");
+  return DTB_OK;
+}
+
+dtb_status dtb_read_spikes(dtb_net* net, int64_t t0, int64_t t1, uint32_t* dst, int dst_on_device) {
+  dtb_status st = check_net(net);
+  if (st || (st = window(net, t0, t1))) return st;
+  if (!dst && t1 > t0) return fail(DTB_ERR_INVALID, "dst is NULL");
+  const DeviceNet& d = net->d;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t slot = t % (d.rec + 1);
+    if ((st = copy_out(net, dst + (t - t0) * d.words, d.raster + slot * d.words_pad, d.words * 4, dst_on_device)))
+      return st;
+  }
+  return DTB_OK;
+}
+
+dtb_status dtb_read_spike_ids(dtb_net* net, int32_t* ids, int64_t cap, int64_t* count) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!count || cap < 0 || (cap > 0 && !ids)) return fail(DTB_ERR_INVALID, "bad ids / cap / count");
+  int32_t c = 0;
+  if (net->t > 0 && (st = copy_out(net, &c, net->d.id_count, 4, 0))) return st;
+  *count = c;
+  const int64_t m = std::min<int64_t>(c, cap);
+  if (m > 0 && (st = copy_out(net, ids, net->d.ids, size_t(m) * 4, 0))) return st;
+  return DTB_OK;
+}
+
+dtb_status dtb_read_state(dtb_net* net, int32_t field, float* dst, int dst_on_device) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!dst) return fail(DTB_ERR_INVALID, "dst is NULL");
+  const DeviceNet& d = net->d;
+  if (field == DTB_V) return copy_out(net, dst, d.V, d.n * 4, dst_on_device);
+  if (field >= DTB_J_AMPA && field <= DTB_J_GABAB)
+    return copy_out(net, dst, d.j + (field - 1) * d.n_pad, d.n * 4, dst_on_device);
+  if (field == DTB_REF) {
+    std::vector<uint8_t> r(d.n);
+    if ((st = copy_out(net, r.data(), d.ref, d.n, 0))) return st;
+    std::vector<float> f(r.begin(), r.end());
+    if (dst_on_device) {
+      hipError_t e = hipMemcpy(dst, f.data(), d.n * 4, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy");
+    } else {
+      std::memcpy(dst, f.data(), d.n * 4);
+    }
+    return DTB_OK;
+  }
+  return fail(DTB_ERR_INVALID, "unknown field");
+}
+
+dtb_status dtb_read_region_counts(dtb_net* net, int64_t t0, int64_t t1, int32_t* dst) {
+  dtb_status st = check_net(net);
+  if (st || (st = window(net, t0, t1))) return st;
+  if (!dst && t1 > t0) return fail(DTB_ERR_INVALID, "dst is NULL");
+  const DeviceNet& d = net->d;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t slot = t % (d.rec + 1);
+    if ((st = copy_out(net, dst + (t - t0) * d.n_regions, d.counts + slot * d.n_regions, d.n_regions * 4, 0)))
+      return st;
+  }
+  return DTB_OK;
+}
+
+dtb_status dtb_read_region_rates(dtb_net* net, int64_t t0, int64_t t1, float* hz) {
+  dtb_status st = check_net(net);
+  if (st || (st = window(net, t0, t1))) return st;
+  if (!hz) return fail(DTB_ERR_INVALID, "hz is NULL");
+  const int R = net->d.n_regions;
+  std::vector<int32_t> c(size_t(std::max<int64_t>(1, t1 - t0)) * R, 0);
+  if (t1 > t0 && (st = dtb_read_region_counts(net, t0, t1, c.data()))) return st;
+  for (int r = 0; r < R; ++r) {
+    int64_t s = 0;
+    for (int64_t q = 0; q < t1 - t0; ++q) s += c[q * R + r];
+    const double denom = double(net->region_n[r]) * double(t1 - t0) * double(net->dt_ms) * 1e-3;
+    hz[r] = denom > 0 ? float(double(s) / denom) : 0.f;
+  }
+  return DTB_OK;
+}
+
+dtb_status dtb_read_step_events(dtb_net* net, int64_t t0, int64_t t1, int64_t* ev_rec, int64_t* ev_bg) {
+  dtb_status st = check_net(net);
+  if (st || (st = window(net, t0, t1))) return st;
+  const DeviceNet& d = net->d;
+  int64_t v[2];
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t slot = t % (d.rec + 1);
+    if ((st = copy_out(net, v, d.ev + slot * kStripes * 2, 16, 0))) return st;
+    if (ev_rec) ev_rec[t - t0] = v[0];
+    if (ev_bg) ev_bg[t - t0] = v[1];
+  }
+  return DTB_OK;
+}
+
+dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int64_t* ev_rec, int64_t* ev_bg) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  int64_t v[4];
+  if ((st = copy_out(net, v, net->d.totals, 32, 0))) return st;
+  if (steps) *steps = v[3];
+  if (spikes) *spikes = v[0];
+  if (ev_rec) *ev_rec = v[1];
+  if (ev_bg) *ev_bg = v[2];
+  return DTB_OK;
+}
+
+dtb_status dtb_sync(dtb_net* net) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  hipError_t e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipStreamSynchronize");
+  int32_t bad = 0;
+  if ((st = copy_out(net, &bad, net->d.bad, 4, 0))) return st;
+  if (bad) {
+    e = hipMemsetAsync(net->d.bad, 0, 4, net->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) return hip_fail(net, e, "hipMemset");
+    return fail(DTB_ERR_NUMERIC, "non-finite membrane potential or gate produced");
+  }
+  return DTB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+"""Python handle over one partition of the C ABI (argument marshalling only;
+every step of the simulation runs in the library's HIP kernels)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import FIELDS, W_BF16, W_F32, Desc, Ptype, check, load
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream_handle(stream):
+    """hipStream_t of a torch stream (or an int), None -> legacy default."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Net:
+    """One partition on the GPU.
+
+    ``network`` is a ``netgen.Network``-like object (attributes n, n_regions,
+    max_delay, row_ptr, col, w, delay, is_inh, region, ptype, ptypes, V0, E,
+    tau_ms, dt_ms, bg_lambda, bg_w, seed, member).
+    """
+
+    def __init__(self, network, wtype: str = "f32", record_steps: int = 1024, stream=None):
+        lib = load()
+        self._lib = lib
+        nw = network
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return _ptr(a)
+
+        d = Desc()
+        d.n = int(nw.n)
+        d.n_regions = int(nw.n_regions)
+        d.max_delay = int(nw.max_delay)
+        pt = np.ascontiguousarray(nw.ptypes, dtype=np.float32).reshape(-1, 11)
+        d.n_ptypes = int(pt.shape[0])
+        d.member = int(getattr(nw, "member", 0))
+        d.nnz = int(nw.row_ptr[-1])
+        d.row_ptr = arr(nw.row_ptr, np.int64)
+        d.col = arr(nw.col, np.int32)
+        d.w = arr(nw.w, np.float32)
+        d.delay = arr(nw.delay, np.uint8)
+        d.is_inh = arr(nw.is_inh, np.uint8)
+        d.region = arr(nw.region, np.int32)
+        d.ptype = arr(nw.ptype, np.uint16)
+        ptypes = (Ptype * d.n_ptypes)()
+        for p in range(d.n_ptypes):
+            r = pt[p]
+            ptypes[p] = Ptype(*[float(x) for x in r[:7]], (ctypes.c_float * 4)(*[float(x) for x in r[7:11]]))
+        d.ptypes = ctypes.cast(ptypes, ctypes.c_void_p)
+        d.V0 = arr(nw.V0, np.float32)
+        for u in range(4):
+            d.E[u] = float(nw.E[u])
+            d.tau_ms[u] = float(nw.tau_ms[u])
+        d.dt_ms = float(nw.dt_ms)
+        d.bg_w = float(nw.bg_w)
+        d.bg_lambda = float(nw.bg_lambda)
+        d.seed = int(nw.seed)
+        d.wtype = {"f32": W_F32, "bf16": W_BF16}[wtype]
+        d.record_steps = int(record_steps)
+        h = ctypes.c_void_p()
+        check(lib.dtb_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.n = d.n
+        self.n_regions = d.n_regions
+        self.words = int(lib.dtb_bitmap_words(d.n))
+        self.record_steps = int(record_steps)
+        self.t = 0
+        del keep, ptypes
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.dtb_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n_steps: int = 1) -> None:
+        check(self._lib.dtb_step(self._h, int(n_steps)))
+        self.t += int(n_steps)
+
+    def force(self, raster: np.ndarray) -> None:
+        """Queue teacher-forced spikes: raster [n_steps, n] of 0/1."""
+        r = np.ascontiguousarray(raster, dtype=np.uint8).reshape(-1, self.n)
+        bits = pack_bits(r, self.words)
+        check(self._lib.dtb_force_spikes(self._h, _ptr(bits), int(r.shape[0])))
+
+    def set_timing(self, enable: bool) -> None:
+        check(self._lib.dtb_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self) -> dict:
+        """Summed kernel durations (ms) and launch counts since the last read."""
+        ms = np.zeros(4, dtype=np.float64)
+        n = np.zeros(4, dtype=np.int64)
+        check(self._lib.dtb_read_timing(self._h, _ptr(ms), _ptr(n)))
+        names = ("neuron_update", "compact", "gather", "finalize")
+        return {k: {"ms": float(ms[q]), "launches": int(n[q])} for q, k in enumerate(names)}
+
+    def sync(self) -> None:
+        check(self._lib.dtb_sync(self._h))
+
+    # ---------------------------------------------------------------- reads
+    def spikes_bits(self, t0: int, t1: int) -> np.ndarray:
+        out = np.zeros((max(0, t1 - t0), self.words), dtype=np.uint32)
+        check(self._lib.dtb_read_spikes(self._h, int(t0), int(t1), _ptr(out), 0))
+        return out
+
+    def raster(self, t0: int, t1: int) -> np.ndarray:
+        """uint8 [t1-t0, n] spike raster of the recorded steps."""
+        return unpack_bits(self.spikes_bits(t0, t1), self.n)
+
+    def spike_ids(self, cap=None) -> np.ndarray:
+        cap = self.n if cap is None else int(cap)
+        ids = np.zeros(max(cap, 1), dtype=np.int32)
+        cnt = ctypes.c_int64(0)
+        check(self._lib.dtb_read_spike_ids(self._h, _ptr(ids), cap, ctypes.byref(cnt)))
+        return ids[:min(cap, cnt.value)].copy()
+
+    def state(self, field: str) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.float32)
+        check(self._lib.dtb_read_state(self._h, FIELDS[field], _ptr(out), 0))
+        return out
+
+    def state_into(self, field: str, tensor) -> None:
+        """Read a state field into a device tensor (float32, >= n elements)."""
+        check(self._lib.dtb_read_state(self._h, FIELDS[field], ctypes.c_void_p(tensor.data_ptr()), 1))
+
+    def region_counts(self, t0: int, t1: int) -> np.ndarray:
+        out = np.zeros((max(0, t1 - t0), self.n_regions), dtype=np.int32)
+        check(self._lib.dtb_read_region_counts(self._h, int(t0), int(t1), _ptr(out)))
+        return out
+
+    def region_rates(self, t0: int, t1: int) -> np.ndarray:
+        out = np.zeros(self.n_regions, dtype=np.float32)
+        check(self._lib.dtb_read_region_rates(self._h, int(t0), int(t1), _ptr(out)))
+        return out
+
+    def step_events(self, t0: int, t1: int):
+        er = np.zeros(max(0, t1 - t0), dtype=np.int64)
+        eb = np.zeros(max(0, t1 - t0), dtype=np.int64)
+        check(self._lib.dtb_read_step_events(self._h, int(t0), int(t1), _ptr(er), _ptr(eb)))
+        return er, eb
+
+    def counters(self) -> dict:
+        v = [ctypes.c_int64(0) for _ in range(4)]
+        check(self._lib.dtb_read_counters(self._h, *[ctypes.byref(x) for x in v]))
+        return {"steps": v[0].value, "spikes": v[1].value, "ev_rec": v[2].value, "ev_bg": v[3].value}
+
+
+def pack_bits(raster: np.ndarray, words: int) -> np.ndarray:
+    """[T, n] 0/1 -> [T, words] uint32 with neuron i at bit (i & 31) of word i >> 5."""
+    T, n = raster.shape
+    padded = np.zeros((T, words * 32), dtype=np.uint8)
+    padded[:, :n] = raster
+    b = np.packbits(padded, axis=-1, bitorder="little")          # [T, words * 4] bytes
+    return np.ascontiguousarray(b).view("<u4").reshape(T, words)
+
+
+def unpack_bits(bits: np.ndarray, n: int) -> np.ndarray:
+    T, words = bits.shape
+    by = np.ascontiguousarray(bits, dtype="<u4").view(np.uint8).reshape(T, words * 4)
+    u = np.unpackbits(by, axis=-1, bitorder="little")
+    return np.ascontiguousarray(u[:, :n])
