@@ -204,31 +204,101 @@ dtb_status upload(dtb_net* net, void* dst, const void* src, size_t bytes) {
   return DTB_OK;
 }
 
-// CSR (row order = summation order) -> SELL-64: slice s holds rows
-// [64 s, 64 s + 64); entry k of lane l sits at slice_off[s] + 64 k + l.
+// Run fn(b) for b in [0, n) on host threads with dynamic scheduling.
+void parallel_items(int64_t n, const std::function<void(int64_t)>& fn) {
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<int64_t> next(0);
+  auto work = [&] {
+    for (int64_t b = next++; b < n; b = next++) fn(b);
+  };
+  if (nt == 1 || n < 2) {
+    work();
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned q = 0; q < nt; ++q) th.emplace_back(work);
+  for (auto& x : th) x.join();
+}
+
+// The connection table (Sec. V-D) in the gather's layout: rows cut into
+// bundles, each bundle's synapses once in CSR order (weights, sign bit =
+// inhibitory source) and once sorted by (delay, source) as 64-entry tiles of
+// (source delta, CSR position) lookups (see dtb_internal.h).
 dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   DeviceNet& d = net->d;
-  const int64_t ns = d.n_slices;
-  std::vector<int32_t> slen(ns), rlen(d.n_pad, 0);
-  std::vector<int64_t> soff(ns);
-  for (int64_t i = 0; i < s->n; ++i) rlen[i] = int32_t(s->row_ptr[i + 1] - s->row_ptr[i]);
-  int64_t off = 0;
-  for (int64_t q = 0; q < ns; ++q) {
-    int32_t L = 0;
-    for (int l = 0; l < kSlice; ++l) L = std::max(L, rlen[q * kSlice + l]);
-    slen[q] = L;
-    soff[q] = off;
-    off += int64_t(L) * kSlice;
+  const int64_t n = s->n;
+  // 1. bundles of consecutive rows
+  const int64_t max_rows = std::min<int64_t>(65536, std::max<int64_t>(64, (n + 511) / 512));
+  std::vector<Bundle> bl;
+  for (int64_t r = 0; r < n;) {
+    Bundle b{};
+    b.row0 = r;
+    b.syn0 = s->row_ptr[r];
+    while (r < n && r - b.row0 < max_rows && s->row_ptr[r + 1] - b.syn0 <= kBundleMaxSyn) ++r;
+    if (r == b.row0)
+      return fail(DTB_ERR_UNSUPPORTED, "row " + std::to_string(r) + " has more than " +
+                                           std::to_string(kBundleMaxSyn) + " synapses");
+    b.row1 = r;
+    b.nsyn = int32_t(s->row_ptr[r] - b.syn0);
+    bl.push_back(b);
   }
-  d.total_slots = off;
+  const int64_t nb = int64_t(bl.size());
+  // 2. per bundle: sort by (delay, source, position) and cut into tiles
+  std::vector<std::vector<uint32_t>> btiles(nb), bheads(nb);
+  parallel_items(nb, [&](int64_t q) {
+    const Bundle& b = bl[q];
+    std::vector<uint64_t> key(size_t(b.nsyn));
+    for (int32_t p = 0; p < b.nsyn; ++p) {
+      const int64_t k = b.syn0 + p;
+      key[p] = (uint64_t(s->delay[k] - 1) << 46) | (uint64_t(uint32_t(s->col[k])) << 20) | uint64_t(p);
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<uint32_t>& T = btiles[q];
+    std::vector<uint32_t>& H = bheads[q];
+    T.reserve(size_t(b.nsyn) + size_t(b.nsyn) / 16 + kTile);
+    int c = 0;
+    uint32_t prev = 0, d1 = 0;
+    for (uint64_t kk : key) {
+      const uint32_t kd = uint32_t(kk >> 46), src = uint32_t((kk >> 20) & 0x3FFFFFFu);
+      const uint32_t pos = uint32_t(kk & kPosMask);
+      if (c == 0 || c == kTile || kd != d1 || src - prev > kMaxDelta) {
+        while (c > 0 && c < kTile) {
+          T.push_back(kInvalidPos);
+          ++c;
+        }
+        H.push_back(src | (kd << 26));
+        prev = src;
+        d1 = kd;
+        c = 0;
+      }
+      T.push_back(((src - prev) << kPosBits) | pos);
+      prev = src;
+      ++c;
+    }
+    while (c > 0 && c < kTile) {
+      T.push_back(kInvalidPos);
+      ++c;
+    }
+  });
+  int64_t ntiles = 0;
+  int32_t hw = 1;
+  for (int64_t q = 0; q < nb; ++q) {
+    bl[q].tile0 = ntiles;
+    bl[q].ntiles = int32_t(bheads[q].size());
+    ntiles += bl[q].ntiles;
+    hw = std::max(hw, int32_t((bl[q].nsyn + 31) / 32));
+  }
+  d.n_bundles = nb;
+  d.n_tiles = ntiles;
+  d.hit_words = hw;
   dtb_status st;
-  if ((st = dalloc(net, &d.slice_off, ns)) || (st = dalloc(net, &d.slice_len, ns)) ||
-      (st = dalloc(net, &d.row_len, d.n_pad)) || (st = dalloc(net, &d.syn, std::max<int64_t>(1, off))))
-    return st;
   const size_t wsz = d.wtype == DTB_W_BF16 ? 2 : 4;
+  if ((st = dalloc(net, &d.bundles, nb)) || (st = dalloc(net, &d.tiles, std::max<int64_t>(1, ntiles) * kTile)) ||
+      (st = dalloc(net, &d.theads, std::max<int64_t>(1, ntiles))) || (st = dalloc(net, &d.row_ptr, n + 1)))
+    return st;
   {
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(1, size_t(off) * wsz));
+    hipError_t e = hipMalloc(&q, std::max<size_t>(1, size_t(s->nnz) * wsz));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(DTB_ERR_OOM, "hipMalloc of weights failed");
@@ -236,51 +306,40 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     net->allocs.push_back(q);
     d.wts = q;
   }
-  if ((st = upload(net, d.slice_off, soff.data(), ns * sizeof(int64_t))) ||
-      (st = upload(net, d.slice_len, slen.data(), ns * sizeof(int32_t))) ||
-      (st = upload(net, d.row_len, rlen.data(), d.n_pad * sizeof(int32_t))))
+  if ((st = upload(net, d.bundles, bl.data(), nb * sizeof(Bundle))) ||
+      (st = upload(net, d.row_ptr, s->row_ptr, (n + 1) * sizeof(int64_t))))
     return st;
-  // pack in chunks of whole slices so host staging stays bounded
-  const int64_t chunk_target = int64_t(1) << 26;  // entries per chunk (256 MB of words)
-  std::vector<uint32_t> hw;
+  for (int64_t q = 0; q < nb; ++q) {
+    if (bl[q].ntiles == 0) continue;
+    if ((st = upload(net, d.tiles + bl[q].tile0 * kTile, btiles[q].data(), btiles[q].size() * 4)) ||
+        (st = upload(net, d.theads + bl[q].tile0, bheads[q].data(), bheads[q].size() * 4)))
+      return st;
+    std::vector<uint32_t>().swap(btiles[q]);
+    std::vector<uint32_t>().swap(bheads[q]);
+  }
+  // 3. weights in CSR order with the sign bit marking an inhibitory source
+  const int64_t chunk = int64_t(1) << 26;
   std::vector<uint8_t> hwt;
-  int64_t q0 = 0;
-  while (q0 < ns) {
-    int64_t q1 = q0, cnt = 0;
-    while (q1 < ns && (cnt == 0 || cnt + int64_t(slen[q1]) * kSlice <= chunk_target)) {
-      cnt += int64_t(slen[q1]) * kSlice;
-      ++q1;
-    }
-    if (cnt > 0) {
-      hw.assign(size_t(cnt), 0u);
-      hwt.assign(size_t(cnt) * wsz, 0);
-      const int64_t base = soff[q0];
-      parallel_for(q1 - q0, [&](int64_t a, int64_t b) {
-        for (int64_t q = q0 + a; q < q0 + b; ++q) {
-          for (int l = 0; l < kSlice; ++l) {
-            const int64_t i = q * kSlice + l;
-            if (i >= s->n) break;
-            const int64_t r0 = s->row_ptr[i];
-            for (int32_t k = 0; k < rlen[i]; ++k) {
-              const int32_t m = s->col[r0 + k];
-              const uint32_t word = uint32_t(m) | (uint32_t(s->delay[r0 + k] - 1) << kColBits) |
-                                    (uint32_t(s->is_inh[m] ? 1 : 0) << 31);
-              const int64_t idx = soff[q] - base + int64_t(k) * kSlice + l;
-              hw[idx] = word;
-              if (wsz == 4) std::memcpy(&hwt[idx * 4], &s->w[r0 + k], 4);
-              else {
-                const uint16_t b16 = f32_to_bf16_rne(s->w[r0 + k]);
-                std::memcpy(&hwt[idx * 2], &b16, 2);
-              }
-            }
-          }
+  for (int64_t k0 = 0; k0 < s->nnz; k0 += chunk) {
+    const int64_t k1 = std::min<int64_t>(s->nnz, k0 + chunk);
+    hwt.assign(size_t(k1 - k0) * wsz, 0);
+    parallel_for(k1 - k0, [&](int64_t a, int64_t b) {
+      for (int64_t q = a; q < b; ++q) {
+        const int64_t k = k0 + q;
+        const bool inh = s->is_inh[s->col[k]] != 0;
+        if (wsz == 4) {
+          uint32_t u;
+          std::memcpy(&u, &s->w[k], 4);
+          u = (u & 0x7FFFFFFFu) | (inh ? 0x80000000u : 0u);
+          std::memcpy(&hwt[q * 4], &u, 4);
+        } else {
+          uint16_t u = uint16_t(f32_to_bf16_rne(s->w[k]) & 0x7FFFu);
+          u = uint16_t(u | (inh ? 0x8000u : 0u));
+          std::memcpy(&hwt[q * 2], &u, 2);
         }
-      });
-      if ((st = upload(net, d.syn + base, hw.data(), size_t(cnt) * 4)) ||
-          (st = upload(net, static_cast<uint8_t*>(d.wts) + base * wsz, hwt.data(), size_t(cnt) * wsz)))
-        return st;
-    }
-    q0 = q1;
+      }
+    });
+    if ((st = upload(net, static_cast<uint8_t*>(d.wts) + k0 * wsz, hwt.data(), hwt.size()))) return st;
   }
   return DTB_OK;
 }
@@ -333,6 +392,13 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
   *out = nullptr;
   dtb_status st = validate(desc);
   if (st) return st;
+  {
+    hipError_t e = gather_set_lds_limit();
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
+  }
   dtb_net* net = new (std::nothrow) dtb_net();
   if (!net) return fail(DTB_ERR_OOM, "host allocation failed");
   net->stream = static_cast<hipStream_t>(hip_stream);
@@ -342,13 +408,14 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
   d.n_pad = round_up(desc->n, kNeuronPad);
   d.words = dtb_bitmap_words(desc->n);
   d.words_pad = d.n_pad / 32;
-  d.n_slices = d.n_pad / kSlice;
+  d.nnz = desc->nnz;
   d.n_regions = desc->n_regions;
   d.max_delay = desc->max_delay;
   d.n_ptypes = desc->n_ptypes;
   d.member = desc->member;
   d.wtype = desc->wtype;
   d.rec = desc->record_steps;
+  d.slots = std::max(d.rec, d.max_delay) + 1;
   d.bg_w = desc->bg_w;
   d.seed = desc->seed;
   d.compact_blocks = (d.words_pad + 2 * kCompactBlock - 1) / (2 * kCompactBlock);
@@ -362,17 +429,17 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
     delete net;
     return fail(DTB_ERR_INVALID, "bg_lambda needs more than 512 inversion-table entries");
   }
-  const int64_t slots = int64_t(d.rec) + 1;
+  const int64_t slots = int64_t(d.slots);
   if ((st = dalloc(net, &d.V, d.n_pad)) || (st = dalloc(net, &d.j, 4 * d.n_pad)) ||
       (st = dalloc(net, &d.ref, d.n_pad)) || (st = dalloc(net, &d.ptype, d.n_pad)) ||
-      (st = dalloc(net, &d.region, d.n_pad)) || (st = dalloc(net, &d.ring, d.n_pad)) ||
+      (st = dalloc(net, &d.region, d.n_pad)) ||
       (st = dalloc(net, &d.ptab, d.n_ptypes)) || (st = dalloc(net, &d.gain, 4 * d.n_regions)) ||
       (st = dalloc(net, &d.poisson, std::max(1, d.poisson_K))) ||
       (st = dalloc(net, &d.raster, slots * d.words_pad)) ||
       (st = dalloc(net, &d.counts, slots * d.n_regions)) || (st = dalloc(net, &d.ev, slots * kStripes * 2)) ||
       (st = dalloc(net, &d.totals, 4)) || (st = dalloc(net, &d.ids, d.n_pad)) ||
       (st = dalloc(net, &d.id_count, 1)) || (st = dalloc(net, &d.cstatus, d.compact_blocks)) ||
-      (st = dalloc(net, &d.cticket, 1)) || (st = dalloc(net, &d.force, slots * d.words_pad)) ||
+      (st = dalloc(net, &d.cticket, 1)) || (st = dalloc(net, &d.force, (d.rec + 1) * d.words_pad)) ||
       (st = dalloc(net, &d.bad, 1))) {
     dtb_destroy(net);
     return st;
@@ -380,7 +447,7 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
   auto zero = [&](void* p, size_t bytes) { return hipMemsetAsync(p, 0, bytes, net->stream); };
   hipError_t e = hipSuccess;
   for (auto pr : std::vector<std::pair<void*, size_t>>{
-           {d.j, 4 * d.n_pad * sizeof(float)}, {d.ref, size_t(d.n_pad)}, {d.ring, d.n_pad * 4},
+           {d.j, 4 * d.n_pad * sizeof(float)}, {d.ref, size_t(d.n_pad)},
            {d.raster, slots * d.words_pad * 4}, {d.counts, slots * d.n_regions * 4},
            {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32}, {d.id_count, 4},
            {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.ptype, d.n_pad * 2},
@@ -513,7 +580,7 @@ dtb_status dtb_read_spikes(dtb_net* net, int64_t t0, int64_t t1, uint32_t* dst, 
   if (!dst && t1 > t0) return fail(DTB_ERR_INVALID, "dst is NULL");
   const DeviceNet& d = net->d;
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t slot = t % (d.rec + 1);
+    const int64_t slot = t % d.slots;
     if ((st = copy_out(net, dst + (t - t0) * d.words, d.raster + slot * d.words_pad, d.words * 4, dst_on_device)))
       return st;
   }
@@ -561,7 +628,7 @@ dtb_status dtb_read_region_counts(dtb_net* net, int64_t t0, int64_t t1, int32_t*
   if (!dst && t1 > t0) return fail(DTB_ERR_INVALID, "dst is NULL");
   const DeviceNet& d = net->d;
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t slot = t % (d.rec + 1);
+    const int64_t slot = t % d.slots;
     if ((st = copy_out(net, dst + (t - t0) * d.n_regions, d.counts + slot * d.n_regions, d.n_regions * 4, 0)))
       return st;
   }
@@ -590,7 +657,7 @@ dtb_status dtb_read_step_events(dtb_net* net, int64_t t0, int64_t t1, int64_t* e
   const DeviceNet& d = net->d;
   int64_t v[2];
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t slot = t % (d.rec + 1);
+    const int64_t slot = t % d.slots;
     if ((st = copy_out(net, v, d.ev + slot * kStripes * 2, 16, 0))) return st;
     if (ev_rec) ev_rec[t - t0] = v[0];
     if (ev_bg) ev_bg[t - t0] = v[1];

@@ -6,26 +6,44 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <string>
-
 #include "../../include/dtb.h"
 
 namespace dtb {
 
-// Packed synapse word of the connection table (Sec. V-D), one per synapse:
-//   bits  0..25  presynaptic neuron id (n < 2^26)
-//   bits 26..30  delay - 1             (1 <= delay <= 31)
-//   bit  31      presynaptic neuron is inhibitory
-constexpr uint32_t kColBits = 26;
-constexpr uint32_t kColMask = (1u << kColBits) - 1u;
 constexpr int kMaxDelay = 31;
-constexpr int64_t kMaxNeurons = (int64_t(1) << kColBits) - 1;
-constexpr int kSlice = 64;          // rows per SELL slice = one wavefront
+constexpr int64_t kMaxNeurons = (int64_t(1) << 26) - 1;
 constexpr int kNeuronPad = 1024;    // neuron arrays padded to this multiple
 constexpr int kStripes = 64;        // striped event counters per step
 constexpr int kMaxPoisson = 512;    // entries of the background inversion table
 constexpr int kCompactBlock = 256;  // threads of the compaction kernel
-constexpr int kCompactPerBlock = kCompactBlock * 64;  // neurons per compaction block
+
+// ---- gather layout ("bundles") --------------------------------------------
+// Rows are cut into bundles of consecutive rows holding at most
+// kBundleMaxSyn synapses.  One workgroup owns a bundle.  A bundle's synapses
+// are stored twice:
+//  * the weight stream, in CSR order (= the fixed summation order), the sign
+//    bit marking an inhibitory presynaptic neuron;
+//  * the lookup stream: the same synapses sorted by (delay, source), cut into
+//    tiles of 64 entries.  Entry = source delta (12 bits, relative to the
+//    previous entry of the tile; the first entry has delta 0) << 20 | position
+//    of the synapse in the bundle's CSR range (20 bits; kInvalidPos = padding).
+//    Tile header = first source of the tile (26 bits) | (delay - 1) << 26.
+constexpr int kTile = 64;
+constexpr int kPosBits = 20;
+constexpr uint32_t kPosMask = (1u << kPosBits) - 1u;
+constexpr uint32_t kInvalidPos = kPosMask;
+constexpr uint32_t kMaxDelta = (1u << (32 - kPosBits)) - 1u;  // 4095
+constexpr int64_t kBundleMaxSyn = int64_t(kInvalidPos);     // positions 0 .. 2^20 - 2
+constexpr int kGatherThreads = 1024;
+constexpr int kHitWords = int((kBundleMaxSyn + 31) / 32);   // LDS hit bitmap words
+
+struct Bundle {
+  int64_t row0, row1;   // rows [row0, row1)
+  int64_t syn0;         // CSR index of the bundle's first synapse
+  int64_t tile0;        // first tile of the bundle's lookup stream
+  int32_t ntiles;       // tiles of the lookup stream
+  int32_t nsyn;         // synapses of the bundle
+};
 
 // Derived per-type constants in the order the neuron update reads them.
 struct PType {
@@ -38,11 +56,14 @@ struct PType {
 
 struct DeviceNet {
   // sizes
-  int64_t n = 0, n_pad = 0, words = 0, n_slices = 0, total_slots = 0;
+  int64_t n = 0, n_pad = 0, words = 0, words_pad = 0, nnz = 0;
   int32_t n_regions = 0, max_delay = 0, n_ptypes = 0, member = 0;
-  int32_t wtype = 0, rec = 0;       // rec = record_steps; rings hold rec + 1 slots
+  int32_t wtype = 0, rec = 0;       // rec = record_steps
+  int32_t slots = 0;                // spike-bitmap ring slots: max(rec, D) + 1
   int32_t poisson_K = 0;
   int64_t compact_blocks = 0;
+  int64_t n_bundles = 0, n_tiles = 0;
+  int32_t hit_words = 1;            // LDS words of the largest bundle's hit bitmap
   float a[4] = {0, 0, 0, 0};        // exp(-dt / tau_u)
   float E[4] = {0, 0, 0, 0};        // reversal potentials
   float bg_w = 0.f;
@@ -53,20 +74,19 @@ struct DeviceNet {
   uint8_t* ref = nullptr;           // [n_pad]
   uint16_t* ptype = nullptr;        // [n_pad]
   int32_t* region = nullptr;        // [n_pad]
-  uint32_t* ring = nullptr;         // [n_pad] delay ring: bit (t & 31) holds s^t
   PType* ptab = nullptr;            // [n_ptypes]
   float* gain = nullptr;            // [n_regions][4]
   uint32_t* poisson = nullptr;      // [poisson_K]
-  // connection table, SELL-64
-  uint32_t* syn = nullptr;          // [total_slots] packed words
-  void* wts = nullptr;              // [total_slots] float or bf16 (uint16)
-  int64_t* slice_off = nullptr;     // [n_slices]
-  int32_t* slice_len = nullptr;     // [n_slices]
-  int32_t* row_len = nullptr;       // [n_pad]
+  // connection table
+  int64_t* row_ptr = nullptr;       // [n + 1]
+  void* wts = nullptr;              // [nnz] float or bf16, sign bit = inhibitory source
+  uint32_t* tiles = nullptr;        // [n_tiles][kTile] lookup entries
+  uint32_t* theads = nullptr;       // [n_tiles] tile headers
+  Bundle* bundles = nullptr;        // [n_bundles]
   // history and outputs
-  uint32_t* raster = nullptr;       // [rec + 1][words_pad] spike bitmaps
-  int32_t* counts = nullptr;        // [rec + 1][n_regions]
-  int64_t* ev = nullptr;            // [rec + 1][kStripes][2] striped (rec, bg); [slot][0][*] final
+  uint32_t* raster = nullptr;       // [slots][words_pad] spike bitmaps: the delay ring
+  int32_t* counts = nullptr;        // [slots][n_regions]
+  int64_t* ev = nullptr;            // [slots][kStripes][2] striped (rec, bg); [slot][0][*] final
   int64_t* totals = nullptr;        // [4]: spikes, ev_rec, ev_bg, steps
   int32_t* ids = nullptr;           // [n_pad] ascending spike ids of the last step
   int32_t* id_count = nullptr;      // [1]
@@ -74,7 +94,6 @@ struct DeviceNet {
   uint32_t* cticket = nullptr;      // [1] dynamic block ticket
   uint32_t* force = nullptr;        // [rec + 1][words_pad] pending forced bitmaps
   int32_t* bad = nullptr;           // [1] non-finite flag
-  int64_t words_pad = 0;
 };
 
 // launchers (dtb_kernels.hip); all enqueue on `s`
@@ -82,5 +101,6 @@ hipError_t launch_neuron_update(const DeviceNet& d, int64_t t, const uint32_t* f
 hipError_t launch_compact(const DeviceNet& d, int64_t t, hipStream_t s);
 hipError_t launch_gather(const DeviceNet& d, int64_t t, hipStream_t s);
 hipError_t launch_finalize(const DeviceNet& d, int64_t t, hipStream_t s);
+hipError_t gather_set_lds_limit();
 
 }  // namespace dtb

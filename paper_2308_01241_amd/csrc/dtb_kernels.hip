@@ -2,15 +2,16 @@
 //
 // A step t is, in stream order (the computing cycle of Sec. V-B / VI-C):
 //   k_neuron_update  membrane update of Eq. (1) by forward Euler (Sec. VI-A),
-//                    threshold / reset / refractory, spike into the delay
-//                    ring, wavefront ballot into the step's spike bitmap,
-//                    per-population spike counts;
+//                    threshold / reset / refractory, wavefront ballot into
+//                    the step's spike bitmap (a slot of the delay ring of
+//                    bitmaps), per-population spike counts;
 //   k_compact        ascending spike-id list from the bitmap (ballot
 //                    popcounts, block scan, decoupled look-back);
-//   k_gather         pull over each row's in-edges in CSR order through the
-//                    delay ring (J_intra), plus the Poisson count that stands
-//                    in for the spikes of other partitions (J_inter), then
-//                    the gate update (jump + exact exponential decay);
+//   k_gather         pull over each row's in-edges through the delay ring
+//                    (J_intra) - delivery tests in (delay, source) order,
+//                    sums in each row's CSR order - plus the Poisson count
+//                    that stands in for the spikes of other partitions
+//                    (J_inter), then the gate update (jump + exact decay);
 //   k_finalize       per-step event totals.
 //
 // Everything is FP32 except the integer work (ids, delays, ballots, counts,
@@ -60,7 +61,7 @@ __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_
 __global__ __launch_bounds__(1024) void k_neuron_update(
     int64_t n, int64_t n_pad, int64_t t, float* __restrict__ V, const float* __restrict__ j,
     uint8_t* __restrict__ ref, const uint16_t* __restrict__ ptype, const int32_t* __restrict__ region,
-    uint32_t* __restrict__ ring, const PType* __restrict__ ptab, const float* __restrict__ gain,
+    const PType* __restrict__ ptab, const float* __restrict__ gain,
     float E0, float E1, float E2, float E3, const uint32_t* __restrict__ forced,
     uint32_t* __restrict__ raster_slot, int32_t* __restrict__ counts_slot, uint32_t* __restrict__ cticket,
     int32_t* __restrict__ bad) {
@@ -104,9 +105,6 @@ __global__ __launch_bounds__(1024) void k_neuron_update(
     V[i] = nv;
     ref[i] = (uint8_t)nr;
     if (!isfinite(nv)) atomicOr(bad, 1);
-    const uint32_t bit = 1u << (uint32_t(t) & 31u);
-    const uint32_t h = ring[i];
-    ring[i] = s ? (h | bit) : (h & ~bit);
   }
   // the wavefront's 64 spike predicates are 64 consecutive bits of the bitmap
   const uint64_t m = __ballot(s);
@@ -151,9 +149,16 @@ __global__ __launch_bounds__(1024) void k_neuron_update(
 // ---------------------------------------------------------------- compaction
 // Each thread owns 64 neurons (two bitmap words).  Blocks take a dynamic
 // ticket so that a block only waits on blocks that are already running.
-// Look-back status word: epoch (32) | flag (2: 1 aggregate, 2 prefix) | value (30).
+// Look-back status word: epoch (32) | flag (2: 1 aggregate, 2 prefix) | value (30);
+// one wavefront inspects 64 predecessors per round.
 __device__ inline uint64_t pack_status(uint32_t epoch, uint32_t flag, uint32_t value) {
   return (uint64_t(epoch) << 32) | (uint64_t(flag) << 30) | uint64_t(value);
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
 __global__ __launch_bounds__(kCompactBlock) void k_compact(
@@ -185,30 +190,42 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
     if (w < wave) wave_off += s_wave[w];
     agg += s_wave[w];
   }
-  if (tid == 0) {
+  if (wave == 0) {
     uint32_t excl = 0;
     if (bid == 0) {
-      __hip_atomic_store(&status[0], pack_status(epoch, 2, uint32_t(agg)), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&status[0], pack_status(epoch, 2, uint32_t(agg)), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      __hip_atomic_store(&status[bid], pack_status(epoch, 1, uint32_t(agg)), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int64_t p = bid - 1;
+      if (lane == 0)
+        __hip_atomic_store(&status[bid], pack_status(epoch, 1, uint32_t(agg)), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      int64_t top = bid - 1;  // lane l inspects predecessor top - l
       while (true) {
-        const uint64_t st = __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t idx = top - lane;
+        const uint64_t st = idx >= 0 ? __hip_atomic_load(&status[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                                     : pack_status(epoch, 2, 0);
         const uint32_t flag = uint32_t(st >> 30) & 3u;
-        if (uint32_t(st >> 32) != epoch || flag == 0) continue;  // predecessor still running
-        excl += uint32_t(st) & 0x3FFFFFFFu;
-        if (flag == 2) break;
-        --p;
+        const bool ready = uint32_t(st >> 32) == epoch && flag != 0;
+        const uint64_t incl = __ballot(ready && flag == 2);
+        const uint64_t wait = __ballot(!ready);
+        const int f = incl ? __ffsll((unsigned long long)incl) - 1 : 64;   // nearest inclusive prefix
+        const uint64_t need = f >= 63 ? ~0ull : ((2ull << f) - 1ull);        // lanes 0 .. f
+        if (wait & need) continue;                                           // a predecessor is still running
+        excl += wave_sum_u32(lane <= f ? (uint32_t(st) & 0x3FFFFFFFu) : 0u);
+        if (f < 64) break;
+        top -= 64;
       }
-      __hip_atomic_store(&status[bid], pack_status(epoch, 2, excl + uint32_t(agg)), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&status[bid], pack_status(epoch, 2, excl + uint32_t(agg)), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_excl = int(excl);
-    if (bid == n_blocks - 1) {
-      *id_count = int(excl) + agg;
-      atomicAdd(reinterpret_cast<unsigned long long*>(spike_total), (unsigned long long)(excl + agg));
+    if (lane == 0) {
+      s_excl = int(excl);
+      if (bid == n_blocks - 1) {
+        *id_count = int(excl) + agg;
+        atomicAdd(reinterpret_cast<unsigned long long*>(spike_total), (unsigned long long)(excl + agg));
+      }
     }
   }
   __syncthreads();
@@ -227,70 +244,130 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
 }
 
 // ------------------------------------------------------------------ gather
-// One wavefront per SELL-64 slice (64 consecutive rows), one lane per row.
-// Lane `l` walks its row in CSR order k = 0, 1, ...: the slice stores entry
-// (k, l) at slice_off + 64 k + l, so the wavefront's loads of one k are one
-// contiguous 256-byte segment.  A synapse delivers when bit (t - d + 1) & 31
-// of its presynaptic neuron's ring word is set.
+// One workgroup (16 wavefronts) per bundle of rows.
+//  Phase 1 - delivery tests.  The bundle's lookup stream is sorted by
+//    (delay, source); a wavefront takes one 64-entry tile per load, rebuilds
+//    the sources by a prefix sum of the 12-bit deltas, reads the spike bit of
+//    step t - d + 1 from that step's bitmap (monotone addresses, so the
+//    cache lines of the bitmaps are swept rather than hit at random) and
+//    sets the synapse's bit in the LDS hit bitmap (integer OR: order-free).
+//  Phase 2 - sums.  Each lane takes rows of the bundle; for a row it visits
+//    the set hit bits in ascending position, which is the row's CSR order,
+//    loads only those weights and accumulates E and I in FP32 - the fixed
+//    per-neuron summation order - then adds the background count and
+//    updates the four gates.
+// Workgroups are mapped XCD-aware: the blocks an XCD receives (blockIdx
+// congruent mod 8) take a contiguous range of bundles, so bundles of the
+// same population (same source set) share that XCD's L2.
+constexpr int kUnroll = 8;
+
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
 template <bool kBF16>
-__global__ __launch_bounds__(256) void k_gather(
-    int64_t n, int64_t n_slices, int64_t n_pad, int64_t t, int32_t member, uint64_t seed,
-    const uint32_t* __restrict__ syn, const void* __restrict__ wts_v, const int64_t* __restrict__ slice_off,
-    const int32_t* __restrict__ slice_len, const int32_t* __restrict__ row_len,
-    const uint32_t* __restrict__ ring, float* __restrict__ j, float a0, float a1, float a2, float a3,
+__global__ __launch_bounds__(kGatherThreads) void k_gather(
+    int64_t n, int64_t n_bundles, int64_t n_pad, int64_t t, int32_t member, uint64_t seed,
+    const Bundle* __restrict__ bundles, const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
+    const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v, const uint32_t* __restrict__ bitmaps,
+    int64_t words_pad, int32_t slots, float* __restrict__ j, float a0, float a1, float a2, float a3,
     float bg_w, const uint32_t* __restrict__ poisson, int K, int64_t* __restrict__ ev_slot,
     int32_t* __restrict__ bad) {
-  __shared__ int64_t s_ev[4][2];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t slice = int64_t(blockIdx.x) * 4 + wave;
+  extern __shared__ uint32_t s_hits[];
+  __shared__ uint32_t s_ev[kGatherThreads / 64][2];
+  __shared__ int64_t s_slot[32];  // bitmap offset of step t - d1, d1 = delay - 1
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t per = (n_bundles + 7) / 8;
+  const int64_t bi = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (bi >= n_bundles) return;  // whole block leaves together
+  const Bundle B = bundles[bi];
+  const int hw = (B.nsyn + 31) >> 5;
+  for (int q = tid; q < hw; q += kGatherThreads) s_hits[q] = 0u;
+  if (tid < 32) {
+    // steps before 0 map to slots not yet written (all-zero bitmaps)
+    const int64_t te = t - tid;
+    s_slot[tid] = (((te % slots) + slots) % slots) * words_pad;
+  }
+  __syncthreads();
+
+  // ---- phase 1: delivery tests in (delay, source) order
+  const uint32_t* tp = tiles + B.tile0 * kTile + lane;
+  const uint32_t* hp = theads + B.tile0;
+  constexpr int kWaves = kGatherThreads / 64;
+  for (int q0 = wave; q0 < B.ntiles; q0 += kWaves * kUnroll) {
+    uint32_t e[kUnroll], h[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int q = q0 + u * kWaves;
+      const bool ok = q < B.ntiles;
+      e[u] = ok ? tp[int64_t(q) * kTile] : kInvalidPos;
+      h[u] = ok ? __builtin_amdgcn_readfirstlane(hp[q]) : 0u;
+    }
+    uint32_t src[kUnroll], word[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) src[u] = (h[u] & 0x3FFFFFFu) + wave_incl_scan_u32(e[u] >> kPosBits, lane);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t base = s_slot[h[u] >> 26];  // spikes of step t - d + 1 arrive now
+      word[u] = (e[u] & kPosMask) != kInvalidPos ? bitmaps[base + (src[u] >> 5)] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if ((word[u] >> (src[u] & 31u)) & 1u) {
+        const uint32_t pos = e[u] & kPosMask;
+        atomicOr(&s_hits[pos >> 5], 1u << (pos & 31u));
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: sums in CSR order, background, gates
   uint32_t ev = 0, evb = 0;
-  if (slice < n_slices) {
-    const int64_t row = slice * kSlice + lane;
-    const int64_t base = slice_off[slice];
-    const int L = slice_len[slice];
-    const int len = row_len[row];
-    const uint32_t* sp = syn + base + lane;
-    const float* wf = reinterpret_cast<const float*>(wts_v) + base + lane;
-    const uint16_t* wb = reinterpret_cast<const uint16_t*>(wts_v) + base + lane;
-    const uint32_t tt = uint32_t(t);
+  const float* wf = reinterpret_cast<const float*>(wts_v);
+  const uint16_t* wb = reinterpret_cast<const uint16_t*>(wts_v);
+  for (int64_t r = B.row0 + tid; r < B.row1; r += kGatherThreads) {
+    const int64_t k0 = row_ptr[r] - B.syn0, k1 = row_ptr[r + 1] - B.syn0;
     float dE = 0.f, dI = 0.f;
-    int k = 0;
-    for (; k + 8 <= L; k += 8) {
-      uint32_t wd[8], h[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) wd[u] = sp[int64_t(k + u) * kSlice];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) h[u] = (k + u < len) ? ring[wd[u] & kColMask] : 0u;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const uint32_t hit = (h[u] >> ((tt - ((wd[u] >> kColBits) & 31u)) & 31u)) & 1u;
-        if (hit) {
-          const int64_t o = int64_t(k + u) * kSlice;
-          const float w = kBF16 ? bf16_to_f32(wb[o]) : wf[o];
-          if (wd[u] >> 31) dI += w;
-          else dE += w;
+    if (k1 > k0) {
+      const int w0 = int(k0 >> 5), w1 = int((k1 - 1) >> 5);
+      for (int w = w0; w <= w1; ++w) {
+        uint32_t bits = s_hits[w];
+        if (w == w0) bits &= ~0u << (k0 & 31);
+        if (w == w1) bits &= ~0u >> (31 - ((k1 - 1) & 31));
+        while (bits) {
+          const int bb = __ffs(bits) - 1;
+          bits &= bits - 1u;
+          const int64_t p = B.syn0 + int64_t(w) * 32 + bb;
+          uint32_t u;
+          float wv;
+          if (kBF16) {
+            const uint16_t x = wb[p];
+            u = x >> 15;
+            wv = bf16_to_f32(uint16_t(x & 0x7FFFu));
+          } else {
+            const uint32_t x = __float_as_uint(wf[p]);
+            u = x >> 31;
+            wv = __uint_as_float(x & 0x7FFFFFFFu);
+          }
+          if (u) dI += wv;
+          else dE += wv;
           ++ev;
         }
       }
     }
-    for (; k < L; ++k) {
-      const uint32_t wd = sp[int64_t(k) * kSlice];
-      const uint32_t h = (k < len) ? ring[wd & kColMask] : 0u;
-      if ((h >> ((tt - ((wd >> kColBits) & 31u)) & 31u)) & 1u) {
-        const int64_t o = int64_t(k) * kSlice;
-        const float w = kBF16 ? bf16_to_f32(wb[o]) : wf[o];
-        if (wd >> 31) dI += w;
-        else dE += w;
-        ++ev;
-      }
-    }
-    if (row < n) {
+    if (r < n) {
       // background Poisson count: Philox4x64-10, key (seed, 0), counter (t, i, member, 0)
-      const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(row), uint64_t(member), 0ull, seed, 0ull));
+      const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r), uint64_t(member), 0ull, seed, 0ull));
       const int c = poisson_count(u, poisson, K);
-      evb = uint32_t(c);
+      evb += uint32_t(c);
       dE = __fmaf_rn(float(c), bg_w, dE);
-      float* jr = j + row;
+      float* jr = j + r;
       const float ja = __fmaf_rn(a0, jr[0], dE);
       const float jn = __fmaf_rn(a1, jr[n_pad], dE);
       const float jga = __fmaf_rn(a2, jr[2 * n_pad], dI);
@@ -310,13 +387,16 @@ __global__ __launch_bounds__(256) void k_gather(
     eb += __shfl_down(eb, off);
   }
   if (lane == 0) {
-    s_ev[wave][0] = e;
-    s_ev[wave][1] = eb;
+    s_ev[tid >> 6][0] = e;
+    s_ev[tid >> 6][1] = eb;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t r = s_ev[0][0] + s_ev[1][0] + s_ev[2][0] + s_ev[3][0];
-    const int64_t bgs = s_ev[0][1] + s_ev[1][1] + s_ev[2][1] + s_ev[3][1];
+  if (tid == 0) {
+    int64_t r = 0, bgs = 0;
+    for (int w = 0; w < kGatherThreads / 64; ++w) {
+      r += s_ev[w][0];
+      bgs += s_ev[w][1];
+    }
     int64_t* dst = ev_slot + 2 * (blockIdx.x & (kStripes - 1));
     if (r) atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)r);
     if (bgs) atomicAdd(reinterpret_cast<unsigned long long*>(dst + 1), (unsigned long long)bgs);
@@ -352,16 +432,16 @@ __global__ __launch_bounds__(64) void k_finalize(int64_t* __restrict__ ev_slot, 
 }  // namespace
 
 hipError_t launch_neuron_update(const DeviceNet& d, int64_t t, const uint32_t* forced, hipStream_t s) {
-  const int64_t slot = t % (d.rec + 1);
+  const int64_t slot = t % d.slots;
   const unsigned grid = unsigned(d.n_pad / 1024);
   hipLaunchKernelGGL(k_neuron_update, dim3(grid), dim3(1024), 0, s, d.n, d.n_pad, t, d.V, d.j, d.ref,
-                     d.ptype, d.region, d.ring, d.ptab, d.gain, d.E[0], d.E[1], d.E[2], d.E[3], forced,
+                     d.ptype, d.region, d.ptab, d.gain, d.E[0], d.E[1], d.E[2], d.E[3], forced,
                      d.raster + slot * d.words_pad, d.counts + slot * d.n_regions, d.cticket, d.bad);
   return hipGetLastError();
 }
 
 hipError_t launch_compact(const DeviceNet& d, int64_t t, hipStream_t s) {
-  const int64_t slot = t % (d.rec + 1);
+  const int64_t slot = t % d.slots;
   hipLaunchKernelGGL(k_compact, dim3(unsigned(d.compact_blocks)), dim3(kCompactBlock), 0, s,
                      d.raster + slot * d.words_pad, d.words_pad, d.compact_blocks,
                      uint32_t(uint64_t(t) + 1u), d.ids, d.id_count, d.cstatus, d.cticket, d.totals);
@@ -369,22 +449,32 @@ hipError_t launch_compact(const DeviceNet& d, int64_t t, hipStream_t s) {
 }
 
 hipError_t launch_gather(const DeviceNet& d, int64_t t, hipStream_t s) {
-  const int64_t slot = t % (d.rec + 1);
-  const unsigned grid = unsigned((d.n_slices + 3) / 4);
+  const int64_t slot = t % d.slots;
+  const unsigned grid = unsigned((d.n_bundles + 7) / 8 * 8);
+  const size_t lds = size_t(d.hit_words) * 4;
   int64_t* evs = d.ev + slot * kStripes * 2;
   if (d.wtype == DTB_W_BF16)
-    hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(256), 0, s, d.n, d.n_slices, d.n_pad, t, d.member,
-                       d.seed, d.syn, d.wts, d.slice_off, d.slice_len, d.row_len, d.ring, d.j, d.a[0], d.a[1],
-                       d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, evs, d.bad);
+    hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad, t,
+                       d.member, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
+                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, evs, d.bad);
   else
-    hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(256), 0, s, d.n, d.n_slices, d.n_pad, t, d.member,
-                       d.seed, d.syn, d.wts, d.slice_off, d.slice_len, d.row_len, d.ring, d.j, d.a[0], d.a[1],
-                       d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, evs, d.bad);
+    hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad, t,
+                       d.member, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
+                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, evs, d.bad);
   return hipGetLastError();
 }
 
+hipError_t gather_set_lds_limit() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kHitWords * 4);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kHitWords * 4);
+  return e;
+}
+
 hipError_t launch_finalize(const DeviceNet& d, int64_t t, hipStream_t s) {
-  const int64_t slot = t % (d.rec + 1), next = (t + 1) % (d.rec + 1);
+  const int64_t slot = t % d.slots, next = (t + 1) % d.slots;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, d.ev + slot * kStripes * 2,
                      d.ev + next * kStripes * 2, d.counts + next * d.n_regions, d.n_regions, d.totals);
   return hipGetLastError();

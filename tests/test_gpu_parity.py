@@ -179,3 +179,27 @@ def test_single_neuron_no_synapses_isi(dtb):
     g.step(200)
     spikes = np.nonzero(g.raster(0, 200)[:, 0])[0]
     assert spikes[0] == 30 and np.all(np.diff(spikes) == 33)
+
+
+def test_many_bundles_teacher_forced(dtb):
+    """A 60,000-neuron partition net cuts into hundreds of row bundles: the
+    per-step delivered events must match the reference exactly and the state
+    stay within tolerance across bundle boundaries."""
+    net = netgen.make_network(netgen.partition_spec(n=60_000, bg_lambda=0.5))
+    T = 40
+    rng = np.random.default_rng(11)
+    forced = (rng.random((T, net.n)) < 0.02).astype(np.uint8)   # 20 Hz synthetic raster
+    o = oracle.OracleNet(net)
+    g = _gpu(dtb, net)
+    g.force(forced)
+    for t in range(T):
+        out = o.step(forced=forced[t])
+        g.step(1)
+        er, eb = g.step_events(t, t + 1)
+        assert int(er[0]) == out["ev_rec"] and int(eb[0]) == out["ev_bg"], f"step {t}"
+    jmax = max(np.abs(o.get(f)).max() for f in FIELDS[1:])
+    for f in FIELDS:
+        floor = 0.0 if f == "V" else 1e-3 * jmax
+        ok = _state_close(g.state(f), o.get(f), floor)
+        assert ok.all(), f"{f}: {np.count_nonzero(~ok)} neurons out of tolerance"
+    np.testing.assert_array_equal(g.region_counts(0, T).sum(axis=1), forced.sum(axis=1))
