@@ -105,6 +105,52 @@ def cpu_baseline(net, rate_hz: float, frac: float = 0.02, warm: int = 20, timed:
             "rtf_extrapolated": step_s / frac / (net.dt_ms * 1e-3)}
 
 
+def tune_rates(net, rates, steps=400, skip=150, iters=9):
+    """Bisect the background drive so that the mean rate over steps
+    [skip, steps) hits each target (one handle, reset between trials)."""
+    import torch
+    import paper_2308_01241_amd as dtb
+
+    g = dtb.Net(net, record_steps=steps, stream=torch.cuda.current_stream())
+    out = {}
+
+    def rate(lam):
+        g.reset()
+        g.set_background(lam, net.bg_w)
+        g.step(steps)
+        c = g.region_counts(skip, steps).sum()
+        return c / (net.n * (steps - skip) * net.dt_ms * 1e-3)
+
+    for r in rates:
+        lo, hi = 0.02, 8.0
+        for _ in range(iters):
+            mid = float(np.sqrt(lo * hi))
+            m = rate(mid)
+            log(f"[tune] target {r} Hz: lambda {mid:.5f} -> {m:.3f} Hz")
+            if m < r:
+                lo = mid
+            else:
+                hi = mid
+        lam = float(np.sqrt(lo * hi))
+        out[r] = {"bg_lambda": round(lam, 5), "rate_hz": float(rate(lam))}
+    g.close()
+    return out
+
+
+def calibrate_copy(gib: float = 1.0):
+    """A plain elementwise pass of known size (reads and writes `gib` GiB),
+    whose FETCH_SIZE / WRITE_SIZE readings scale the counters of the
+    simulator's kernels."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.add(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    return {"calibration": "elementwise add", "bytes_read": 4 * n, "bytes_written": 4 * n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +160,8 @@ def main():
     ap.add_argument("--rates", type=str, default="7,15,30")
     ap.add_argument("--wtype", type=str, default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="bisect the background drive per target rate")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run a plain copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's partition; --gpus {args.gpus} is not supported "
@@ -126,10 +174,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dtb.load()
+    if args.calibrate_copy:
+        print(json.dumps(calibrate_copy()), flush=True)
+        return
     rates = [int(x) for x in args.rates.split(",")]
     t0 = time.time()
     net = netgen.make_network(netgen.partition_spec(n=args.n, rate_hz=rates[0]))
     log(f"[bench] generated n={net.n} nnz={net.nnz} in {time.time() - t0:.1f}s")
+    if args.tune:
+        print(json.dumps({"tuned": tune_rates(net, rates), "n": net.n}), flush=True)
+        return
     res = {}
     for r in rates:
         res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype)

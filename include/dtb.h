@@ -127,6 +127,18 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out);
  * (asynchronous on the handle's stream).  n_steps >= 0. */
 dtb_status dtb_step(dtb_net* net, int32_t n_steps);
 
+/* Return to the initial state of dtb_create (V = V0, gates 0, no refractory
+ * neuron, empty delay ring, counters 0, t = 0), keeping the tables, the
+ * background settings and any gains.  Re-running after a reset with the same
+ * settings reproduces the first run exactly (the background draws are keyed
+ * by step, neuron and member).  Drops pending teacher forcing. */
+dtb_status dtb_reset(dtb_net* net);
+
+/* Change the background drive standing in for J_inter (Sec. V-B): mean
+ * Poisson count per neuron-step (0 .. 400) and event weight (finite, >= 0).
+ * Takes effect from the next step. */
+dtb_status dtb_set_background(dtb_net* net, double bg_lambda, float bg_w);
+
 /* Teacher forcing (a test hook for the accuracy check of Sec. VII-B): the
  * next n_steps steps take their spikes from bits (host, [n_steps] bitmaps
  * of dtb_bitmap_words(n) words) instead of the threshold test.  A forced bit
@@ -177,6 +189,76 @@ dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int6
  * finalize (double [4], int64 [4]; either may be NULL), and clears them. */
 dtb_status dtb_set_timing(dtb_net* net, int enable);
 dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches);
+
+/* ------------------------------------------------- batched ensemble */
+
+/* Build one handle that advances n_members independent networks together
+ * (the ensemble of brain samples that the paper's data assimilation runs on
+ * disjoint node sets, Sec. V-E).  The members become one block-diagonal
+ * partition: member m's neurons, populations and property-table rows follow
+ * member m-1's.  Each member keeps its own background counter (t, i, member,
+ * 0), i its own neuron index and member its desc's `member` field, so a
+ * member advanced in a batch computes exactly what it computes alone.
+ * Members may differ in size, connectivity, populations, property table and
+ * V0; E, tau_ms, dt_ms, bg_lambda, bg_w, seed, wtype and record_steps must be
+ * equal (DTB_ERR_UNSUPPORTED otherwise).  Inputs are copied. */
+dtb_status dtb_create_batch(const dtb_desc* members, int32_t n_members, void* hip_stream,
+                            dtb_net** out);
+
+/* Member table of a handle: *n_members, and for m = 0 .. min(cap, n_members)
+ * the first neuron (int64) and first population (int32) of member m (entry
+ * n_members holds the totals).  A plain partition is one member. */
+dtb_status dtb_batch_info(dtb_net* net, int32_t* n_members, int64_t* neuron_offset,
+                          int32_t* region_offset, int32_t cap);
+
+/* Per-population gains on the four channel conductances (the population
+ * hyper-parameters of the assimilation, Sec. V-E): g_u of every neuron of
+ * population r is multiplied by gains[4 r + u].  float32 [n_regions][4],
+ * finite and >= 0 (checked for host sources).  Default 1. */
+dtb_status dtb_set_gains(dtb_net* net, const float* gains, int src_on_device);
+
+/* Advance n_steps steps as one captured HIP graph (captured on the first
+ * call with a given n_steps, replayed afterwards); same results as
+ * dtb_step(n_steps).  Not available while teacher forcing is pending. */
+dtb_status dtb_run(dtb_net* net, int32_t n_steps);
+
+/* Balloon-Windkessel BOLD signal per population after the last step (the
+ * hemodynamic readout of Sec. V-E, integrated with the population rates of
+ * every step): y float32 [n_regions] (host or device), and optionally the
+ * state (s, f, v, q) float32 [n_regions][4] (host only).  Either may be NULL. */
+dtb_status dtb_read_bold(dtb_net* net, float* y, float* sfvq, int dst_on_device);
+
+/* ------------------------------------------------------- surrogate */
+
+/* A small dense network that predicts population rates and BOLD from
+ * population hyper-parameters, to screen assimilation proposals (Sec. V-E)
+ * before they are simulated.  Layers: n_in -> n_hidden x hidden (exact-erf
+ * GELU) -> n_out (linear).  Matrix products on MFMA with bfloat16 operands
+ * and FP32 accumulation; parameters, Adam state and gradients FP32.
+ * Parameters are one flat float32 vector, layer by layer: W [out][in]
+ * row-major then b [out] (dtb_mlp_num_params entries).  Initial weights are
+ * uniform(-1/sqrt(in), 1/sqrt(in)) from `seed`, biases 0. */
+typedef struct dtb_mlp dtb_mlp;
+dtb_status dtb_mlp_create(int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out, uint64_t seed,
+                          void* hip_stream, dtb_mlp** out);
+int64_t dtb_mlp_num_params(const dtb_mlp* mlp);
+/* get = 1 copies the parameters out; get = 0 sets them (and resets Adam). */
+dtb_status dtb_mlp_params(dtb_mlp* mlp, float* buf, int get, int on_device);
+/* Y [batch][n_out] = f(X [batch][n_in]); on_device tells where X and Y live. */
+dtb_status dtb_mlp_forward(dtb_mlp* mlp, const float* X, int32_t batch, float* Y, int on_device);
+/* loss = mean over all entries of (f(X) - T)^2; grads [num_params] its
+ * gradient (either output may be NULL).  Loss is written to host memory. */
+dtb_status dtb_mlp_grad(dtb_mlp* mlp, const float* X, const float* T, int32_t batch, float* loss,
+                        float* grads, int on_device);
+/* One Adam step (Kingma & Ba; beta 0.9 / 0.999, eps 1e-8) on that loss. */
+dtb_status dtb_mlp_train_step(dtb_mlp* mlp, const float* X, const float* T, int32_t batch, float lr,
+                              float* loss, int on_device);
+void dtb_mlp_destroy(dtb_mlp* mlp);
+
+/* Indices of the k smallest of n scores (ties: smaller index first; NaN
+ * last), 1 <= k <= n <= 4096, in ascending order of score. */
+dtb_status dtb_topk(const float* score, int32_t n, int32_t k, int32_t* idx, void* hip_stream,
+                    int on_device);
 
 /* Wait for the handle's stream; report asynchronous failures (DTB_ERR_NUMERIC
  * when a non-finite V or gate was produced since the last check). */

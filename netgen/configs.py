@@ -29,7 +29,7 @@ G_DEFAULT = (0.023125, 0.00115625, 0.32, 0.008)
 
 # background drive (mean Poisson count per neuron-step) giving ~7/15/30 Hz on
 # the partition network; fixed by bisection on the mean rate, then frozen
-PARTITION_LAMBDA = {7: 0.25, 15: 0.5, 30: 1.0}
+PARTITION_LAMBDA = {7: 0.27346, 15: 0.56492, 30: 1.52745}
 
 FULL_PARTITION_N = 20_000_000
 

@@ -235,3 +235,12 @@ class OracleNet:
                 states.append(self.state())
         return {"raster": raster, "counts": counts, "ev_rec": ev[:, 0], "ev_bg": ev[:, 1],
                 "states": states, "margins": margins}
+
+
+def bf16_round(w) -> np.ndarray:
+    """Round float32 values to bfloat16 (round to nearest, ties to even) and
+    return them as float32 - the weights a BF16-weight run computes with.
+    Pinned against torch's bfloat16 conversion in the tests."""
+    u = np.ascontiguousarray(w, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (r.astype(np.uint32) << 16).view(np.float32)

@@ -6,5 +6,6 @@ kernels for gfx950.  Importing works without a GPU, but creating a handle
 needs the compiled library and a GPU (no CPU fallback exists)."""
 from ._lib import DtbError, load
 from .net import Net, pack_bits, unpack_bits
+from .surrogate import MLP, topk
 
-__all__ = ["DtbError", "load", "Net", "pack_bits", "unpack_bits"]
+__all__ = ["DtbError", "load", "Net", "MLP", "topk", "pack_bits", "unpack_bits"]

@@ -47,6 +47,8 @@ SIGNATURES = {
     "dtb_bitmap_words": ([_I64], _I64),
     "dtb_create": ([ctypes.POINTER(Desc), _P, ctypes.POINTER(_P)], ctypes.c_int),
     "dtb_step": ([_P, _I32], ctypes.c_int),
+    "dtb_reset": ([_P], ctypes.c_int),
+    "dtb_set_background": ([_P, ctypes.c_double, ctypes.c_float], ctypes.c_int),
     "dtb_force_spikes": ([_P, _P, _I32], ctypes.c_int),
     "dtb_read_spikes": ([_P, _I64, _I64, _P, ctypes.c_int], ctypes.c_int),
     "dtb_read_spike_ids": ([_P, _P, _I64, ctypes.POINTER(_I64)], ctypes.c_int),
@@ -57,6 +59,19 @@ SIGNATURES = {
     "dtb_read_counters": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "dtb_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "dtb_read_timing": ([_P, _P, _P], ctypes.c_int),
+    "dtb_create_batch": ([ctypes.POINTER(Desc), _I32, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "dtb_batch_info": ([_P, _P, _P, _P, _I32], ctypes.c_int),
+    "dtb_set_gains": ([_P, _P, ctypes.c_int], ctypes.c_int),
+    "dtb_run": ([_P, _I32], ctypes.c_int),
+    "dtb_read_bold": ([_P, _P, _P, ctypes.c_int], ctypes.c_int),
+    "dtb_mlp_create": ([_I32, _I32, _I32, _I32, ctypes.c_uint64, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "dtb_mlp_num_params": ([_P], _I64),
+    "dtb_mlp_params": ([_P, _P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "dtb_mlp_forward": ([_P, _P, _I32, _P, ctypes.c_int], ctypes.c_int),
+    "dtb_mlp_grad": ([_P, _P, _P, _I32, _P, _P, ctypes.c_int], ctypes.c_int),
+    "dtb_mlp_train_step": ([_P, _P, _P, _I32, ctypes.c_float, _P, ctypes.c_int], ctypes.c_int),
+    "dtb_mlp_destroy": ([_P], None),
+    "dtb_topk": ([_P, _I32, _I32, _P, _P, ctypes.c_int], ctypes.c_int),
     "dtb_sync": ([_P], ctypes.c_int),
     "dtb_destroy": ([_P], None),
 }

@@ -97,6 +97,10 @@ uint16_t f32_to_bf16_rne(float f) {
 bool finite_f(float x) { return std::isfinite(x); }
 }  // namespace
 
+namespace dtb {
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace dtb
+
 struct dtb_net {
   DeviceNet d;
   hipStream_t stream = nullptr;
@@ -107,6 +111,15 @@ struct dtb_net {
   int64_t force_pending = 0;     // forced steps not yet consumed
   std::vector<int64_t> region_n; // neurons per population
   std::vector<void*> allocs;
+  bool own_stream = false;       // created by the library (caller passed NULL)
+  // members of a batched partition: first row and first population of each
+  std::vector<int64_t> member_row0;
+  std::vector<int32_t> member_region0;
+  std::vector<int32_t> member_id;
+  // captured step sequence replayed by dtb_run
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int32_t graph_steps = 0;
   // kernel timing: event pairs per kernel kind, reused after each read
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[4];
@@ -227,14 +240,20 @@ void parallel_items(int64_t n, const std::function<void(int64_t)>& fn) {
 dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   DeviceNet& d = net->d;
   const int64_t n = s->n;
+  const std::vector<int64_t>& mrow = net->member_row0;
   // 1. bundles of consecutive rows
   const int64_t max_rows = std::min<int64_t>(65536, std::max<int64_t>(64, (n + 511) / 512));
   std::vector<Bundle> bl;
+  size_t mq = 0;  // member of row r
   for (int64_t r = 0; r < n;) {
+    while (mq + 1 < mrow.size() && mrow[mq + 1] <= r) ++mq;
+    const int64_t mend = mq + 1 < mrow.size() ? mrow[mq + 1] : n;  // bundles never cross members
     Bundle b{};
     b.row0 = r;
     b.syn0 = s->row_ptr[r];
-    while (r < n && r - b.row0 < max_rows && s->row_ptr[r + 1] - b.syn0 <= kBundleMaxSyn) ++r;
+    b.member_row0 = mrow[mq];
+    b.member = net->member_id[mq];
+    while (r < mend && r - b.row0 < max_rows && s->row_ptr[r + 1] - b.syn0 <= kBundleMaxSyn) ++r;
     if (r == b.row0)
       return fail(DTB_ERR_UNSUPPORTED, "row " + std::to_string(r) + " has more than " +
                                            std::to_string(kBundleMaxSyn) + " synapses");
@@ -383,15 +402,17 @@ void dtb_destroy(dtb_net* net) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }
+  if (net->graph_exec) (void)hipGraphExecDestroy(net->graph_exec);
+  if (net->graph) (void)hipGraphDestroy(net->graph);
   for (void* p : net->allocs) (void)hipFree(p);
+  if (net->own_stream) (void)hipStreamDestroy(net->stream);
   delete net;
 }
 
-dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
-  if (!out) return fail(DTB_ERR_INVALID, "out is NULL");
-  *out = nullptr;
-  dtb_status st = validate(desc);
-  if (st) return st;
+// Build a handle from a validated description; `net` already carries the
+// member table (one member for a plain partition).
+static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stream, dtb_net** out) {
+  dtb_status st;
   {
     hipError_t e = gather_set_lds_limit();
     if (e != hipSuccess) {
@@ -399,11 +420,20 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
       return fail(DTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
   }
-  dtb_net* net = new (std::nothrow) dtb_net();
-  if (!net) return fail(DTB_ERR_OOM, "host allocation failed");
   net->stream = static_cast<hipStream_t>(hip_stream);
+  if (!net->stream) {
+    // graph capture needs a non-default stream: use a private blocking stream,
+    // which the legacy default stream still orders against
+    hipError_t e = hipStreamCreate(&net->stream);
+    if (e != hipSuccess) {
+      delete net;
+      return fail(DTB_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    net->own_stream = true;
+  }
   net->dt_ms = desc->dt_ms;
   DeviceNet& d = net->d;
+  d.dt_ms = desc->dt_ms;
   d.n = desc->n;
   d.n_pad = round_up(desc->n, kNeuronPad);
   d.words = dtb_bitmap_words(desc->n);
@@ -426,11 +456,13 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
   std::vector<uint32_t> T(kMaxPoisson);
   d.poisson_K = poisson_thresholds(desc->bg_lambda, T.data(), kMaxPoisson);
   if (d.poisson_K < 0) {
-    delete net;
+    dtb_destroy(net);
     return fail(DTB_ERR_INVALID, "bg_lambda needs more than 512 inversion-table entries");
   }
   const int64_t slots = int64_t(d.slots);
-  if ((st = dalloc(net, &d.V, d.n_pad)) || (st = dalloc(net, &d.j, 4 * d.n_pad)) ||
+  d.poisson_cap = std::max(1, d.poisson_K);
+  if ((st = dalloc(net, &d.V, d.n_pad)) || (st = dalloc(net, &d.V0, d.n_pad)) ||
+      (st = dalloc(net, &d.j, 4 * d.n_pad)) ||
       (st = dalloc(net, &d.ref, d.n_pad)) || (st = dalloc(net, &d.ptype, d.n_pad)) ||
       (st = dalloc(net, &d.region, d.n_pad)) ||
       (st = dalloc(net, &d.ptab, d.n_ptypes)) || (st = dalloc(net, &d.gain, 4 * d.n_regions)) ||
@@ -440,7 +472,9 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
       (st = dalloc(net, &d.totals, 4)) || (st = dalloc(net, &d.ids, d.n_pad)) ||
       (st = dalloc(net, &d.id_count, 1)) || (st = dalloc(net, &d.cstatus, d.compact_blocks)) ||
       (st = dalloc(net, &d.cticket, 1)) || (st = dalloc(net, &d.force, (d.rec + 1) * d.words_pad)) ||
-      (st = dalloc(net, &d.bad, 1))) {
+      (st = dalloc(net, &d.bad, 1)) || (st = dalloc(net, &d.step, 2)) ||
+      (st = dalloc(net, &d.inv_nr_dt, d.n_regions)) || (st = dalloc(net, &d.bold, 4 * d.n_regions)) ||
+      (st = dalloc(net, &d.bold_y, d.n_regions))) {
     dtb_destroy(net);
     return st;
   }
@@ -451,7 +485,8 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
            {d.raster, slots * d.words_pad * 4}, {d.counts, slots * d.n_regions * 4},
            {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32}, {d.id_count, 4},
            {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.ptype, d.n_pad * 2},
-           {d.region, d.n_pad * 4}, {d.V, d.n_pad * 4}}) {
+           {d.region, d.n_pad * 4}, {d.V, d.n_pad * 4}, {d.step, 16}, {d.bold, size_t(d.n_regions) * 16},
+           {d.bold_y, size_t(d.n_regions) * 4}}) {
     if (e == hipSuccess) e = zero(pr.first, pr.second);
   }
   if (e != hipSuccess) {
@@ -476,15 +511,168 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
   std::vector<float> gain(4 * d.n_regions, 1.0f);
   net->region_n.assign(d.n_regions, 0);
   for (int64_t i = 0; i < d.n; ++i) net->region_n[desc->region[i]]++;
+  std::vector<float> inr(d.n_regions, 0.f);
+  for (int r = 0; r < d.n_regions; ++r)
+    if (net->region_n[r] > 0) inr[r] = float(1.0 / (double(net->region_n[r]) * double(desc->dt_ms) * 1e-3));
   if ((st = upload(net, d.ptab, pt.data(), pt.size() * sizeof(PType))) ||
       (st = upload(net, d.gain, gain.data(), gain.size() * 4)) ||
+      (st = upload(net, d.inv_nr_dt, inr.data(), inr.size() * 4)) ||
       (st = upload(net, d.poisson, T.data(), std::max(1, d.poisson_K) * 4)) ||
-      (st = upload(net, d.V, desc->V0, d.n * 4)) || (st = upload(net, d.ptype, desc->ptype, d.n * 2)) ||
+      (st = upload(net, d.V, desc->V0, d.n * 4)) || (st = upload(net, d.V0, desc->V0, d.n * 4)) ||
+      (st = upload(net, d.ptype, desc->ptype, d.n * 2)) ||
       (st = upload(net, d.region, desc->region, d.n * 4)) || (st = build_connections(net, desc))) {
     dtb_destroy(net);
     return st;
   }
   *out = net;
+  return DTB_OK;
+}
+
+dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
+  if (!out) return fail(DTB_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  dtb_status st = validate(desc);
+  if (st) return st;
+  dtb_net* net = new (std::nothrow) dtb_net();
+  if (!net) return fail(DTB_ERR_OOM, "host allocation failed");
+  net->member_row0 = {0};
+  net->member_region0 = {0, desc->n_regions};
+  net->member_id = {desc->member};
+  return create_impl(desc, net, hip_stream, out);
+}
+
+dtb_status dtb_create_batch(const dtb_desc* members, int32_t n_members, void* hip_stream, dtb_net** out) {
+  if (!out) return fail(DTB_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!members || n_members < 1) return fail(DTB_ERR_INVALID, "need at least one member");
+  const dtb_desc& m0 = members[0];
+  int64_t n = 0, nnz = 0;
+  int64_t R = 0, P = 0;
+  int32_t D = 0;
+  for (int32_t m = 0; m < n_members; ++m) {
+    const dtb_desc& q = members[m];
+    dtb_status st = validate(&q);
+    if (st) return fail(st, "member " + std::to_string(m) + ": " + g_err);
+    bool same = q.dt_ms == m0.dt_ms && q.bg_w == m0.bg_w && q.bg_lambda == m0.bg_lambda &&
+                q.seed == m0.seed && q.wtype == m0.wtype && q.record_steps == m0.record_steps;
+    for (int u = 0; u < 4; ++u) same = same && q.E[u] == m0.E[u] && q.tau_ms[u] == m0.tau_ms[u];
+    if (!same)
+      return fail(DTB_ERR_UNSUPPORTED, "member " + std::to_string(m) +
+                                           ": E, tau, dt, background, seed, wtype and record_steps must match member 0");
+    n += q.n;
+    nnz += q.nnz;
+    R += q.n_regions;
+    P += q.n_ptypes;
+    D = std::max(D, q.max_delay);
+  }
+  if (n > kMaxNeurons) return fail(DTB_ERR_INVALID, "members exceed the neuron limit together");
+  if (nnz > INT32_MAX) return fail(DTB_ERR_INVALID, "members exceed 2^31-1 synapses together");
+  if (R > INT32_MAX || P > 65536) return fail(DTB_ERR_INVALID, "members exceed the population / type limits");
+  // the batch is one block-diagonal partition
+  std::vector<int64_t> row_ptr(n + 1);
+  std::vector<int32_t> col(nnz), region(n);
+  std::vector<float> w(nnz), V0(n);
+  std::vector<uint8_t> delay(nnz), is_inh(n);
+  std::vector<uint16_t> ptype(n);
+  std::vector<dtb_ptype> ptypes(P);
+  dtb_net* net = new (std::nothrow) dtb_net();
+  if (!net) return fail(DTB_ERR_OOM, "host allocation failed");
+  int64_t i0 = 0, k0 = 0;
+  int32_t r0 = 0, p0 = 0;
+  for (int32_t m = 0; m < n_members; ++m) {
+    const dtb_desc& q = members[m];
+    net->member_row0.push_back(i0);
+    net->member_region0.push_back(r0);
+    net->member_id.push_back(q.member);
+    parallel_for(q.nnz, [&](int64_t a, int64_t b) {
+      for (int64_t k = a; k < b; ++k) {
+        col[k0 + k] = int32_t(q.col[k] + i0);
+        w[k0 + k] = q.w[k];
+        delay[k0 + k] = q.delay[k];
+      }
+    });
+    for (int64_t i = 0; i < q.n; ++i) {
+      row_ptr[i0 + i] = q.row_ptr[i] + k0;
+      region[i0 + i] = q.region[i] + r0;
+      ptype[i0 + i] = uint16_t(q.ptype[i] + p0);
+      is_inh[i0 + i] = q.is_inh[i];
+      V0[i0 + i] = q.V0[i];
+    }
+    for (int32_t p = 0; p < q.n_ptypes; ++p) ptypes[p0 + p] = q.ptypes[p];
+    i0 += q.n;
+    k0 += q.nnz;
+    r0 += q.n_regions;
+    p0 += q.n_ptypes;
+  }
+  row_ptr[n] = nnz;
+  net->member_region0.push_back(r0);
+  dtb_desc all = m0;
+  all.n = n;
+  all.nnz = nnz;
+  all.n_regions = int32_t(R);
+  all.n_ptypes = int32_t(P);
+  all.max_delay = D;
+  all.row_ptr = row_ptr.data();
+  all.col = col.data();
+  all.w = w.data();
+  all.delay = delay.data();
+  all.is_inh = is_inh.data();
+  all.region = region.data();
+  all.ptype = ptype.data();
+  all.ptypes = ptypes.data();
+  all.V0 = V0.data();
+  all.member = 0;
+  return create_impl(&all, net, hip_stream, out);
+}
+
+dtb_status dtb_batch_info(dtb_net* net, int32_t* n_members, int64_t* neuron_offset, int32_t* region_offset,
+                          int32_t cap) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  const int32_t M = int32_t(net->member_row0.size());
+  if (n_members) *n_members = M;
+  for (int32_t m = 0; m <= std::min(M, cap); ++m) {
+    if (neuron_offset) neuron_offset[m] = m < M ? net->member_row0[m] : net->d.n;
+    if (region_offset) region_offset[m] = net->member_region0[m];
+  }
+  return DTB_OK;
+}
+
+dtb_status dtb_set_gains(dtb_net* net, const float* gains, int src_on_device) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!gains) return fail(DTB_ERR_INVALID, "gains is NULL");
+  const size_t bytes = size_t(net->d.n_regions) * 16;
+  if (!src_on_device) {
+    for (int64_t q = 0; q < int64_t(net->d.n_regions) * 4; ++q)
+      if (!(gains[q] >= 0.f) || !finite_f(gains[q]))
+        return fail(DTB_ERR_INVALID, "gain " + std::to_string(q) + " is not finite and >= 0");
+  }
+  hipError_t e = hipMemcpyAsync(net->d.gain, gains, bytes,
+                                src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, net->stream);
+  if (e == hipSuccess && !src_on_device) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy gains");
+  return DTB_OK;
+}
+
+dtb_status dtb_read_bold(dtb_net* net, float* y, float* sfvq, int dst_on_device) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  const DeviceNet& d = net->d;
+  if (sfvq && dst_on_device) return fail(DTB_ERR_UNSUPPORTED, "the hemodynamic state is read into host memory");
+  if (y) {
+    hipError_t e = hipMemcpyAsync(y, d.bold_y, size_t(d.n_regions) * 4,
+                                  dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, net->stream);
+    if (e == hipSuccess && !dst_on_device) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy bold");
+  }
+  if (sfvq) {
+    hipError_t e = hipMemcpyAsync(sfvq, d.bold, size_t(d.n_regions) * 16, hipMemcpyDeviceToHost, net->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy bold state");
+    for (int64_t r = 0; r < d.n_regions; ++r)
+      for (int c = 1; c < 4; ++c) sfvq[4 * r + c] += 1.f;  // stored as deviations from rest
+  }
   return DTB_OK;
 }
 
@@ -528,13 +716,89 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
       net->force_head++;
       net->force_pending--;
     }
-    hipError_t e = timed(net, 0, [&] { return launch_neuron_update(d, t, forced, net->stream); });
-    if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, t, net->stream); });
-    if (e == hipSuccess) e = timed(net, 2, [&] { return launch_gather(d, t, net->stream); });
-    if (e == hipSuccess) e = timed(net, 3, [&] { return launch_finalize(d, t, net->stream); });
+    hipError_t e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
+    if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
+    if (e == hipSuccess) e = timed(net, 2, [&] { return launch_gather(d, net->stream); });
+    if (e == hipSuccess) e = timed(net, 3, [&] { return launch_finalize(d, net->stream); });
     if (e != hipSuccess) return hip_fail(net, e, "kernel launch");
     net->t = t + 1;
   }
+  return DTB_OK;
+}
+
+dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (n_steps < 0) return fail(DTB_ERR_INVALID, "n_steps must be >= 0");
+  if (net->force_pending) return fail(DTB_ERR_STATE, "teacher forcing is pending: use dtb_step");
+  if (n_steps == 0) return DTB_OK;
+  DeviceNet& d = net->d;
+  hipError_t e = hipSuccess;
+  if (!net->graph_exec || net->graph_steps != n_steps) {
+    if (net->graph_exec) (void)hipGraphExecDestroy(net->graph_exec);
+    if (net->graph) (void)hipGraphDestroy(net->graph);
+    net->graph_exec = nullptr;
+    net->graph = nullptr;
+    e = hipStreamBeginCapture(net->stream, hipStreamCaptureModeThreadLocal);
+    for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
+      e = launch_neuron_update(d, nullptr, net->stream);
+      if (e == hipSuccess) e = launch_compact(d, net->stream);
+      if (e == hipSuccess) e = launch_gather(d, net->stream);
+      if (e == hipSuccess) e = launch_finalize(d, net->stream);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(net->stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&net->graph_exec, g, nullptr, nullptr, 0);
+    net->graph = g;
+    if (e != hipSuccess) return hip_fail(net, e, "graph capture of the step sequence");
+    net->graph_steps = n_steps;
+  }
+  e = hipGraphLaunch(net->graph_exec, net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipGraphLaunch");
+  net->t += n_steps;
+  return DTB_OK;
+}
+
+dtb_status dtb_reset(dtb_net* net) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  DeviceNet& d = net->d;
+  const size_t slots = size_t(d.slots);
+  hipError_t e = hipMemcpyAsync(d.V, d.V0, d.n_pad * 4, hipMemcpyDeviceToDevice, net->stream);
+  for (auto pr : std::vector<std::pair<void*, size_t>>{
+           {d.j, 4 * d.n_pad * sizeof(float)}, {d.ref, size_t(d.n_pad)}, {d.raster, slots * d.words_pad * 4},
+           {d.counts, slots * d.n_regions * 4}, {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32},
+           {d.id_count, 4}, {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.step, 16},
+           {d.bold, size_t(d.n_regions) * 16}, {d.bold_y, size_t(d.n_regions) * 4}}) {
+    if (e == hipSuccess) e = hipMemsetAsync(pr.first, 0, pr.second, net->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "reset");
+  net->t = 0;
+  net->force_pending = 0;
+  net->force_head = 0;
+  return DTB_OK;
+}
+
+dtb_status dtb_set_background(dtb_net* net, double bg_lambda, float bg_w) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!(bg_lambda >= 0.0) || !(bg_lambda <= 400.0)) return fail(DTB_ERR_INVALID, "bg_lambda must be in [0, 400]");
+  if (!(bg_w >= 0.f) || !finite_f(bg_w)) return fail(DTB_ERR_INVALID, "bg_w must be finite and >= 0");
+  std::vector<uint32_t> T(kMaxPoisson);
+  const int K = poisson_thresholds(bg_lambda, T.data(), kMaxPoisson);
+  if (K < 0) return fail(DTB_ERR_INVALID, "bg_lambda needs more than 512 inversion-table entries");
+  DeviceNet& d = net->d;
+  if (K > d.poisson_cap) {
+    uint32_t* q = nullptr;
+    if ((st = dalloc(net, &q, K))) return st;
+    d.poisson = q;
+    d.poisson_cap = K;
+  }
+  if (K > 0 && (st = upload(net, d.poisson, T.data(), size_t(K) * 4))) return st;
+  d.poisson_K = K;
+  d.bg_w = bg_w;
   return DTB_OK;
 }
 

@@ -24,11 +24,13 @@ constexpr int kCompactBlock = 256;  // threads of the compaction kernel
 //  * the weight stream, in CSR order (= the fixed summation order), the sign
 //    bit marking an inhibitory presynaptic neuron;
 //  * the lookup stream: the same synapses sorted by (delay, source), cut into
-//    tiles of 64 entries.  Entry = source delta (12 bits, relative to the
-//    previous entry of the tile; the first entry has delta 0) << 20 | position
-//    of the synapse in the bundle's CSR range (20 bits; kInvalidPos = padding).
-//    Tile header = first source of the tile (26 bits) | (delay - 1) << 26.
-constexpr int kTile = 64;
+//    tiles of 256 entries (a wavefront loads one tile as one 16-byte load per
+//    lane: lane l holds entries 4l .. 4l+3).  Entry = source delta (12 bits,
+//    relative to the previous entry of the tile; the first entry has delta 0)
+//    << 20 | position of the synapse in the bundle's CSR range (20 bits;
+//    kInvalidPos = padding).  Tile header = first source of the tile
+//    (26 bits) | (delay - 1) << 26.
+constexpr int kTile = 256;
 constexpr int kPosBits = 20;
 constexpr uint32_t kPosMask = (1u << kPosBits) - 1u;
 constexpr uint32_t kInvalidPos = kPosMask;
@@ -39,6 +41,9 @@ constexpr int kHitWords = int((kBundleMaxSyn + 31) / 32);   // LDS hit bitmap wo
 
 struct Bundle {
   int64_t row0, row1;   // rows [row0, row1)
+  int64_t member_row0;  // first row of the member network the bundle belongs to
+  int32_t member;       // member id (background counter)
+  int32_t pad;
   int64_t syn0;         // CSR index of the bundle's first synapse
   int64_t tile0;        // first tile of the bundle's lookup stream
   int32_t ntiles;       // tiles of the lookup stream
@@ -60,7 +65,7 @@ struct DeviceNet {
   int32_t n_regions = 0, max_delay = 0, n_ptypes = 0, member = 0;
   int32_t wtype = 0, rec = 0;       // rec = record_steps
   int32_t slots = 0;                // spike-bitmap ring slots: max(rec, D) + 1
-  int32_t poisson_K = 0;
+  int32_t poisson_K = 0, poisson_cap = 1;
   int64_t compact_blocks = 0;
   int64_t n_bundles = 0, n_tiles = 0;
   int32_t hit_words = 1;            // LDS words of the largest bundle's hit bitmap
@@ -70,6 +75,7 @@ struct DeviceNet {
   uint64_t seed = 0;
   // neuron state (SoA) and tables
   float* V = nullptr;               // [n_pad]
+  float* V0 = nullptr;              // [n_pad] initial potentials (for dtb_reset)
   float* j = nullptr;               // [4][n_pad]
   uint8_t* ref = nullptr;           // [n_pad]
   uint16_t* ptype = nullptr;        // [n_pad]
@@ -94,13 +100,20 @@ struct DeviceNet {
   uint32_t* cticket = nullptr;      // [1] dynamic block ticket
   uint32_t* force = nullptr;        // [rec + 1][words_pad] pending forced bitmaps
   int32_t* bad = nullptr;           // [1] non-finite flag
+  int64_t* step = nullptr;          // [2] device step counter: t, t mod slots
+  float* inv_nr_dt = nullptr;       // [n_regions] 1 / (neurons of the population * dt in s)
+  float* bold = nullptr;            // [n_regions][4] Balloon-Windkessel state (deviations from rest)
+  float* bold_y = nullptr;          // [n_regions] BOLD signal after the last step
+  float dt_ms = 1.f;
 };
 
 // launchers (dtb_kernels.hip); all enqueue on `s`
-hipError_t launch_neuron_update(const DeviceNet& d, int64_t t, const uint32_t* forced, hipStream_t s);
-hipError_t launch_compact(const DeviceNet& d, int64_t t, hipStream_t s);
-hipError_t launch_gather(const DeviceNet& d, int64_t t, hipStream_t s);
-hipError_t launch_finalize(const DeviceNet& d, int64_t t, hipStream_t s);
+// Every kernel reads the step t from d.step, so a sequence of launches can be
+// captured once and replayed; k_finalize (last of a step) advances it.
+hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s);
+hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
+hipError_t launch_gather(const DeviceNet& d, hipStream_t s);
+hipError_t launch_finalize(const DeviceNet& d, hipStream_t s);
 hipError_t gather_set_lds_limit();
 
 }  // namespace dtb

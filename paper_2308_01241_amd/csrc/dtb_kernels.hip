@@ -19,6 +19,8 @@
 // multiply-add below is written out, so the arithmetic is the source's.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "dtb_internal.h"
 
 namespace dtb {
@@ -59,14 +61,17 @@ __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_
 // ----------------------------------------------------------- neuron update
 // One thread per neuron, 1024 threads (16 wavefronts) per block.
 __global__ __launch_bounds__(1024) void k_neuron_update(
-    int64_t n, int64_t n_pad, int64_t t, float* __restrict__ V, const float* __restrict__ j,
+    int64_t n, int64_t n_pad, const int64_t* __restrict__ step, float* __restrict__ V, const float* __restrict__ j,
     uint8_t* __restrict__ ref, const uint16_t* __restrict__ ptype, const int32_t* __restrict__ region,
     const PType* __restrict__ ptab, const float* __restrict__ gain,
     float E0, float E1, float E2, float E3, const uint32_t* __restrict__ forced,
-    uint32_t* __restrict__ raster_slot, int32_t* __restrict__ counts_slot, uint32_t* __restrict__ cticket,
-    int32_t* __restrict__ bad) {
+    uint32_t* __restrict__ raster, int64_t words_pad, int32_t* __restrict__ counts, int32_t n_regions,
+    uint32_t* __restrict__ cticket, int32_t* __restrict__ bad) {
   __shared__ int s_reg[16];
   __shared__ int s_cnt[16];
+  const int64_t slot = step[1];  // step[0] = t, step[1] = t mod ring slots
+  uint32_t* __restrict__ raster_slot = raster + slot * words_pad;
+  int32_t* __restrict__ counts_slot = counts + slot * n_regions;
   const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool valid = i < n;
@@ -162,12 +167,14 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 }
 
 __global__ __launch_bounds__(kCompactBlock) void k_compact(
-    const uint32_t* __restrict__ bits, int64_t words, int64_t n_blocks, uint32_t epoch,
+    const int64_t* __restrict__ step, const uint32_t* __restrict__ raster, int64_t words, int64_t n_blocks,
     int32_t* __restrict__ ids, int32_t* __restrict__ id_count, uint64_t* __restrict__ status,
     uint32_t* __restrict__ ticket, int64_t* __restrict__ spike_total) {
   __shared__ uint32_t s_bid;
   __shared__ int s_wave[kCompactBlock / 64];
   __shared__ int s_excl;
+  const uint32_t epoch = uint32_t(uint64_t(step[0]) + 1u);  // never 0 for a live step
+  const uint32_t* __restrict__ bits = raster + step[1] * words;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_bid = atomicAdd(ticket, 1u);
   __syncthreads();
@@ -259,28 +266,33 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
 // Workgroups are mapped XCD-aware: the blocks an XCD receives (blockIdx
 // congruent mod 8) take a contiguous range of bundles, so bundles of the
 // same population (same source set) share that XCD's L2.
-constexpr int kUnroll = 8;
+constexpr int kUnroll = 4;  // tiles per wavefront per round (4 KB per wavefront in flight)
 
-__device__ inline uint32_t wave_incl_scan_u32(uint32_t x, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off);
-    if (lane >= off) x += y;
-  }
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP row shifts
+// (within each 16-lane row) and the row broadcasts of lanes 15 and 31.
+__device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x111, 0xF, 0xF, true));   // row_shr:1
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x112, 0xF, 0xF, true));   // row_shr:2
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x114, 0xF, 0xF, true));   // row_shr:4
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x118, 0xF, 0xF, true));   // row_shr:8
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x142, 0xA, 0xF, false));  // row_bcast:15
+  x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x143, 0xC, 0xF, false));  // row_bcast:31
   return x;
 }
 
 template <bool kBF16>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(
-    int64_t n, int64_t n_bundles, int64_t n_pad, int64_t t, int32_t member, uint64_t seed,
+    int64_t n, int64_t n_bundles, int64_t n_pad, const int64_t* __restrict__ step, uint64_t seed,
     const Bundle* __restrict__ bundles, const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
     const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v, const uint32_t* __restrict__ bitmaps,
     int64_t words_pad, int32_t slots, float* __restrict__ j, float a0, float a1, float a2, float a3,
-    float bg_w, const uint32_t* __restrict__ poisson, int K, int64_t* __restrict__ ev_slot,
+    float bg_w, const uint32_t* __restrict__ poisson, int K, int64_t* __restrict__ ev_ring,
     int32_t* __restrict__ bad) {
   extern __shared__ uint32_t s_hits[];
+  const int64_t t = step[0];
+  const int32_t t_mod = int32_t(step[1]);
+  int64_t* __restrict__ ev_slot = ev_ring + int64_t(t_mod) * kStripes * 2;
   __shared__ uint32_t s_ev[kGatherThreads / 64][2];
-  __shared__ int64_t s_slot[32];  // bitmap offset of step t - d1, d1 = delay - 1
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t per = (n_bundles + 7) / 8;
@@ -289,39 +301,68 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
   const Bundle B = bundles[bi];
   const int hw = (B.nsyn + 31) >> 5;
   for (int q = tid; q < hw; q += kGatherThreads) s_hits[q] = 0u;
-  if (tid < 32) {
-    // steps before 0 map to slots not yet written (all-zero bitmaps)
-    const int64_t te = t - tid;
-    s_slot[tid] = (((te % slots) + slots) % slots) * words_pad;
-  }
   __syncthreads();
 
   // ---- phase 1: delivery tests in (delay, source) order
-  const uint32_t* tp = tiles + B.tile0 * kTile + lane;
-  const uint32_t* hp = theads + B.tile0;
   constexpr int kWaves = kGatherThreads / 64;
-  for (int q0 = wave; q0 < B.ntiles; q0 += kWaves * kUnroll) {
-    uint32_t e[kUnroll], h[kUnroll];
+  const int nt = B.ntiles;
+  const uint4* tp = reinterpret_cast<const uint4*>(tiles + B.tile0 * kTile) + lane;
+  const uint32_t* hp = theads + B.tile0;
+  const uint32_t wmax = uint32_t(words_pad - 1);
+  // Software pipeline: the tile loads of round r+1 are issued after the
+  // bitmap loads of round r, so waiting for the bitmap words (loads return in
+  // order) leaves the next tiles in flight.
+  uint4 tv[kUnroll];
+  uint32_t h[kUnroll];
+  bool live[kUnroll];
+  auto fetch = [&](int qb) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int q = q0 + u * kWaves;
-      const bool ok = q < B.ntiles;
-      e[u] = ok ? tp[int64_t(q) * kTile] : kInvalidPos;
-      h[u] = ok ? __builtin_amdgcn_readfirstlane(hp[q]) : 0u;
+      const int q = qb + u * kWaves;
+      live[u] = q < nt;
+      const int qc = live[u] ? q : nt - 1;  // a valid tile; its results are masked out
+      tv[u] = tp[int64_t(qc) * 64];
+      h[u] = __builtin_amdgcn_readfirstlane(hp[qc]);
     }
-    uint32_t src[kUnroll], word[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) src[u] = (h[u] & 0x3FFFFFFu) + wave_incl_scan_u32(e[u] >> kPosBits, lane);
+  };
+  if (wave < nt) fetch(wave);  // nt > 0 inside the loop, so fetch's clamp stays in the bundle
+  for (int q0 = wave; q0 < nt; q0 += kWaves * kUnroll) {
+    uint32_t src[kUnroll][4], word[kUnroll][4], pos[kUnroll][4];
+    bool cur_live[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t base = s_slot[h[u] >> 26];  // spikes of step t - d + 1 arrive now
-      word[u] = (e[u] & kPosMask) != kInvalidPos ? bitmaps[base + (src[u] >> 5)] : 0u;
+      const uint32_t d0 = tv[u].x >> kPosBits, d1 = tv[u].y >> kPosBits, d2 = tv[u].z >> kPosBits,
+                     d3 = tv[u].w >> kPosBits;
+      const uint32_t sum = d0 + d1 + d2 + d3;
+      const uint32_t excl = wave_incl_scan_dpp(sum) - sum;
+      src[u][0] = (h[u] & 0x3FFFFFFu) + excl + d0;
+      src[u][1] = src[u][0] + d1;
+      src[u][2] = src[u][1] + d2;
+      src[u][3] = src[u][2] + d3;
+      pos[u][0] = tv[u].x & kPosMask;
+      pos[u][1] = tv[u].y & kPosMask;
+      pos[u][2] = tv[u].z & kPosMask;
+      pos[u][3] = tv[u].w & kPosMask;
+      cur_live[u] = live[u];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      if ((word[u] >> (src[u] & 31u)) & 1u) {
-        const uint32_t pos = e[u] & kPosMask;
-        atomicOr(&s_hits[pos >> 5], 1u << (pos & 31u));
+      // spikes of step t - d + 1 arrive now; steps before 0 map to unwritten (zero) slots
+      int32_t slot = t_mod - int32_t(h[u] >> 26);
+      if (slot < 0) slot += slots;
+      const uint32_t* bm = bitmaps + int64_t(slot) * words_pad;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) word[u][c] = bm[min(src[u][c] >> 5, wmax)];
+    }
+    fetch(q0 + kWaves * kUnroll);  // unconditional (clamped), so the waits above count exactly
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        // branch-free predicate: every bitmap word is consumed before any branch
+        const uint32_t hit = ((word[u][c] >> (src[u][c] & 31u)) & 1u) & uint32_t(pos[u][c] != kInvalidPos) &
+                             uint32_t(cur_live[u]);
+        if (hit) atomicOr(&s_hits[pos[u][c] >> 5], 1u << (pos[u][c] & 31u));
       }
     }
   }
@@ -363,7 +404,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
     }
     if (r < n) {
       // background Poisson count: Philox4x64-10, key (seed, 0), counter (t, i, member, 0)
-      const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r), uint64_t(member), 0ull, seed, 0ull));
+      // with i the neuron's index inside its member network
+      const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - B.member_row0), uint64_t(B.member),
+                                                    0ull, seed, 0ull));
       const int c = poisson_count(u, poisson, K);
       evb += uint32_t(c);
       dE = __fmaf_rn(float(c), bg_w, dE);
@@ -404,63 +447,108 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
 }
 
 // ---------------------------------------------------------------- finalize
-// Reduce the striped event counters of step t, add them to the totals, and
-// clear the ring slot that step t+1 will fill.
-__global__ __launch_bounds__(64) void k_finalize(int64_t* __restrict__ ev_slot, int64_t* __restrict__ ev_next,
-                                                 int32_t* __restrict__ counts_next, int32_t n_regions,
-                                                 int64_t* __restrict__ totals) {
-  const int lane = threadIdx.x;
-  int64_t r = ev_slot[2 * lane], b = ev_slot[2 * lane + 1];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    r += __shfl_down(r, off);
-    b += __shfl_down(b, off);
-  }
+// Last kernel of a step: reduce the striped event counters of step t into
+// the totals, advance the per-population Balloon-Windkessel hemodynamics
+// by one Euler step with the population rates of step t, clear the ring
+// slot step t+1 will fill, and advance the device step counter.
+//
+// Balloon-Windkessel (Friston et al. 2000; the BOLD model of Sec. V-E) is
+// integrated in FP32 for the deviations from rest x = (s, f-1, v-1, q-1),
+// which keeps the small increments of a 1 ms step representable:
+//   ds = eps u - kappa s - gamma (f-1)        df = s
+//   tau0 dv = f - v^(1/alpha)                 tau0 dq = f E(f)/E0 - v^(1/alpha) q / v
+//   E(f) = 1 - (1-E0)^(1/f),  y = V0 [-k1 (q-1) + k2 (v-q)/v - k3 (v-1)]
+struct BoldParams {
+  float kappa, gamma, tau0, inv_alpha, E0, log1mE0, V0, eps, k1, k2, k3, rate_scale;
+};
+
+__global__ __launch_bounds__(256) void k_finalize(
+    int64_t* __restrict__ step, int32_t slots, int64_t* __restrict__ ev, int32_t* __restrict__ counts,
+    int32_t n_regions, int64_t* __restrict__ totals, const float* __restrict__ inv_nr_dt, float dt_s,
+    float* __restrict__ bold, float* __restrict__ bold_y, BoldParams bp) {
+  const int tid = threadIdx.x;
+  const int64_t t = step[0];
+  const int32_t slot = int32_t(step[1]);
+  const int32_t next = slot + 1 == slots ? 0 : slot + 1;
+  int64_t* ev_slot = ev + int64_t(slot) * kStripes * 2;
+  int64_t* ev_next = ev + int64_t(next) * kStripes * 2;
   __syncthreads();
-  if (lane == 0) {
-    ev_slot[0] = r;
-    ev_slot[1] = b;
-    totals[1] += r;
-    totals[2] += b;
-    totals[3] += 1;
+  if (tid < 64) {
+    int64_t r = ev_slot[2 * tid], b = ev_slot[2 * tid + 1];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      r += __shfl_down(r, off);
+      b += __shfl_down(b, off);
+    }
+    if (tid == 0) {
+      ev_slot[0] = r;
+      ev_slot[1] = b;
+      totals[1] += r;
+      totals[2] += b;
+      totals[3] += 1;
+    }
   }
-  ev_next[2 * lane] = 0;
-  ev_next[2 * lane + 1] = 0;
-  for (int q = lane; q < n_regions; q += 64) counts_next[q] = 0;
+  const int32_t* c = counts + int64_t(slot) * n_regions;
+  for (int q = tid; q < n_regions; q += 256) {
+    const float u = float(c[q]) * inv_nr_dt[q] / bp.rate_scale;  // population rate (Hz) / scale
+    float* x = bold + 4 * q;
+    const float s = x[0], fm = x[1], vm = x[2], qm = x[3];
+    const float f = 1.f + fm, v = 1.f + vm, qq = 1.f + qm;
+    const float vpow = expf(bp.inv_alpha * log1pf(vm));           // v^(1/alpha)
+    const float Ef = 1.f - expf(bp.log1mE0 / f);                   // 1 - (1-E0)^(1/f)
+    const float ds = bp.eps * u - bp.kappa * s - bp.gamma * fm;
+    const float dv = (fm - (vpow - 1.f)) / bp.tau0;
+    const float dq = (f * Ef / bp.E0 - vpow * qq / v) / bp.tau0;
+    const float ns = __fmaf_rn(dt_s, ds, s);
+    const float nf = __fmaf_rn(dt_s, s, fm);
+    const float nv = __fmaf_rn(dt_s, dv, vm);
+    const float nq = __fmaf_rn(dt_s, dq, qm);
+    x[0] = ns;
+    x[1] = nf;
+    x[2] = nv;
+    x[3] = nq;
+    bold_y[q] = bp.V0 * (-bp.k1 * nq + bp.k2 * (nv - nq) / (1.f + nv) - bp.k3 * nv);
+  }
+  if (tid < 64) {
+    ev_next[2 * tid] = 0;
+    ev_next[2 * tid + 1] = 0;
+  }
+  int32_t* cn = counts + int64_t(next) * n_regions;
+  for (int q = tid; q < n_regions; q += 256) cn[q] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    step[0] = t + 1;
+    step[1] = next;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_neuron_update(const DeviceNet& d, int64_t t, const uint32_t* forced, hipStream_t s) {
-  const int64_t slot = t % d.slots;
+hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s) {
   const unsigned grid = unsigned(d.n_pad / 1024);
-  hipLaunchKernelGGL(k_neuron_update, dim3(grid), dim3(1024), 0, s, d.n, d.n_pad, t, d.V, d.j, d.ref,
-                     d.ptype, d.region, d.ptab, d.gain, d.E[0], d.E[1], d.E[2], d.E[3], forced,
-                     d.raster + slot * d.words_pad, d.counts + slot * d.n_regions, d.cticket, d.bad);
+  hipLaunchKernelGGL(k_neuron_update, dim3(grid), dim3(1024), 0, s, d.n, d.n_pad, d.step, d.V, d.j, d.ref,
+                     d.ptype, d.region, d.ptab, d.gain, d.E[0], d.E[1], d.E[2], d.E[3], forced, d.raster,
+                     d.words_pad, d.counts, d.n_regions, d.cticket, d.bad);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const DeviceNet& d, int64_t t, hipStream_t s) {
-  const int64_t slot = t % d.slots;
-  hipLaunchKernelGGL(k_compact, dim3(unsigned(d.compact_blocks)), dim3(kCompactBlock), 0, s,
-                     d.raster + slot * d.words_pad, d.words_pad, d.compact_blocks,
-                     uint32_t(uint64_t(t) + 1u), d.ids, d.id_count, d.cstatus, d.cticket, d.totals);
+hipError_t launch_compact(const DeviceNet& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(unsigned(d.compact_blocks)), dim3(kCompactBlock), 0, s, d.step, d.raster,
+                     d.words_pad, d.compact_blocks, d.ids, d.id_count, d.cstatus, d.cticket, d.totals);
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const DeviceNet& d, int64_t t, hipStream_t s) {
-  const int64_t slot = t % d.slots;
+hipError_t launch_gather(const DeviceNet& d, hipStream_t s) {
   const unsigned grid = unsigned((d.n_bundles + 7) / 8 * 8);
   const size_t lds = size_t(d.hit_words) * 4;
-  int64_t* evs = d.ev + slot * kStripes * 2;
   if (d.wtype == DTB_W_BF16)
-    hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad, t,
-                       d.member, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
-                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, evs, d.bad);
+    hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
+                       d.step, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
+                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
   else
-    hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad, t,
-                       d.member, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
-                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, evs, d.bad);
+    hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
+                       d.step, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
+                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
   return hipGetLastError();
 }
 
@@ -473,10 +561,13 @@ hipError_t gather_set_lds_limit() {
   return e;
 }
 
-hipError_t launch_finalize(const DeviceNet& d, int64_t t, hipStream_t s) {
-  const int64_t slot = t % d.slots, next = (t + 1) % d.slots;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, d.ev + slot * kStripes * 2,
-                     d.ev + next * kStripes * 2, d.counts + next * d.n_regions, d.n_regions, d.totals);
+
+hipError_t launch_finalize(const DeviceNet& d, hipStream_t s) {
+  const float E0 = 0.34f;
+  BoldParams bp{0.65f, 0.41f, 0.98f, 1.f / 0.32f, E0, std::log(1.f - E0), 0.02f, 0.5f,
+                7.f * E0, 2.f, 2.f * E0 - 0.2f, 100.f};
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, d.step, d.slots, d.ev, d.counts, d.n_regions,
+                     d.totals, d.inv_nr_dt, d.dt_ms * 1e-3f, d.bold, d.bold_y, bp);
   return hipGetLastError();
 }
 

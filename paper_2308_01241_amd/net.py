@@ -30,56 +30,41 @@ class Net:
     tau_ms, dt_ms, bg_lambda, bg_w, seed, member).
     """
 
-    def __init__(self, network, wtype: str = "f32", record_steps: int = 1024, stream=None):
+    def __init__(self, network, wtype: str = "f32", record_steps: int = 1024, stream=None, _members=None):
         lib = load()
         self._lib = lib
-        nw = network
-        keep = []
-
-        def arr(a, dt):
-            a = np.ascontiguousarray(a, dtype=dt)
-            keep.append(a)
-            return _ptr(a)
-
-        d = Desc()
-        d.n = int(nw.n)
-        d.n_regions = int(nw.n_regions)
-        d.max_delay = int(nw.max_delay)
-        pt = np.ascontiguousarray(nw.ptypes, dtype=np.float32).reshape(-1, 11)
-        d.n_ptypes = int(pt.shape[0])
-        d.member = int(getattr(nw, "member", 0))
-        d.nnz = int(nw.row_ptr[-1])
-        d.row_ptr = arr(nw.row_ptr, np.int64)
-        d.col = arr(nw.col, np.int32)
-        d.w = arr(nw.w, np.float32)
-        d.delay = arr(nw.delay, np.uint8)
-        d.is_inh = arr(nw.is_inh, np.uint8)
-        d.region = arr(nw.region, np.int32)
-        d.ptype = arr(nw.ptype, np.uint16)
-        ptypes = (Ptype * d.n_ptypes)()
-        for p in range(d.n_ptypes):
-            r = pt[p]
-            ptypes[p] = Ptype(*[float(x) for x in r[:7]], (ctypes.c_float * 4)(*[float(x) for x in r[7:11]]))
-        d.ptypes = ctypes.cast(ptypes, ctypes.c_void_p)
-        d.V0 = arr(nw.V0, np.float32)
-        for u in range(4):
-            d.E[u] = float(nw.E[u])
-            d.tau_ms[u] = float(nw.tau_ms[u])
-        d.dt_ms = float(nw.dt_ms)
-        d.bg_w = float(nw.bg_w)
-        d.bg_lambda = float(nw.bg_lambda)
-        d.seed = int(nw.seed)
-        d.wtype = {"f32": W_F32, "bf16": W_BF16}[wtype]
-        d.record_steps = int(record_steps)
         h = ctypes.c_void_p()
-        check(lib.dtb_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)))
+        if _members is None:
+            d, keep = _make_desc(network, wtype, record_steps)
+            check(lib.dtb_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)))
+        else:
+            descs = (Desc * len(_members))()
+            keep = []
+            for m, nw in enumerate(_members):
+                d, k = _make_desc(nw, wtype, record_steps)
+                descs[m] = d
+                keep.append(k)
+            check(lib.dtb_create_batch(descs, len(_members), _stream_handle(stream), ctypes.byref(h)))
+            del descs
+        del keep
         self._h = h
-        self.n = d.n
-        self.n_regions = d.n_regions
-        self.words = int(lib.dtb_bitmap_words(d.n))
+        nm = ctypes.c_int32(0)
+        check(lib.dtb_batch_info(h, ctypes.byref(nm), None, None, 0))
+        self.n_members = nm.value
+        noff = np.zeros(nm.value + 1, dtype=np.int64)
+        roff = np.zeros(nm.value + 1, dtype=np.int32)
+        check(lib.dtb_batch_info(h, None, _ptr(noff), _ptr(roff), nm.value))
+        self.neuron_offset, self.region_offset = noff, roff
+        self.n = int(noff[-1])
+        self.n_regions = int(roff[-1])
+        self.words = int(lib.dtb_bitmap_words(self.n))
         self.record_steps = int(record_steps)
         self.t = 0
-        del keep, ptypes
+
+    @classmethod
+    def batch(cls, members, wtype: str = "f32", record_steps: int = 1024, stream=None) -> "Net":
+        """One handle advancing several independent networks together."""
+        return cls(None, wtype=wtype, record_steps=record_steps, stream=stream, _members=list(members))
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -94,6 +79,28 @@ class Net:
     def step(self, n_steps: int = 1) -> None:
         check(self._lib.dtb_step(self._h, int(n_steps)))
         self.t += int(n_steps)
+
+    def run(self, n_steps: int) -> None:
+        """n_steps steps as one captured HIP graph (replayed on later calls)."""
+        check(self._lib.dtb_run(self._h, int(n_steps)))
+        self.t += int(n_steps)
+
+    def set_gains(self, gains) -> None:
+        g = np.ascontiguousarray(gains, dtype=np.float32).reshape(self.n_regions, 4)
+        check(self._lib.dtb_set_gains(self._h, _ptr(g), 0))
+
+    def bold(self, state: bool = False):
+        y = np.zeros(self.n_regions, dtype=np.float32)
+        st = np.zeros((self.n_regions, 4), dtype=np.float32) if state else None
+        check(self._lib.dtb_read_bold(self._h, _ptr(y), None if st is None else _ptr(st), 0))
+        return (y, st) if state else y
+
+    def reset(self) -> None:
+        check(self._lib.dtb_reset(self._h))
+        self.t = 0
+
+    def set_background(self, bg_lambda: float, bg_w: float) -> None:
+        check(self._lib.dtb_set_background(self._h, float(bg_lambda), float(bg_w)))
 
     def force(self, raster: np.ndarray) -> None:
         """Queue teacher-forced spikes: raster [n_steps, n] of 0/1."""
@@ -161,6 +168,48 @@ class Net:
         v = [ctypes.c_int64(0) for _ in range(4)]
         check(self._lib.dtb_read_counters(self._h, *[ctypes.byref(x) for x in v]))
         return {"steps": v[0].value, "spikes": v[1].value, "ev_rec": v[2].value, "ev_bg": v[3].value}
+
+
+def _make_desc(nw, wtype, record_steps):
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return _ptr(a)
+
+    d = Desc()
+    d.n = int(nw.n)
+    d.n_regions = int(nw.n_regions)
+    d.max_delay = int(nw.max_delay)
+    pt = np.ascontiguousarray(nw.ptypes, dtype=np.float32).reshape(-1, 11)
+    d.n_ptypes = int(pt.shape[0])
+    d.member = int(getattr(nw, "member", 0))
+    d.nnz = int(nw.row_ptr[-1])
+    d.row_ptr = arr(nw.row_ptr, np.int64)
+    d.col = arr(nw.col, np.int32)
+    d.w = arr(nw.w, np.float32)
+    d.delay = arr(nw.delay, np.uint8)
+    d.is_inh = arr(nw.is_inh, np.uint8)
+    d.region = arr(nw.region, np.int32)
+    d.ptype = arr(nw.ptype, np.uint16)
+    ptypes = (Ptype * d.n_ptypes)()
+    for p in range(d.n_ptypes):
+        r = pt[p]
+        ptypes[p] = Ptype(*[float(x) for x in r[:7]], (ctypes.c_float * 4)(*[float(x) for x in r[7:11]]))
+    keep.append(ptypes)
+    d.ptypes = ctypes.cast(ptypes, ctypes.c_void_p)
+    d.V0 = arr(nw.V0, np.float32)
+    for u in range(4):
+        d.E[u] = float(nw.E[u])
+        d.tau_ms[u] = float(nw.tau_ms[u])
+    d.dt_ms = float(nw.dt_ms)
+    d.bg_w = float(nw.bg_w)
+    d.bg_lambda = float(nw.bg_lambda)
+    d.seed = int(nw.seed)
+    d.wtype = {"f32": W_F32, "bf16": W_BF16}[wtype]
+    d.record_steps = int(record_steps)
+    return d, keep
 
 
 def pack_bits(raster: np.ndarray, words: int) -> np.ndarray:

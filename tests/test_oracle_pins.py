@@ -247,3 +247,12 @@ def test_gain_scales_conductances():
     ref = brute.run(net, 60, gain=gain)
     np.testing.assert_array_equal(a["raster"], b["raster"])
     np.testing.assert_array_equal(a["raster"], ref["raster"])
+
+
+def test_bf16_round_matches_torch():
+    import torch
+    rng = np.random.default_rng(3)
+    w = np.concatenate([rng.lognormal(-1, 0.5, 10000).astype(np.float32),
+                        np.array([1.0, 1.00390625, 1.005859375, 3.0e-39, 0.0], dtype=np.float32)])
+    ref = torch.from_numpy(w).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(oracle.bf16_round(w), ref)
