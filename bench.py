@@ -26,6 +26,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "synaptic events/s & realtime factor, plain vs BF16/batched; surrogate err"
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "gather_traffic_partition20M_7hz.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2308_01241_amd", "csrc", "dtb_kernels.hip")
+
+
+def measured_traffic(kernel: str = "k_gather"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since those counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_JSON) as f:
+            tj = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if tj.get("kernel_source_sha256") != h or kernel not in tj.get("per_launch", {}):
+        return None
+    t = tj["per_launch"][kernel]
+    return float(t["read_bytes"] + t["write_bytes"])
 HBM_PEAK_GBS = 8000.0
 
 
@@ -40,13 +59,14 @@ def gather_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) 
     return 5.0 * nnz + w_bytes * events + 32.0 * n + n * (max_delay + 1) / 8.0
 
 
-def run_rate(net, rate, lam, steps, warmup, wtype):
+def run_rate(net, rate, lam, steps, warmup, wtype, bundle_syn=0):
     import torch
     import paper_2308_01241_amd as dtb
 
     net.bg_lambda = lam
     t0 = time.time()
-    g = dtb.Net(net, wtype=wtype, record_steps=max(steps, 16), stream=torch.cuda.current_stream())
+    g = dtb.Net(net, wtype=wtype, record_steps=max(steps, 16), stream=torch.cuda.current_stream(),
+                bundle_syn=bundle_syn)
     torch.cuda.synchronize()
     log(f"[bench] {rate} Hz: created in {time.time() - t0:.1f}s; warmup {warmup}")
     g.step(warmup)
@@ -162,6 +182,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", action="store_true", help="bisect the background drive per target rate")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a plain copy of known size")
+    ap.add_argument("--autotune", action="store_true", help="search the gather launch shape, store it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's partition; --gpus {args.gpus} is not supported "
@@ -184,9 +205,20 @@ def main():
     if args.tune:
         print(json.dumps({"tuned": tune_rates(net, rates), "n": net.n}), flush=True)
         return
+    from paper_2308_01241_amd import autotune
+    key = autotune.shape_key(net.n, net.nnz, 1, args.wtype, net.max_delay)
+    if args.autotune:
+        net.bg_lambda = netgen.PARTITION_LAMBDA[rates[0]]
+        best, res = autotune.tune(
+            lambda c: dtb.Net(net, wtype=args.wtype, record_steps=64, stream=torch.cuda.current_stream(),
+                              bundle_syn=c), key, log=log)
+        print(json.dumps({"autotune": key, "best": best, "ms_per_step": res}), flush=True)
+        return
+    bsyn = autotune.lookup(net.n, net.nnz, 1, args.wtype, net.max_delay)
+    log(f"[bench] gather bundle size: {bsyn or 'default'}")
     res = {}
     for r in rates:
-        res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype)
+        res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype, bsyn)
         log(f"[bench] {r} Hz: {json.dumps({k: v for k, v in res[r].items() if k != 'kernels'})}")
         log(f"[bench] {r} Hz kernels: {res[r]['kernels']}")
     head = res[rates[0]]
@@ -197,7 +229,7 @@ def main():
     B = gather_bytes(net.nnz, net.n, net.max_delay, ev_step, wb)
     achieved = B / (g_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_gather",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_gather",
             "algorithmic_bytes_per_launch": B, "avg_launch_ms": g_ms}
     cpu = None
     if not args.no_cpu:
@@ -211,7 +243,7 @@ def main():
            "config": {"workload": f"partition_net: {net.n} neurons, {net.nnz} synapses, 90 regions, "
                                   f"in-degree 100, delays 1-{net.max_delay}, dt 1 ms, {rates[0]} Hz",
                       "global_batch": 1, "seq_len": args.steps, "parallelism": "single-gpu"},
-           "rtf": head["rtf"], "roofline": roof, "cpu_baseline": cpu,
+           "rtf": head["rtf"], "roofline": roof, "cpu_baseline": cpu, "gather_bundle_syn": bsyn or None,
            "rates": {str(r): {k: v for k, v in res[r].items() if k != "kernels"} for r in rates},
            "kernels_ms_per_step": {k: v["ms"] / max(1, v["launches"]) for k, v in head["kernels"].items()}}
     print(json.dumps(out), flush=True)

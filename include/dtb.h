@@ -99,6 +99,9 @@ typedef struct dtb_desc {
   uint64_t seed;             /* background seed: Philox4x64-10 key (seed, 0) */
   int32_t wtype;             /* dtb_wtype: storage precision of w (accumulation is FP32) */
   int32_t record_steps;      /* steps of raster / counts history kept on device, >= 1 */
+  int32_t gather_bundle_syn; /* launch shape of the gather: most synapses per workgroup
+                                (4096 .. 2^20-1; 0 = 2^20-1); a tuning knob, results do
+                                not depend on it */
 } dtb_desc;
 
 /* ------------------------------------------------------------ library */
@@ -197,11 +200,12 @@ dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches);
  * disjoint node sets, Sec. V-E).  The members become one block-diagonal
  * partition: member m's neurons, populations and property-table rows follow
  * member m-1's.  Each member keeps its own background counter (t, i, member,
- * 0), i its own neuron index and member its desc's `member` field, so a
- * member advanced in a batch computes exactly what it computes alone.
- * Members may differ in size, connectivity, populations, property table and
- * V0; E, tau_ms, dt_ms, bg_lambda, bg_w, seed, wtype and record_steps must be
- * equal (DTB_ERR_UNSUPPORTED otherwise).  Inputs are copied. */
+ * 0) under its own seed, i its own neuron index and member its desc's
+ * `member` field, so a member advanced in a batch computes exactly what it
+ * computes alone.  Members may differ in size, connectivity, populations,
+ * property table, V0 and seed; E, tau_ms, dt_ms, bg_lambda, bg_w, wtype and
+ * record_steps must be equal (DTB_ERR_UNSUPPORTED otherwise).  Inputs are
+ * copied. */
 dtb_status dtb_create_batch(const dtb_desc* members, int32_t n_members, void* hip_stream,
                             dtb_net** out);
 

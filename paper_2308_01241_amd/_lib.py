@@ -35,7 +35,8 @@ class Desc(ctypes.Structure):
                 ("ptype", ctypes.c_void_p), ("ptypes", ctypes.c_void_p), ("V0", ctypes.c_void_p),
                 ("E", ctypes.c_float * 4), ("tau_ms", ctypes.c_float * 4), ("dt_ms", ctypes.c_float),
                 ("bg_w", ctypes.c_float), ("bg_lambda", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("wtype", ctypes.c_int32), ("record_steps", ctypes.c_int32)]
+                ("wtype", ctypes.c_int32), ("record_steps", ctypes.c_int32),
+                ("gather_bundle_syn", ctypes.c_int32)]
 
 
 # every symbol include/dtb.h declares, with its ctypes signature

@@ -116,6 +116,7 @@ struct dtb_net {
   std::vector<int64_t> member_row0;
   std::vector<int32_t> member_region0;
   std::vector<int32_t> member_id;
+  std::vector<uint64_t> member_seed;
   // captured step sequence replayed by dtb_run
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -169,6 +170,8 @@ dtb_status validate(const dtb_desc* s) {
     return fail(DTB_ERR_INVALID, "col/w/delay must be non-NULL when nnz > 0");
   if (s->wtype != DTB_W_F32 && s->wtype != DTB_W_BF16) return fail(DTB_ERR_INVALID, "unknown wtype");
   if (s->record_steps < 1) return fail(DTB_ERR_INVALID, "record_steps must be >= 1");
+  if (s->gather_bundle_syn != 0 && (s->gather_bundle_syn < 4096 || s->gather_bundle_syn > kBundleMaxSyn))
+    return fail(DTB_ERR_INVALID, "gather_bundle_syn must be 0 or in [4096, 2^20-1]");
   if (!(s->dt_ms > 0.f) || !finite_f(s->dt_ms)) return fail(DTB_ERR_INVALID, "dt_ms must be finite and > 0");
   for (int u = 0; u < 4; ++u) {
     if (!(s->tau_ms[u] > 0.f) || !finite_f(s->tau_ms[u]))
@@ -243,6 +246,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   const std::vector<int64_t>& mrow = net->member_row0;
   // 1. bundles of consecutive rows
   const int64_t max_rows = std::min<int64_t>(65536, std::max<int64_t>(64, (n + 511) / 512));
+  const int64_t max_syn = s->gather_bundle_syn ? int64_t(s->gather_bundle_syn) : kBundleMaxSyn;
   std::vector<Bundle> bl;
   size_t mq = 0;  // member of row r
   for (int64_t r = 0; r < n;) {
@@ -253,10 +257,11 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     b.syn0 = s->row_ptr[r];
     b.member_row0 = mrow[mq];
     b.member = net->member_id[mq];
-    while (r < mend && r - b.row0 < max_rows && s->row_ptr[r + 1] - b.syn0 <= kBundleMaxSyn) ++r;
+    b.seed = net->member_seed[mq];
+    while (r < mend && r - b.row0 < max_rows && s->row_ptr[r + 1] - b.syn0 <= max_syn) ++r;
     if (r == b.row0)
       return fail(DTB_ERR_UNSUPPORTED, "row " + std::to_string(r) + " has more than " +
-                                           std::to_string(kBundleMaxSyn) + " synapses");
+                                           std::to_string(max_syn) + " synapses (gather_bundle_syn)");
     b.row1 = r;
     b.nsyn = int32_t(s->row_ptr[r] - b.syn0);
     bl.push_back(b);
@@ -538,6 +543,7 @@ dtb_status dtb_create(const dtb_desc* desc, void* hip_stream, dtb_net** out) {
   net->member_row0 = {0};
   net->member_region0 = {0, desc->n_regions};
   net->member_id = {desc->member};
+  net->member_seed = {desc->seed};
   return create_impl(desc, net, hip_stream, out);
 }
 
@@ -554,11 +560,11 @@ dtb_status dtb_create_batch(const dtb_desc* members, int32_t n_members, void* hi
     dtb_status st = validate(&q);
     if (st) return fail(st, "member " + std::to_string(m) + ": " + g_err);
     bool same = q.dt_ms == m0.dt_ms && q.bg_w == m0.bg_w && q.bg_lambda == m0.bg_lambda &&
-                q.seed == m0.seed && q.wtype == m0.wtype && q.record_steps == m0.record_steps;
+                q.wtype == m0.wtype && q.record_steps == m0.record_steps;
     for (int u = 0; u < 4; ++u) same = same && q.E[u] == m0.E[u] && q.tau_ms[u] == m0.tau_ms[u];
     if (!same)
       return fail(DTB_ERR_UNSUPPORTED, "member " + std::to_string(m) +
-                                           ": E, tau, dt, background, seed, wtype and record_steps must match member 0");
+                                           ": E, tau, dt, background rate and weight, wtype and record_steps must match member 0");
     n += q.n;
     nnz += q.nnz;
     R += q.n_regions;
@@ -584,6 +590,7 @@ dtb_status dtb_create_batch(const dtb_desc* members, int32_t n_members, void* hi
     net->member_row0.push_back(i0);
     net->member_region0.push_back(r0);
     net->member_id.push_back(q.member);
+    net->member_seed.push_back(q.seed);
     parallel_for(q.nnz, [&](int64_t a, int64_t b) {
       for (int64_t k = a; k < b; ++k) {
         col[k0 + k] = int32_t(q.col[k] + i0);

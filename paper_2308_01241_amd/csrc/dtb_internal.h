@@ -42,6 +42,7 @@ constexpr int kHitWords = int((kBundleMaxSyn + 31) / 32);   // LDS hit bitmap wo
 struct Bundle {
   int64_t row0, row1;   // rows [row0, row1)
   int64_t member_row0;  // first row of the member network the bundle belongs to
+  uint64_t seed;        // the member's background seed (Philox key)
   int32_t member;       // member id (background counter)
   int32_t pad;
   int64_t syn0;         // CSR index of the bundle's first synapse

@@ -282,7 +282,7 @@ __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
 
 template <bool kBF16>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(
-    int64_t n, int64_t n_bundles, int64_t n_pad, const int64_t* __restrict__ step, uint64_t seed,
+    int64_t n, int64_t n_bundles, int64_t n_pad, const int64_t* __restrict__ step,
     const Bundle* __restrict__ bundles, const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
     const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v, const uint32_t* __restrict__ bitmaps,
     int64_t words_pad, int32_t slots, float* __restrict__ j, float a0, float a1, float a2, float a3,
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
       // background Poisson count: Philox4x64-10, key (seed, 0), counter (t, i, member, 0)
       // with i the neuron's index inside its member network
       const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - B.member_row0), uint64_t(B.member),
-                                                    0ull, seed, 0ull));
+                                                    0ull, B.seed, 0ull));
       const int c = poisson_count(u, poisson, K);
       evb += uint32_t(c);
       dE = __fmaf_rn(float(c), bg_w, dE);
@@ -543,11 +543,11 @@ hipError_t launch_gather(const DeviceNet& d, hipStream_t s) {
   const size_t lds = size_t(d.hit_words) * 4;
   if (d.wtype == DTB_W_BF16)
     hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
-                       d.step, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
+                       d.step, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
                        d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
   else
     hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
-                       d.step, d.seed, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
+                       d.step, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
                        d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
   return hipGetLastError();
 }

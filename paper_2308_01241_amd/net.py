@@ -30,18 +30,19 @@ class Net:
     tau_ms, dt_ms, bg_lambda, bg_w, seed, member).
     """
 
-    def __init__(self, network, wtype: str = "f32", record_steps: int = 1024, stream=None, _members=None):
+    def __init__(self, network, wtype: str = "f32", record_steps: int = 1024, stream=None, _members=None,
+                 bundle_syn: int = 0):
         lib = load()
         self._lib = lib
         h = ctypes.c_void_p()
         if _members is None:
-            d, keep = _make_desc(network, wtype, record_steps)
+            d, keep = _make_desc(network, wtype, record_steps, bundle_syn)
             check(lib.dtb_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)))
         else:
             descs = (Desc * len(_members))()
             keep = []
             for m, nw in enumerate(_members):
-                d, k = _make_desc(nw, wtype, record_steps)
+                d, k = _make_desc(nw, wtype, record_steps, bundle_syn)
                 descs[m] = d
                 keep.append(k)
             check(lib.dtb_create_batch(descs, len(_members), _stream_handle(stream), ctypes.byref(h)))
@@ -62,9 +63,10 @@ class Net:
         self.t = 0
 
     @classmethod
-    def batch(cls, members, wtype: str = "f32", record_steps: int = 1024, stream=None) -> "Net":
+    def batch(cls, members, wtype: str = "f32", record_steps: int = 1024, stream=None, bundle_syn: int = 0) -> "Net":
         """One handle advancing several independent networks together."""
-        return cls(None, wtype=wtype, record_steps=record_steps, stream=stream, _members=list(members))
+        return cls(None, wtype=wtype, record_steps=record_steps, stream=stream, _members=list(members),
+                   bundle_syn=bundle_syn)
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -170,7 +172,7 @@ class Net:
         return {"steps": v[0].value, "spikes": v[1].value, "ev_rec": v[2].value, "ev_bg": v[3].value}
 
 
-def _make_desc(nw, wtype, record_steps):
+def _make_desc(nw, wtype, record_steps, bundle_syn=0):
     keep = []
 
     def arr(a, dt):
@@ -209,6 +211,7 @@ def _make_desc(nw, wtype, record_steps):
     d.seed = int(nw.seed)
     d.wtype = {"f32": W_F32, "bf16": W_BF16}[wtype]
     d.record_steps = int(record_steps)
+    d.gather_bundle_syn = int(bundle_syn)
     return d, keep
 
 

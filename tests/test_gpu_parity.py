@@ -257,21 +257,31 @@ def test_bf16_weights_match_reference_on_rounded_weights(dtb):
         assert _state_close(g.state(f), o.get(f), floor).all(), f
 
 
-def test_bf16_free_run_region_rates_within_2_percent(dtb):
-    """Region firing rates of the BF16-weight run over 1 s of biological time
-    stay within 2 % of the FP32-weight run (pooled over 8 seeds)."""
-    tot32 = np.zeros(2)
-    tot16 = np.zeros(2)
-    for s in range(1, 9):
-        net = netgen.make_network(netgen.small_net(seed_offset=s))
-        a = _gpu(dtb, net)
-        b = _gpu(dtb, net, wtype="bf16")
-        a.step(1000)
-        b.step(1000)
-        tot32 += a.region_counts(0, 1000).sum(axis=0)
-        tot16 += b.region_counts(0, 1000).sum(axis=0)
-    rel = np.abs(tot16 - tot32) / tot32
-    assert np.all(rel < 0.02), rel
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("rate", [7, 15, 30])
+def test_bf16_rates_within_2_percent_on_the_slice(dtb, rate):
+    """Precision form on the 200k-neuron slice: the network-wide rate of the
+    BF16-weight run over steps [200, 1000) is within 2 % of the FP32 run, and
+    its per-population differences are no larger than twice those between
+    two FP32 realizations (V0 shifted by 1 uV), the noise floor of a 0.8 s
+    population rate."""
+    lam = netgen.PARTITION_LAMBDA[rate]
+    net = netgen.make_network(netgen.slice_spec(rate_hz=rate, bg_lambda=lam))
+    alt = netgen.make_network(netgen.slice_spec(rate_hz=rate, bg_lambda=lam))
+    alt.V0 = (alt.V0 + np.float32(1e-3)).astype(np.float32)
+    counts = {}
+    for tag, nw, wt in (("f32", net, "f32"), ("bf16", net, "bf16"), ("f32b", alt, "f32")):
+        g = _gpu(dtb, nw, wtype=wt, record_steps=1000)
+        g.step(1000)
+        counts[tag] = g.region_counts(200, 1000).sum(axis=0).astype(np.float64)
+        g.close()
+    a, b, c = counts["f32"], counts["bf16"], counts["f32b"]
+    assert abs(b.sum() - a.sum()) / a.sum() < 0.02
+    sizes = net.region_sizes()
+    w = sizes / sizes.sum()
+    d16 = (np.abs(b - a) / np.maximum(a, 1) * w).sum()
+    d32 = (np.abs(c - a) / np.maximum(a, 1) * w).sum()
+    assert d16 <= 2.0 * d32 + 0.005, (d16, d32)
 
 
 @pytest.mark.timeout(600)
