@@ -369,58 +369,89 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
   __syncthreads();
 
   // ---- phase 2: sums in CSR order, background, gates
+  // Rows are software-pipelined: the next row's CSR bounds and gates are
+  // loaded while the current row is summed.  A row's hit positions are
+  // collected first (up to kHitBatch at a time) so their weight loads issue
+  // together; the adds then run in ascending position, the row's CSR order.
+  constexpr int kHitBatch = 8;
   uint32_t ev = 0, evb = 0;
   const float* wf = reinterpret_cast<const float*>(wts_v);
   const uint16_t* wb = reinterpret_cast<const uint16_t*>(wts_v);
-  for (int64_t r = B.row0 + tid; r < B.row1; r += kGatherThreads) {
-    const int64_t k0 = row_ptr[r] - B.syn0, k1 = row_ptr[r + 1] - B.syn0;
+  int64_t r = B.row0 + tid;
+  int64_t k0n = 0, k1n = 0;
+  float jn0 = 0.f, jn1 = 0.f, jn2 = 0.f, jn3 = 0.f;
+  if (r < B.row1) {
+    k0n = row_ptr[r] - B.syn0;
+    k1n = row_ptr[r + 1] - B.syn0;
+    jn0 = j[r];
+    jn1 = j[n_pad + r];
+    jn2 = j[2 * n_pad + r];
+    jn3 = j[3 * n_pad + r];
+  }
+  for (; r < B.row1; r += kGatherThreads) {
+    const int k0 = int(k0n), k1 = int(k1n);
+    const float j0 = jn0, j1 = jn1, j2 = jn2, j3 = jn3;
+    const int64_t rn = r + kGatherThreads;
+    if (rn < B.row1) {
+      k0n = row_ptr[rn] - B.syn0;
+      k1n = row_ptr[rn + 1] - B.syn0;
+      jn0 = j[rn];
+      jn1 = j[n_pad + rn];
+      jn2 = j[2 * n_pad + rn];
+      jn3 = j[3 * n_pad + rn];
+    }
+    // background Poisson count: Philox4x64-10, key (seed, 0), counter (t, i, member, 0)
+    // with i the neuron's index inside its member network
+    const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - B.member_row0), uint64_t(B.member),
+                                                  0ull, B.seed, 0ull));
     float dE = 0.f, dI = 0.f;
     if (k1 > k0) {
-      const int w0 = int(k0 >> 5), w1 = int((k1 - 1) >> 5);
-      for (int w = w0; w <= w1; ++w) {
-        uint32_t bits = s_hits[w];
-        if (w == w0) bits &= ~0u << (k0 & 31);
-        if (w == w1) bits &= ~0u >> (31 - ((k1 - 1) & 31));
-        while (bits) {
-          const int bb = __ffs(bits) - 1;
-          bits &= bits - 1u;
-          const int64_t p = B.syn0 + int64_t(w) * 32 + bb;
-          uint32_t u;
-          float wv;
-          if (kBF16) {
-            const uint16_t x = wb[p];
-            u = x >> 15;
-            wv = bf16_to_f32(uint16_t(x & 0x7FFFu));
+      int w = k0 >> 5;
+      const int w1 = (k1 - 1) >> 5;
+      uint32_t bits = s_hits[w] & (~0u << (k0 & 31));
+      while (true) {
+        // collect up to kHitBatch hit positions of this row, in ascending order
+        int hp[kHitBatch];
+        int nh = 0;
+        while (nh < kHitBatch) {
+          if (w == w1) bits &= ~0u >> (31 - ((k1 - 1) & 31));
+          if (bits) {
+            hp[nh++] = w * 32 + __ffs(bits) - 1;
+            bits &= bits - 1u;
+          } else if (w < w1) {
+            bits = s_hits[++w];
           } else {
-            const uint32_t x = __float_as_uint(wf[p]);
-            u = x >> 31;
-            wv = __uint_as_float(x & 0x7FFFFFFFu);
+            break;
           }
-          if (u) dI += wv;
-          else dE += wv;
-          ++ev;
         }
+        uint32_t x[kHitBatch];
+#pragma unroll
+        for (int q = 0; q < kHitBatch; ++q)
+          if (q < nh) x[q] = kBF16 ? uint32_t(wb[B.syn0 + hp[q]]) << 16 : __float_as_uint(wf[B.syn0 + hp[q]]);
+#pragma unroll
+        for (int q = 0; q < kHitBatch; ++q) {
+          if (q < nh) {
+            const float wv = __uint_as_float(x[q] & 0x7FFFFFFFu);
+            if (x[q] >> 31) dI += wv;
+            else dE += wv;
+          }
+        }
+        ev += uint32_t(nh);
+        if (nh < kHitBatch) break;
       }
     }
-    if (r < n) {
-      // background Poisson count: Philox4x64-10, key (seed, 0), counter (t, i, member, 0)
-      // with i the neuron's index inside its member network
-      const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - B.member_row0), uint64_t(B.member),
-                                                    0ull, B.seed, 0ull));
-      const int c = poisson_count(u, poisson, K);
-      evb += uint32_t(c);
-      dE = __fmaf_rn(float(c), bg_w, dE);
-      float* jr = j + r;
-      const float ja = __fmaf_rn(a0, jr[0], dE);
-      const float jn = __fmaf_rn(a1, jr[n_pad], dE);
-      const float jga = __fmaf_rn(a2, jr[2 * n_pad], dI);
-      const float jgb = __fmaf_rn(a3, jr[3 * n_pad], dI);
-      jr[0] = ja;
-      jr[n_pad] = jn;
-      jr[2 * n_pad] = jga;
-      jr[3 * n_pad] = jgb;
-      if (!(isfinite(ja) && isfinite(jn) && isfinite(jga) && isfinite(jgb))) atomicOr(bad, 1);
-    }
+    const int c = poisson_count(u, poisson, K);
+    evb += uint32_t(c);
+    dE = __fmaf_rn(float(c), bg_w, dE);
+    const float ja = __fmaf_rn(a0, j0, dE);
+    const float jb = __fmaf_rn(a1, j1, dE);
+    const float jc = __fmaf_rn(a2, j2, dI);
+    const float jd = __fmaf_rn(a3, j3, dI);
+    j[r] = ja;
+    j[n_pad + r] = jb;
+    j[2 * n_pad + r] = jc;
+    j[3 * n_pad + r] = jd;
+    if (!(isfinite(ja) && isfinite(jb) && isfinite(jc) && isfinite(jd))) atomicOr(bad, 1);
   }
   // block totals of delivered events, then one striped atomic per block
   uint32_t e = ev, eb = evb;
