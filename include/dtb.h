@@ -100,8 +100,9 @@ typedef struct dtb_desc {
   int32_t wtype;             /* dtb_wtype: storage precision of w (accumulation is FP32) */
   int32_t record_steps;      /* steps of raster / counts history kept on device, >= 1 */
   int32_t gather_bundle_syn; /* launch shape of the gather: most synapses per workgroup
-                                (4096 .. 2^20-1; 0 = 2^20-1); a tuning knob, results do
-                                not depend on it */
+                                (4096 .. 2^20-1; 0 = library default, 640000, with a row
+                                of up to 2^20-1 synapses in a bundle of its own); a
+                                tuning knob, results do not depend on it */
 } dtb_desc;
 
 /* ------------------------------------------------------------ library */

@@ -246,7 +246,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   const std::vector<int64_t>& mrow = net->member_row0;
   // 1. bundles of consecutive rows
   const int64_t max_rows = std::min<int64_t>(65536, std::max<int64_t>(64, (n + 511) / 512));
-  const int64_t max_syn = s->gather_bundle_syn ? int64_t(s->gather_bundle_syn) : kBundleMaxSyn;
+  const int64_t max_syn = s->gather_bundle_syn ? int64_t(s->gather_bundle_syn) : kBundleDefaultSyn;
   std::vector<Bundle> bl;
   size_t mq = 0;  // member of row r
   for (int64_t r = 0; r < n;) {
@@ -259,6 +259,8 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     b.member = net->member_id[mq];
     b.seed = net->member_seed[mq];
     while (r < mend && r - b.row0 < max_rows && s->row_ptr[r + 1] - b.syn0 <= max_syn) ++r;
+    // with the default size, a longer row still gets a bundle of its own
+    if (r == b.row0 && !s->gather_bundle_syn && s->row_ptr[r + 1] - b.syn0 <= kBundleMaxSyn) ++r;
     if (r == b.row0)
       return fail(DTB_ERR_UNSUPPORTED, "row " + std::to_string(r) + " has more than " +
                                            std::to_string(max_syn) + " synapses (gather_bundle_syn)");
@@ -280,6 +282,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     std::vector<uint32_t>& T = btiles[q];
     std::vector<uint32_t>& H = bheads[q];
     T.reserve(size_t(b.nsyn) + size_t(b.nsyn) / 16 + kTile);
+    const uint32_t pad = uint32_t(b.nsyn);  // delta 0, position one past the last synapse
     int c = 0;
     uint32_t prev = 0, d1 = 0;
     for (uint64_t kk : key) {
@@ -287,7 +290,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
       const uint32_t pos = uint32_t(kk & kPosMask);
       if (c == 0 || c == kTile || kd != d1 || src - prev > kMaxDelta) {
         while (c > 0 && c < kTile) {
-          T.push_back(kInvalidPos);
+          T.push_back(pad);
           ++c;
         }
         H.push_back(src | (kd << 26));
@@ -300,17 +303,17 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
       ++c;
     }
     while (c > 0 && c < kTile) {
-      T.push_back(kInvalidPos);
+      T.push_back(pad);
       ++c;
     }
   });
   int64_t ntiles = 0;
-  int32_t hw = 1;
+  int32_t hw = 2 * (kGatherThreads / 64);  // the block totals reuse the hit bitmap's words
   for (int64_t q = 0; q < nb; ++q) {
     bl[q].tile0 = ntiles;
     bl[q].ntiles = int32_t(bheads[q].size());
     ntiles += bl[q].ntiles;
-    hw = std::max(hw, int32_t((bl[q].nsyn + 31) / 32));
+    hw = std::max(hw, int32_t(bl[q].nsyn >> 5) + 1);
   }
   d.n_bundles = nb;
   d.n_tiles = ntiles;

@@ -27,17 +27,43 @@ constexpr int kCompactBlock = 256;  // threads of the compaction kernel
 //    tiles of 256 entries (a wavefront loads one tile as one 16-byte load per
 //    lane: lane l holds entries 4l .. 4l+3).  Entry = source delta (12 bits,
 //    relative to the previous entry of the tile; the first entry has delta 0)
-//    << 20 | position of the synapse in the bundle's CSR range (20 bits;
-//    kInvalidPos = padding).  Tile header = first source of the tile
-//    (26 bits) | (delay - 1) << 26.
+//    << 20 | position of the synapse in the bundle's CSR range (20 bits).
+//    Padding entries (the tail of a tile) have delta 0 and position nsyn,
+//    one past the bundle's last synapse: a bit the sums never read.
+//    Tile header = first source of the tile (26 bits) | (delay - 1) << 26.
 constexpr int kTile = 256;
 constexpr int kPosBits = 20;
 constexpr uint32_t kPosMask = (1u << kPosBits) - 1u;
-constexpr uint32_t kInvalidPos = kPosMask;
 constexpr uint32_t kMaxDelta = (1u << (32 - kPosBits)) - 1u;  // 4095
-constexpr int64_t kBundleMaxSyn = int64_t(kInvalidPos);     // positions 0 .. 2^20 - 2
-constexpr int kGatherThreads = 1024;
-constexpr int kHitWords = int((kBundleMaxSyn + 31) / 32);   // LDS hit bitmap words
+constexpr int64_t kBundleMaxSyn = int64_t(kPosMask);         // synapses 0 .. 2^20 - 2, padding at nsyn
+constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap words of the largest bundle
+
+// Gather launch shape: threads per workgroup, tiles per wavefront per round
+// (per register set) and the wavefronts per SIMD the register allocation
+// must allow.  The default bundle fills the LDS hit bitmap (128 KB of the
+// CU's 160 KB), one 1024-thread workgroup per CU; four rounds of tiles and
+// two of bitmap words per wavefront are in registers at a time.  DTB_GATHER_NT selects
+// non-temporal loads for the data each step reads once.
+#ifndef DTB_GATHER_THREADS
+#define DTB_GATHER_THREADS 1024
+#endif
+#ifndef DTB_GATHER_UNROLL
+#define DTB_GATHER_UNROLL 3
+#endif
+#ifndef DTB_GATHER_WAVES_PER_EU
+#define DTB_GATHER_WAVES_PER_EU 4
+#endif
+#ifndef DTB_GATHER_NT
+#define DTB_GATHER_NT 1
+#endif
+#ifndef DTB_GATHER_BUNDLE_SYN
+#define DTB_GATHER_BUNDLE_SYN 1048575
+#endif
+constexpr int kGatherThreads = DTB_GATHER_THREADS;
+constexpr int kGatherUnroll = DTB_GATHER_UNROLL;
+constexpr int kGatherWavesPerEU = DTB_GATHER_WAVES_PER_EU;
+constexpr int64_t kBundleDefaultSyn = DTB_GATHER_BUNDLE_SYN;
+static_assert(kBundleDefaultSyn <= kBundleMaxSyn, "bundle positions are 20 bits");
 
 struct Bundle {
   int64_t row0, row1;   // rows [row0, row1)

@@ -56,8 +56,6 @@ __device__ inline int poisson_count(uint32_t u, const uint32_t* __restrict__ T, 
   return c;
 }
 
-__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
-
 // ----------------------------------------------------------- neuron update
 // One thread per neuron, 1024 threads (16 wavefronts) per block.
 __global__ __launch_bounds__(1024) void k_neuron_update(
@@ -266,8 +264,6 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
 // Workgroups are mapped XCD-aware: the blocks an XCD receives (blockIdx
 // congruent mod 8) take a contiguous range of bundles, so bundles of the
 // same population (same source set) share that XCD's L2.
-constexpr int kUnroll = 4;  // tiles per wavefront per round (4 KB per wavefront in flight)
-
 // Inclusive prefix sum over the 64 lanes of a wavefront with DPP row shifts
 // (within each 16-lane row) and the row broadcasts of lanes 15 and 31.
 __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
@@ -280,8 +276,77 @@ __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
   return x;
 }
 
+// Data touched once per step (lookup tiles, row pointers, gates, weights)
+// is loaded and stored non-temporally so that it does not push the delayed
+// spike bitmaps, which every bundle re-reads, out of the L2 of its XCD.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ inline T stream_load(const T* p) {
+#if DTB_GATHER_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename T>
+__device__ inline void stream_store(T* p, T v) {
+#if DTB_GATHER_NT
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
+// One round of delivery tests over kU tiles already in registers: rebuild
+// the sources (wavefront prefix sum of the deltas on top of the tile's first
+// source) and issue the kU x 4 bitmap loads.
+template <int kU>
+__device__ inline void gather_lookups(const u32x4 (&tv)[kU], const uint32_t (&h)[kU], const uint32_t* bitmaps,
+                                      int64_t words_pad, int32_t t_mod, int32_t slots, uint32_t wmax,
+                                      uint32_t (&src)[kU][4], uint32_t (&word)[kU][4]) {
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const uint32_t d0 = tv[u].x >> kPosBits, d1 = tv[u].y >> kPosBits, d2 = tv[u].z >> kPosBits,
+                   d3 = tv[u].w >> kPosBits;
+    const uint32_t incl = wave_incl_scan_dpp(d0 + d1 + d2 + d3);
+    src[u][3] = (h[u] & 0x3FFFFFFu) + incl;  // the lane's last source
+    src[u][2] = src[u][3] - d3;
+    src[u][1] = src[u][2] - d2;
+    src[u][0] = src[u][1] - d1;
+    // spikes of step t - d + 1 arrive now; steps before 0 map to unwritten (zero) slots
+    int32_t slot = t_mod - int32_t(h[u] >> 26);
+    if (slot < 0) slot += slots;
+    const uint32_t* bm = bitmaps + int64_t(slot) * words_pad;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) word[u][c] = bm[min(src[u][c] >> 5, wmax)];
+  }
+}
+
+// Set the LDS hit bit of every synapse whose source spiked.  The wavefront
+// skips an entry index (uniform branch) when none of its lanes has a hit.
+// Padding entries point at the bit one past the bundle's last synapse,
+// which the sums never read, and a tile processed twice sets the same bits
+// again, so neither needs a test here.
+template <int kU>
+__device__ inline void gather_hits(const u32x4 (&tv)[kU], const uint32_t (&src)[kU][4],
+                                   const uint32_t (&word)[kU][4], uint32_t* s_hits) {
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const uint32_t e[4] = {tv[u].x, tv[u].y, tv[u].z, tv[u].w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t hit = __builtin_amdgcn_ubfe(word[u][c], src[u][c], 1u);
+      if (__builtin_amdgcn_ballot_w64(hit != 0u)) {
+        asm volatile("");  // keeps this wavefront-uniform skip a scalar branch of its own
+        if (hit) atomicOr(&s_hits[(e[c] & kPosMask) >> 5], 1u << (e[c] & 31u));
+      }
+    }
+  }
+}
+
 template <bool kBF16>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(
+__global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kGatherWavesPerEU)))
+void k_gather(
     int64_t n, int64_t n_bundles, int64_t n_pad, const int64_t* __restrict__ step,
     const Bundle* __restrict__ bundles, const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
     const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v, const uint32_t* __restrict__ bitmaps,
@@ -292,77 +357,80 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
   const int64_t t = step[0];
   const int32_t t_mod = int32_t(step[1]);
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(t_mod) * kStripes * 2;
-  __shared__ uint32_t s_ev[kGatherThreads / 64][2];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t per = (n_bundles + 7) / 8;
   const int64_t bi = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (bi >= n_bundles) return;  // whole block leaves together
   const Bundle B = bundles[bi];
-  const int hw = (B.nsyn + 31) >> 5;
+  const int hw = (B.nsyn >> 5) + 1;  // includes the padding bit at position nsyn
   for (int q = tid; q < hw; q += kGatherThreads) s_hits[q] = 0u;
   __syncthreads();
 
   // ---- phase 1: delivery tests in (delay, source) order
-  constexpr int kWaves = kGatherThreads / 64;
+  // Software pipeline over rounds of kU tiles per wavefront.  In the stage
+  // that takes the hits of round r, the bitmap words of round r+1 are
+  // requested and the tiles of round r+3 are fetched, while those of round
+  // r+2 are still on their way: two rounds of lookups and two of tiles are
+  // in flight per wavefront, and since loads return in order no wait ever
+  // has to drain the newer ones.  Four tile sets and two lookup sets
+  // rotate (the loop body is four stages).  Tile indices past the end are
+  // clamped to the last tile, which then is processed again (the OR is
+  // idempotent), so every load is unconditional.
+  constexpr int kU = kGatherUnroll;
+  constexpr int kS = (kGatherThreads / 64) * kU;  // tiles per round of the workgroup
   const int nt = B.ntiles;
-  const uint4* tp = reinterpret_cast<const uint4*>(tiles + B.tile0 * kTile) + lane;
+  const u32x4* tp = reinterpret_cast<const u32x4*>(tiles + B.tile0 * kTile) + lane;
   const uint32_t* hp = theads + B.tile0;
   const uint32_t wmax = uint32_t(words_pad - 1);
-  // Software pipeline: the tile loads of round r+1 are issued after the
-  // bitmap loads of round r, so waiting for the bitmap words (loads return in
-  // order) leaves the next tiles in flight.
-  uint4 tv[kUnroll];
-  uint32_t h[kUnroll];
-  bool live[kUnroll];
-  auto fetch = [&](int qb) {
+  u32x4 t0[kU], t1[kU], t2[kU], t3[kU];
+  uint32_t h0[kU], h1[kU], h2[kU], h3[kU];
+  uint32_t sa[kU][4], sb[kU][4];  // sources of the rounds being looked up
+  uint32_t xa[kU][4], xb[kU][4];  // their bitmap words
+  auto fetch = [&](u32x4 (&tv)[kU], uint32_t (&h)[kU], int qb) {
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int q = qb + u * kWaves;
-      live[u] = q < nt;
-      const int qc = live[u] ? q : nt - 1;  // a valid tile; its results are masked out
-      tv[u] = tp[int64_t(qc) * 64];
+    for (int u = 0; u < kU; ++u) {
+      const int qc = min(qb + u * (kGatherThreads / 64), nt - 1);
+      tv[u] = stream_load(tp + int64_t(qc) * 64);
       h[u] = __builtin_amdgcn_readfirstlane(hp[qc]);
     }
   };
-  if (wave < nt) fetch(wave);  // nt > 0 inside the loop, so fetch's clamp stays in the bundle
-  for (int q0 = wave; q0 < nt; q0 += kWaves * kUnroll) {
-    uint32_t src[kUnroll][4], word[kUnroll][4], pos[kUnroll][4];
-    bool cur_live[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const uint32_t d0 = tv[u].x >> kPosBits, d1 = tv[u].y >> kPosBits, d2 = tv[u].z >> kPosBits,
-                     d3 = tv[u].w >> kPosBits;
-      const uint32_t sum = d0 + d1 + d2 + d3;
-      const uint32_t excl = wave_incl_scan_dpp(sum) - sum;
-      src[u][0] = (h[u] & 0x3FFFFFFu) + excl + d0;
-      src[u][1] = src[u][0] + d1;
-      src[u][2] = src[u][1] + d2;
-      src[u][3] = src[u][2] + d3;
-      pos[u][0] = tv[u].x & kPosMask;
-      pos[u][1] = tv[u].y & kPosMask;
-      pos[u][2] = tv[u].z & kPosMask;
-      pos[u][3] = tv[u].w & kPosMask;
-      cur_live[u] = live[u];
+  auto lookups = [&](const u32x4 (&tv)[kU], const uint32_t (&h)[kU], uint32_t (&src)[kU][4],
+                     uint32_t (&word)[kU][4]) {
+    gather_lookups<kU>(tv, h, bitmaps, words_pad, t_mod, slots, wmax, src, word);
+  };
+  if (wave < nt) {  // nt > 0 here, so every clamped index lies in the bundle
+    // stage j takes the hits of one round; the loop runs whole groups of
+    // four stages (a break inside the group would make the compiler drain
+    // every load at the loop head), the remaining rounds follow it
+    const int rounds = (nt - wave + kS - 1) / kS;
+    int q0 = wave;
+    fetch(t0, h0, q0);
+    fetch(t1, h1, q0 + kS);
+    fetch(t2, h2, q0 + 2 * kS);
+    lookups(t0, h0, sa, xa);
+    for (int g = rounds >> 2; g > 0; --g, q0 += 4 * kS) {
+      lookups(t1, h1, sb, xb);
+      fetch(t3, h3, q0 + 3 * kS);
+      gather_hits<kU>(t0, sa, xa, s_hits);
+      lookups(t2, h2, sa, xa);
+      fetch(t0, h0, q0 + 4 * kS);
+      gather_hits<kU>(t1, sb, xb, s_hits);
+      lookups(t3, h3, sb, xb);
+      fetch(t1, h1, q0 + 5 * kS);
+      gather_hits<kU>(t2, sa, xa, s_hits);
+      lookups(t0, h0, sa, xa);
+      fetch(t2, h2, q0 + 6 * kS);
+      gather_hits<kU>(t3, sb, xb, s_hits);
     }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      // spikes of step t - d + 1 arrive now; steps before 0 map to unwritten (zero) slots
-      int32_t slot = t_mod - int32_t(h[u] >> 26);
-      if (slot < 0) slot += slots;
-      const uint32_t* bm = bitmaps + int64_t(slot) * words_pad;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) word[u][c] = bm[min(src[u][c] >> 5, wmax)];
-    }
-    fetch(q0 + kWaves * kUnroll);  // unconditional (clamped), so the waits above count exactly
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        // branch-free predicate: every bitmap word is consumed before any branch
-        const uint32_t hit = ((word[u][c] >> (src[u][c] & 31u)) & 1u) & uint32_t(pos[u][c] != kInvalidPos) &
-                             uint32_t(cur_live[u]);
-        if (hit) atomicOr(&s_hits[pos[u][c] >> 5], 1u << (pos[u][c] & 31u));
+    const int rem = rounds & 3;
+    if (rem > 0) {
+      lookups(t1, h1, sb, xb);
+      gather_hits<kU>(t0, sa, xa, s_hits);
+      if (rem > 1) {
+        lookups(t2, h2, sa, xa);
+        gather_hits<kU>(t1, sb, xb, s_hits);
+        if (rem > 2) gather_hits<kU>(t2, sa, xa, s_hits);
       }
     }
   }
@@ -381,24 +449,24 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
   int64_t k0n = 0, k1n = 0;
   float jn0 = 0.f, jn1 = 0.f, jn2 = 0.f, jn3 = 0.f;
   if (r < B.row1) {
-    k0n = row_ptr[r] - B.syn0;
-    k1n = row_ptr[r + 1] - B.syn0;
-    jn0 = j[r];
-    jn1 = j[n_pad + r];
-    jn2 = j[2 * n_pad + r];
-    jn3 = j[3 * n_pad + r];
+    k0n = stream_load(row_ptr + r) - B.syn0;
+    k1n = stream_load(row_ptr + r + 1) - B.syn0;
+    jn0 = stream_load(j + r);
+    jn1 = stream_load(j + n_pad + r);
+    jn2 = stream_load(j + 2 * n_pad + r);
+    jn3 = stream_load(j + 3 * n_pad + r);
   }
   for (; r < B.row1; r += kGatherThreads) {
     const int k0 = int(k0n), k1 = int(k1n);
     const float j0 = jn0, j1 = jn1, j2 = jn2, j3 = jn3;
     const int64_t rn = r + kGatherThreads;
     if (rn < B.row1) {
-      k0n = row_ptr[rn] - B.syn0;
-      k1n = row_ptr[rn + 1] - B.syn0;
-      jn0 = j[rn];
-      jn1 = j[n_pad + rn];
-      jn2 = j[2 * n_pad + rn];
-      jn3 = j[3 * n_pad + rn];
+      k0n = stream_load(row_ptr + rn) - B.syn0;
+      k1n = stream_load(row_ptr + rn + 1) - B.syn0;
+      jn0 = stream_load(j + rn);
+      jn1 = stream_load(j + n_pad + rn);
+      jn2 = stream_load(j + 2 * n_pad + rn);
+      jn3 = stream_load(j + 3 * n_pad + rn);
     }
     // background Poisson count: Philox4x64-10, key (seed, 0), counter (t, i, member, 0)
     // with i the neuron's index inside its member network
@@ -427,7 +495,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
         uint32_t x[kHitBatch];
 #pragma unroll
         for (int q = 0; q < kHitBatch; ++q)
-          if (q < nh) x[q] = kBF16 ? uint32_t(wb[B.syn0 + hp[q]]) << 16 : __float_as_uint(wf[B.syn0 + hp[q]]);
+          if (q < nh)
+            x[q] = kBF16 ? uint32_t(stream_load(wb + B.syn0 + hp[q])) << 16
+                         : __float_as_uint(stream_load(wf + B.syn0 + hp[q]));
 #pragma unroll
         for (int q = 0; q < kHitBatch; ++q) {
           if (q < nh) {
@@ -447,29 +517,32 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(
     const float jb = __fmaf_rn(a1, j1, dE);
     const float jc = __fmaf_rn(a2, j2, dI);
     const float jd = __fmaf_rn(a3, j3, dI);
-    j[r] = ja;
-    j[n_pad + r] = jb;
-    j[2 * n_pad + r] = jc;
-    j[3 * n_pad + r] = jd;
+    stream_store(j + r, ja);
+    stream_store(j + n_pad + r, jb);
+    stream_store(j + 2 * n_pad + r, jc);
+    stream_store(j + 3 * n_pad + r, jd);
     if (!(isfinite(ja) && isfinite(jb) && isfinite(jc) && isfinite(jd))) atomicOr(bad, 1);
   }
-  // block totals of delivered events, then one striped atomic per block
+  // block totals of delivered events, then one striped atomic per block;
+  // the wavefront totals reuse the first words of the hit bitmap
   uint32_t e = ev, eb = evb;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     e += __shfl_down(e, off);
     eb += __shfl_down(eb, off);
   }
+  __syncthreads();  // every row's hit words are read
+  uint32_t* s_ev = s_hits;
   if (lane == 0) {
-    s_ev[tid >> 6][0] = e;
-    s_ev[tid >> 6][1] = eb;
+    s_ev[2 * (tid >> 6)] = e;
+    s_ev[2 * (tid >> 6) + 1] = eb;
   }
   __syncthreads();
   if (tid == 0) {
     int64_t r = 0, bgs = 0;
     for (int w = 0; w < kGatherThreads / 64; ++w) {
-      r += s_ev[w][0];
-      bgs += s_ev[w][1];
+      r += s_ev[2 * w];
+      bgs += s_ev[2 * w + 1];
     }
     int64_t* dst = ev_slot + 2 * (blockIdx.x & (kStripes - 1));
     if (r) atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)r);
