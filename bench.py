@@ -59,14 +59,14 @@ def gather_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) 
     return 5.0 * nnz + w_bytes * events + 32.0 * n + n * (max_delay + 1) / 8.0
 
 
-def run_rate(net, rate, lam, steps, warmup, wtype, bundle_syn=0):
+def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0)):
     import torch
     import paper_2308_01241_amd as dtb
 
     net.bg_lambda = lam
     t0 = time.time()
     g = dtb.Net(net, wtype=wtype, record_steps=max(steps, 16), stream=torch.cuda.current_stream(),
-                bundle_syn=bundle_syn)
+                bundle_syn=shape[0], unroll=shape[1])
     torch.cuda.synchronize()
     log(f"[bench] {rate} Hz: created in {time.time() - t0:.1f}s; warmup {warmup}")
     g.step(warmup)
@@ -93,7 +93,87 @@ def run_rate(net, rate, lam, steps, warmup, wtype, bundle_syn=0):
             "events": ev, "events_per_s": ev / wall, "rtf": wall / (steps * net.dt_ms * 1e-3),
             "mean_rate_hz": spikes / (net.n * steps * net.dt_ms * 1e-3),
             "region_rate_spread": [float(np.min(rates)), float(np.max(rates))],
-            "bg_events_per_s": (c1["ev_bg"] - c0["ev_bg"]) / wall, "kernels": kt}
+            "bg_events_per_s": (c1["ev_bg"] - c0["ev_bg"]) / wall, "kernels": kt, "region_rates": rates}
+
+
+def rate_error(r, ref):
+    """Relative error of per-region rates against a reference run."""
+    r, ref = np.asarray(r, np.float64), np.asarray(ref, np.float64)
+    rel = np.abs(r - ref) / np.maximum(ref, 1e-9)
+    return {"max_region_rel": float(rel.max()), "mean_region_rel": float(rel.mean()),
+            "mean_rate_rel": float(abs(r.mean() - ref.mean()) / ref.mean())}
+
+
+def ensemble_members(n_members: int = 64):
+    """The batched-ensemble workload: members of 50k-400k neurons with 20
+    regions each at the 7 Hz drive, and their per-(region, channel) gains."""
+    import netgen
+    sizes = netgen.ensemble_sizes(n_members)
+    gains = netgen.ensemble_gains(n_members)
+    members = [netgen.make_network(netgen.ensemble_member_spec(m, int(nm), rate_hz=7))
+               for m, nm in enumerate(sizes)]
+    return members, gains
+
+
+def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: int = 200):
+    """The batched ensemble: n_members independent networks of 50k-400k
+    neurons (20 regions each, per-(member, region, channel) gains), advanced
+    together by replays of one captured HIP graph, against the same members
+    stepped one handle at a time (the plain path)."""
+    import torch
+    import paper_2308_01241_amd as dtb
+    from paper_2308_01241_amd import autotune
+
+    t0 = time.time()
+    members, gains = ensemble_members(n_members)
+    n_tot = int(sum(m.n for m in members))
+    s_tot = int(sum(m.nnz for m in members))
+    log(f"[bench] ensemble: {n_members} members, {n_tot} neurons, {s_tot} synapses, generated in "
+        f"{time.time() - t0:.1f}s")
+    shape = autotune.lookup(n_tot, s_tot, n_members, "f32", max(m.max_delay for m in members))
+    stream = torch.cuda.current_stream()
+    g = dtb.Net.batch(members, record_steps=64, stream=stream, bundle_syn=shape[0], unroll=shape[1])
+    g.set_gains(gains.reshape(-1, 4))
+    g.run(warmup)
+    g.sync()
+    c0 = g.counters()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    g.run(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    c1 = g.counters()
+    bold = g.bold()
+    g.close()
+    ev = c1["ev_rec"] - c0["ev_rec"]
+    batched = {"ms_per_step": ms / steps, "events_per_s": ev / (ms * 1e-3),
+               "rtf": ms * 1e-3 / (steps * 1e-3),
+               "mean_rate_hz": (c1["spikes"] - c0["spikes"]) / (n_tot * steps * 1e-3),
+               "bold_finite": bool(np.isfinite(bold).all())}
+    # the plain path, one member at a time, same gains, graph replays too
+    ev_m, ms_m = 0, 0.0
+    for m, nw in enumerate(members):
+        h = dtb.Net(nw, record_steps=64, stream=stream)
+        h.set_gains(gains[m])
+        h.run(warmup)
+        h.sync()
+        e0 = h.counters()["ev_rec"]
+        a.record(stream)
+        h.run(per_member_steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_m += a.elapsed_time(b)
+        ev_m += h.counters()["ev_rec"] - e0
+        h.close()
+    single = {"events_per_s": ev_m / (ms_m * 1e-3), "ms_per_step_all_members": ms_m / per_member_steps,
+              "steps_per_member": per_member_steps}
+    return {"gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None},
+            "workload": f"ensemble: {n_members} members of 50k-400k neurons (20 regions each), "
+                        f"{n_tot} neurons, {s_tot} synapses, per-region channel gains, 7 Hz drive, "
+                        f"{steps} steps under one captured HIP graph",
+            "batched": batched, "member_by_member": single,
+            "speedup_events_per_s": batched["events_per_s"] / single["events_per_s"]}
 
 
 def cpu_baseline(net, rate_hz: float, frac: float = 0.02, warm: int = 20, timed: int = 10):
@@ -183,6 +263,8 @@ def main():
     ap.add_argument("--tune", action="store_true", help="bisect the background drive per target rate")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a plain copy of known size")
     ap.add_argument("--autotune", action="store_true", help="search the gather launch shape, store it")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 and batched-ensemble runs")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's partition; --gpus {args.gpus} is not supported "
@@ -210,41 +292,73 @@ def main():
     if args.autotune:
         net.bg_lambda = netgen.PARTITION_LAMBDA[rates[0]]
         best, res = autotune.tune(
-            lambda c: dtb.Net(net, wtype=args.wtype, record_steps=64, stream=torch.cuda.current_stream(),
-                              bundle_syn=c), key, log=log)
-        print(json.dumps({"autotune": key, "best": best, "ms_per_step": res}), flush=True)
+            lambda b, u: dtb.Net(net, wtype=args.wtype, record_steps=64, stream=torch.cuda.current_stream(),
+                                 bundle_syn=b, unroll=u), key, log=log)
+        out = {key: {"best": list(best), "ms_per_step": {f"{b}/{u}": v for (b, u), v in res.items()}}}
+        del net
+        members, gains = ensemble_members(64)
+        ekey = autotune.shape_key(sum(m.n for m in members), sum(m.nnz for m in members), len(members), "f32",
+                                  max(m.max_delay for m in members))
+
+        def make(b, u):
+            h = dtb.Net.batch(members, record_steps=64, stream=torch.cuda.current_stream(), bundle_syn=b, unroll=u)
+            h.set_gains(gains.reshape(-1, 4))
+            return h
+
+        best, res = autotune.tune(make, ekey, log=log)
+        out[ekey] = {"best": list(best), "ms_per_step": {f"{b}/{u}": v for (b, u), v in res.items()}}
+        print(json.dumps({"autotune": out}), flush=True)
         return
-    bsyn = autotune.lookup(net.n, net.nnz, 1, args.wtype, net.max_delay)
-    log(f"[bench] gather bundle size: {bsyn or 'default'}")
+    shape = autotune.lookup(net.n, net.nnz, 1, args.wtype, net.max_delay)
+    log(f"[bench] gather shape (bundle_syn, unroll): {shape} (0 = library default)")
     res = {}
     for r in rates:
-        res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype, bsyn)
-        log(f"[bench] {r} Hz: {json.dumps({k: v for k, v in res[r].items() if k != 'kernels'})}")
+        res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype, shape)
+        log(f"[bench] {r} Hz: {json.dumps({k: v for k, v in res[r].items() if k not in ('kernels', 'region_rates')})}")
         log(f"[bench] {r} Hz kernels: {res[r]['kernels']}")
     head = res[rates[0]]
+    n_neu, n_syn, n_del = net.n, net.nnz, net.max_delay
     wb = 2 if args.wtype == "bf16" else 4
     kg = head["kernels"]["gather"]
     g_ms = kg["ms"] / max(1, kg["launches"])
     ev_step = head["events"] / args.steps
-    B = gather_bytes(net.nnz, net.n, net.max_delay, ev_step, wb)
+    B = gather_bytes(n_syn, n_neu, n_del, ev_step, wb)
     achieved = B / (g_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_gather",
             "algorithmic_bytes_per_launch": B, "avg_launch_ms": g_ms}
+    forms = {}
+    if not args.no_forms and args.wtype == "f32":
+        r0 = rates[0]
+        bf = run_rate(net, r0, netgen.PARTITION_LAMBDA[r0], args.steps, args.warmup, "bf16",
+                      autotune.lookup(n_neu, n_syn, 1, "bf16", n_del))
+        forms["bf16"] = {"rate_target_hz": r0, "events_per_s": bf["events_per_s"], "ms_per_step": bf["ms_per_step"],
+                         "rtf": bf["rtf"], "speedup_events_per_s": bf["events_per_s"] / res[r0]["events_per_s"],
+                         "gather_ms": bf["kernels"]["gather"]["ms"] / max(1, bf["kernels"]["gather"]["launches"]),
+                         "rate_error_vs_f32": rate_error(bf["region_rates"], res[r0]["region_rates"])}
+        log(f"[bench] bf16: {json.dumps(forms['bf16'])}")
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (FP64 reference, bounded sample)")
         cpu = cpu_baseline(net, float(rates[0]))
         log(f"[bench] cpu: {cpu}")
+    del net
+    if not args.no_forms and args.wtype == "f32":
+        import gc
+        gc.collect()
+        forms["ensemble"] = run_batched(args.batch_steps, 200)
+        log(f"[bench] ensemble: {json.dumps(forms['ensemble'])}")
     out = {"metric": METRIC, "value": head["events_per_s"], "unit": "synaptic events/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": args.wtype, "data": "synthetic",
-           "config": {"workload": f"partition_net: {net.n} neurons, {net.nnz} synapses, 90 regions, "
-                                  f"in-degree 100, delays 1-{net.max_delay}, dt 1 ms, {rates[0]} Hz",
+           "config": {"workload": f"partition_net: {n_neu} neurons, {n_syn} synapses, 90 regions, "
+                                  f"in-degree 100, delays 1-{n_del}, dt 1 ms, {rates[0]} Hz",
                       "global_batch": 1, "seq_len": args.steps, "parallelism": "single-gpu"},
-           "rtf": head["rtf"], "roofline": roof, "cpu_baseline": cpu, "gather_bundle_syn": bsyn or None,
-           "rates": {str(r): {k: v for k, v in res[r].items() if k != "kernels"} for r in rates},
+           "rtf": head["rtf"], "roofline": roof, "cpu_baseline": cpu, "gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None},
+           "rates": {str(r): {k: v for k, v in res[r].items() if k not in ("kernels", "region_rates")}
+                     for r in rates},
+           "forms": forms or None,
            "kernels_ms_per_step": {k: v["ms"] / max(1, v["launches"]) for k, v in head["kernels"].items()}}
     print(json.dumps(out), flush=True)
 

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 1
+#define DTB_ABI_VERSION 2
 
 typedef enum {
   DTB_OK = 0,
@@ -100,9 +100,12 @@ typedef struct dtb_desc {
   int32_t wtype;             /* dtb_wtype: storage precision of w (accumulation is FP32) */
   int32_t record_steps;      /* steps of raster / counts history kept on device, >= 1 */
   int32_t gather_bundle_syn; /* launch shape of the gather: most synapses per workgroup
-                                (4096 .. 2^20-1; 0 = library default, 640000, with a row
-                                of up to 2^20-1 synapses in a bundle of its own); a
-                                tuning knob, results do not depend on it */
+                                (4096 .. 2^20-1; 0 = library default, 2^20-1); a row longer
+                                than a non-default value is rejected.  A tuning knob:
+                                results do not depend on it */
+  int32_t gather_unroll;     /* launch shape of the gather: lookup tiles per wavefront per
+                                round, 1 .. 3 (0 = library default, 3).  A tuning knob:
+                                results do not depend on it */
 } dtb_desc;
 
 /* ------------------------------------------------------------ library */

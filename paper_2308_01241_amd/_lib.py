@@ -36,7 +36,8 @@ class Desc(ctypes.Structure):
                 ("E", ctypes.c_float * 4), ("tau_ms", ctypes.c_float * 4), ("dt_ms", ctypes.c_float),
                 ("bg_w", ctypes.c_float), ("bg_lambda", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("wtype", ctypes.c_int32), ("record_steps", ctypes.c_int32),
-                ("gather_bundle_syn", ctypes.c_int32)]
+                ("gather_bundle_syn", ctypes.c_int32),
+                ("gather_unroll", ctypes.c_int32)]
 
 
 # every symbol include/dtb.h declares, with its ctypes signature
@@ -98,7 +99,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 1:
+    if lib.dtb_abi_version() != 2:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

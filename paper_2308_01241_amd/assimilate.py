@@ -1,31 +1,33 @@
 """Surrogate-screened assimilation of population gains (the hierarchical
-mesoscopic data assimilation idea of Sec. V-E on one GPU).
+mesoscopic data assimilation idea of Sec. V-E, on one GPU).
 
 Pipeline, all on the GPU through the C ABI:
-  1. data   - the batched ensemble runs in segments; each segment gives every
-              member fresh per-population channel gains ~ N(1, 0.2^2) (>= 0),
-              and a sample maps (gains, population rates of the previous
-              segment) -> (population rates of the segment, BOLD at its end);
+  1. data   - the batched ensemble runs from rest one window of `window`
+              steps at unit gains, then one at fresh per-population channel
+              gains ~ N(1, 0.2^2) (clipped at 0); a sample maps (gains,
+              population rates of the first window) -> (population rates of
+              the second window, BOLD at its end);
   2. train  - the MFMA surrogate MLP learns that map (z-scored, Adam, MSE);
-  3. screen - against a synthetic twin target (a member network with hidden
+  3. screen - against a synthetic twin target (a member network whose gains
+              are hidden: one window at unit gains, then one at the hidden
               gains), each iteration scores many Gaussian proposals with the
-              surrogate, re-simulates the best ones as one batch (the judge)
-              and the same number of random proposals (no surrogate), and
-              moves the proposal mean to the best simulated one.
+              surrogate, re-simulates the best k as one batch (the judge) and
+              k random proposals the same way (the method without the
+              surrogate), and moves the proposal mean to the best simulated
+              one.
 
 `python -m paper_2308_01241_amd.assimilate --out report.json` runs it.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import sys
 import time
 
 import numpy as np
 
-R_POP = 20            # populations per member
-SEG = 200             # steps per segment (200 ms)
 GAIN_SD = 0.2
 
 
@@ -38,37 +40,50 @@ def _stream():
     return torch.cuda.current_stream()
 
 
-def member_networks(sizes, seed_base=3100, rate_hz=15):
+@dataclasses.dataclass
+class Setup:
+    members: int = 64          # ensemble members in the data batch
+    lo: int = 50_000           # member sizes ~ U[lo, hi]
+    hi: int = 400_000
+    regions: int = 20          # populations per member
+    window: int = 400          # steps per window (dt = 1 ms)
+    rate_hz: int = 15          # background drive of the members
+    target_n: int = 200_000    # size of the twin target
+
+
+def member_networks(S: Setup, seed: int = 31):
     import netgen
-    return [netgen.make_network(netgen.ensemble_member_spec(m, int(n), rate_hz=rate_hz, n_regions=R_POP))
+    sizes = netgen.ensemble_sizes(S.members, S.lo, S.hi, seed=seed)
+    return [netgen.make_network(netgen.ensemble_member_spec(m, int(n), rate_hz=S.rate_hz, n_regions=S.regions))
             for m, n in enumerate(sizes)]
 
 
-def segment_rates(net, t0, t1):
-    """[members, R_POP] rates (Hz) over steps [t0, t1) from a batch handle."""
-    return net.region_rates(t0, t1).reshape(-1, R_POP)
+def window_rates(net, S: Setup):
+    """[members, regions] rates (Hz) over the last window."""
+    return net.region_rates(net.t - S.window, net.t).reshape(-1, S.regions)
 
 
-def generate(net, n_runs, n_seg, rng, warm=SEG):
-    """Samples from n_runs runs of n_seg segments (after one warm-up segment
-    with unit gains).  Returns X [S, 4 R + R] and Y [S, 2 R]."""
-    M = net.n_members
+def generate(net, S: Setup, n_runs: int, rng):
+    """n_runs x members samples, each run the way the judge simulates a
+    proposal: from rest, one window at unit gains, then one window at fresh
+    gains.  Returns X [samples, 5 R] (gains, rates of the first window) and
+    Y [samples, 2 R] (rates of the second window, BOLD at its end)."""
+    M, R = net.n_members, S.regions
     X, Y = [], []
     for run in range(n_runs):
         net.reset()
-        net.set_gains(np.ones((M * R_POP, 4), dtype=np.float32))
-        net.run(warm)
-        prev = segment_rates(net, net.t - warm, net.t)
-        for s in range(n_seg):
-            g = np.clip(rng.normal(1.0, GAIN_SD, (M, R_POP, 4)), 0.0, None).astype(np.float32)
-            net.set_gains(g.reshape(-1, 4))
-            net.run(SEG)
-            rates = segment_rates(net, net.t - SEG, net.t)
-            bold = net.bold().reshape(M, R_POP)
-            X.append(np.concatenate([g.reshape(M, -1), prev], axis=1))
-            Y.append(np.concatenate([rates, 1e3 * bold], axis=1))  # BOLD in 1e-3 units
-            prev = rates
-        log(f"[data] run {run + 1}/{n_runs}: {len(X) * M} samples")
+        net.set_gains(np.ones((M * R, 4), dtype=np.float32))
+        net.run(S.window)
+        prev = window_rates(net, S)
+        g = np.clip(rng.normal(1.0, GAIN_SD, (M, R, 4)), 0.0, None).astype(np.float32)
+        net.set_gains(g.reshape(-1, 4))
+        net.run(S.window)
+        rates = window_rates(net, S)
+        bold = net.bold().reshape(M, R)
+        X.append(np.concatenate([g.reshape(M, -1), prev], axis=1))
+        Y.append(np.concatenate([rates, 1e3 * bold], axis=1))  # BOLD in 1e-3 units
+        if (run + 1) % 16 == 0 or run + 1 == n_runs:
+            log(f"[data] run {run + 1}/{n_runs}: {len(X) * M} samples")
     return np.concatenate(X).astype(np.float32), np.concatenate(Y).astype(np.float32)
 
 
@@ -84,26 +99,30 @@ class Scaler:
         return Z * self.sd + self.mu
 
 
-def train(X, Y, epochs=30, batch=256, lr=1e-3, seed=0):
+def train(X, Y, epochs=30, batch=256, lr=1e-3, seed=0, width=256, depth=3):
     from . import MLP
     sx, sy = Scaler(X), Scaler(Y)
     Xz, Yz = sx.f(X), sy.f(Y)
-    m = MLP(X.shape[1], 256, 3, Y.shape[1], seed=seed)
+    m = MLP(X.shape[1], width, depth, Y.shape[1], seed=seed)
     rng = np.random.default_rng(seed)
+    bs = min(batch, len(X))
     for ep in range(epochs):
         perm = rng.permutation(len(X))
-        tot = 0.0
-        for b in range(0, len(X) - batch + 1, batch):
-            idx = perm[b:b + batch]
+        tot, nb = 0.0, 0
+        for b in range(0, len(X) - bs + 1, bs):
+            idx = perm[b:b + bs]
             tot += m.train_step(Xz[idx], Yz[idx], lr)
+            nb += 1
         if ep % 5 == 4 or ep == epochs - 1:
-            log(f"[train] epoch {ep + 1}: mean batch loss {tot / max(1, len(X) // batch):.4f}")
+            log(f"[train] epoch {ep + 1}: mean batch loss {tot / max(1, nb):.4f}")
     return m, sx, sy
 
 
-def evaluate(m, sx, sy, X, Y):
+def evaluate(m, sx, sy, X, Y, R):
+    """Held-out error of the surrogate: relative RMSE (against the spread of
+    the data) and the mean across samples of the correlation over
+    populations between predicted and simulated values."""
     P = sy.inv(m.forward(sx.f(X)))
-    R = R_POP
     out = {}
     for name, sl in (("rates", slice(0, R)), ("bold", slice(R, 2 * R))):
         err = P[:, sl] - Y[:, sl]
@@ -118,80 +137,109 @@ def _fit(rates, bold, t_rates, t_bold, sr, sb):
     return np.mean(((rates - t_rates) / sr) ** 2, axis=-1) + np.mean(((bold - t_bold) / sb) ** 2, axis=-1)
 
 
-def screen(m, sx, sy, target_net, hidden_gains, iters=10, n_prop=4096, k=64, seed=0):
-    """Surrogate-screened search for the hidden gains of a twin target."""
-    from . import Net, topk
+class Judge:
+    """k + 1 copies of the target network in one batch (member ids 0 .. k, so
+    each copy draws its own background): copies 0 .. k-1 simulate k gain
+    proposals, copy k is the twin (one window at unit gains, then one at
+    the given gains)."""
+
+    def __init__(self, target_net, k, S: Setup):
+        from . import Net
+        copies = []
+        for c in range(k + 1):
+            cp = dataclasses.replace(target_net)
+            cp.member = c
+            copies.append(cp)
+        self.k, self.S = k, S
+        self.net = Net.batch(copies, record_steps=2 * S.window, stream=_stream())
+
+    def __call__(self, G, twin_gains=None):
+        S, k = self.S, self.k
+        full = np.ones((k + 1, S.regions, 4), dtype=np.float32)
+        full[:k] = np.asarray(G, np.float32).reshape(k, S.regions, 4)
+        if twin_gains is not None:
+            full[k] = twin_gains
+        self.net.reset()
+        self.net.set_gains(np.ones(((k + 1) * S.regions, 4), dtype=np.float32))
+        self.net.run(S.window)
+        base = window_rates(self.net, S)
+        self.net.set_gains(full.reshape(-1, 4))
+        self.net.run(S.window)
+        return window_rates(self.net, S), 1e3 * self.net.bold().reshape(k + 1, S.regions), base
+
+    def close(self):
+        self.net.close()
+
+
+def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096, k=64, seed=0, judge=None,
+           shrink=0.85):
+    """Surrogate-screened search for the hidden gains of a twin target:
+    Gaussian proposals around the best simulated proposal so far, their
+    spread shrinking by `shrink` per iteration (a plain elitist search
+    standing in for the paper's assimilation filter)."""
+    from . import topk
     rng = np.random.default_rng(seed)
-    R = R_POP
-    twin = Net.batch([target_net], record_steps=2 * SEG, stream=_stream())
-    twin.set_gains(hidden_gains.reshape(-1, 4))
-    twin.run(2 * SEG)
-    t_rates = twin.region_rates(SEG, 2 * SEG)
-    t_bold = 1e3 * twin.bold()
-    twin.close()
-    copies = []
-    for c in range(k):
-        nw = target_net
-        cp = type(nw)(**{f: getattr(nw, f) for f in nw.__dataclass_fields__})
-        cp.member = c
-        copies.append(cp)
-    judge = Net.batch(copies, record_steps=2 * SEG, stream=_stream())
+    R = S.regions
+    own = judge is None
+    judge = judge or Judge(target_net, k, S)
+    # the twin: the judge batch's last copy, run at the hidden gains
+    rs, bs, base = judge(np.ones((k, R, 4), dtype=np.float32), twin_gains=hidden_gains)
+    t_rates, t_bold, prev = rs[k].copy(), bs[k].copy(), base[k].copy()
     sr, sb = sy.sd[:R], sy.sd[R:]
-
-    def simulate(G):
-        judge.reset()
-        judge.set_gains(G.reshape(-1, 4))
-        judge.run(2 * SEG)
-        rates = judge.region_rates(SEG, 2 * SEG).reshape(k, R)
-        bold = 1e3 * judge.bold().reshape(k, R)
-        return rates, bold
-
     mu = np.ones((R, 4), dtype=np.float32)
-    prev = simulate(np.repeat(mu[None], k, 0))[0].mean(0)
+    best_fit = np.inf
     hist = []
     for it in range(iters):
-        props = np.clip(mu[None] + rng.normal(0, GAIN_SD, (n_prop, R, 4)), 0.0, None).astype(np.float32)
+        sd = GAIN_SD * shrink ** it
+        props = np.clip(mu[None] + rng.normal(0, sd, (n_prop, R, 4)), 0.0, None).astype(np.float32)
         X = np.concatenate([props.reshape(n_prop, -1), np.repeat(prev[None], n_prop, 0)], axis=1)
+        import torch
+        torch.cuda.synchronize()
         tic = time.perf_counter()
         P = sy.inv(m.forward(sx.f(X)))
         score = _fit(P[:, :R], P[:, R:], t_rates, t_bold, sr, sb).astype(np.float32)
         best = topk(score, k)
         t_screen = time.perf_counter() - tic
         tic = time.perf_counter()
-        rs, bs = simulate(props[best])
+        rs, bs, _ = judge(props[best])
+        rs, bs = rs[:k], bs[:k]
         t_sim = time.perf_counter() - tic
         fit_s = _fit(rs, bs, t_rates, t_bold, sr, sb)
         rnd = rng.choice(n_prop, k, replace=False)
-        rr, br = simulate(props[rnd])
+        rr, br, _ = judge(props[rnd])
+        rr, br = rr[:k], br[:k]
         fit_r = _fit(rr, br, t_rates, t_bold, sr, sb)
         pb = P[best][:, R:]
         corr_pred = np.array([np.corrcoef(pb[i], t_bold)[0, 1] for i in range(k)])
         corr_sim = np.array([np.corrcoef(bs[i], t_bold)[0, 1] for i in range(k)])
         corr_ps = np.array([np.corrcoef(pb[i], bs[i])[0, 1] for i in range(k)])
         j = int(np.argmin(fit_s))
-        mu = props[best[j]]
-        prev = rs[j]
+        if fit_s[j] < best_fit:  # the proposal mean follows the best simulated fit so far
+            best_fit = float(fit_s[j])
+            mu = props[best[j]]
         gain_err = float(np.sqrt(np.mean((mu - hidden_gains) ** 2)))
-        rec = {"iter": it, "best_fit_surrogate": float(fit_s.min()), "mean_fit_surrogate": float(fit_s.mean()),
+        rec = {"iter": it, "proposal_sd": sd, "best_fit_so_far": best_fit,
+               "best_fit_surrogate": float(fit_s.min()), "mean_fit_surrogate": float(fit_s.mean()),
                "best_fit_random": float(fit_r.min()), "mean_fit_random": float(fit_r.mean()),
-               "bold_corr_error": float(np.mean(np.abs(corr_pred - corr_sim))),
+               "bold_corr_error": float(np.nanmean(np.abs(corr_pred - corr_sim))),
                "corr_pred_vs_sim": float(np.nanmean(corr_ps)), "gain_rmse": gain_err,
                "screen_s": t_screen, "simulate_s": t_sim,
                "speedup_per_proposal": (t_sim / k) / (t_screen / n_prop)}
         hist.append(rec)
         log(f"[screen] {json.dumps(rec)}")
-    judge.close()
+    if own:
+        judge.close()
     return hist
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--members", type=int, default=64)
-    ap.add_argument("--runs", type=int, default=80)
-    ap.add_argument("--segments", type=int, default=10)
-    ap.add_argument("--test-runs", type=int, default=8)
-    ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--window", type=int, default=400)
+    ap.add_argument("--runs", type=int, default=192)
+    ap.add_argument("--test-runs", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--iters", type=int, default=8)
     ap.add_argument("--seeds", type=str, default="0,1,2")
     ap.add_argument("--target-n", type=int, default=200_000)
     ap.add_argument("--out", type=str, default="")
@@ -199,29 +247,32 @@ def main(argv=None):
     import netgen
     from . import Net
 
+    S = Setup(members=a.members, window=a.window, target_n=a.target_n)
     t0 = time.time()
-    sizes = netgen.ensemble_sizes(a.members)
-    gains_seed = np.random.default_rng(32)
-    members = member_networks(sizes)
-    net = Net.batch(members, record_steps=2 * SEG, stream=_stream())
+    members = member_networks(S)
+    net = Net.batch(members, record_steps=2 * S.window, stream=_stream())
     del members
-    log(f"[data] ensemble: {net.n} neurons, {len(sizes)} members, built in {time.time() - t0:.1f}s")
+    log(f"[data] ensemble: {net.n} neurons, {net.n_members} members, built in {time.time() - t0:.1f}s")
     tic = time.perf_counter()
-    X, Y = generate(net, a.runs, a.segments, gains_seed)
+    X, Y = generate(net, S, a.runs, np.random.default_rng(32))
     gen_s = time.perf_counter() - tic
-    Xt, Yt = generate(net, a.test_runs, a.segments, np.random.default_rng(33))
+    Xt, Yt = generate(net, S, a.test_runs, np.random.default_rng(33))
     net.close()
     tic = time.perf_counter()
     m, sx, sy = train(X, Y, epochs=a.epochs)
     train_s = time.perf_counter() - tic
-    err = evaluate(m, sx, sy, Xt, Yt)
+    err = evaluate(m, sx, sy, Xt, Yt, S.regions)
     log(f"[train] held-out error: {json.dumps(err)}")
-    rep = {"samples": int(len(X)), "test_samples": int(len(Xt)), "generate_s": gen_s, "train_s": train_s,
-           "held_out": err, "screen": {}}
-    target = netgen.make_network(netgen.ensemble_member_spec(41, a.target_n, rate_hz=15, n_regions=R_POP))
+    rep = {"setup": dataclasses.asdict(S), "samples": int(len(X)), "test_samples": int(len(Xt)),
+           "generate_s": gen_s, "train_s": train_s, "held_out": err, "screen": {}}
+    target = netgen.make_network(netgen.ensemble_member_spec(41, S.target_n, rate_hz=S.rate_hz,
+                                                             n_regions=S.regions))
+    judge = Judge(target, 64, S)
     for s in [int(x) for x in a.seeds.split(",")]:
-        hidden = np.clip(np.random.default_rng(41 + s).normal(1.0, GAIN_SD, (R_POP, 4)), 0, None).astype(np.float32)
-        rep["screen"][str(s)] = screen(m, sx, sy, target, hidden, iters=a.iters, seed=s)
+        hidden = np.clip(np.random.default_rng(41 + s).normal(1.0, GAIN_SD, (S.regions, 4)), 0,
+                         None).astype(np.float32)
+        rep["screen"][str(s)] = screen(m, sx, sy, target, hidden, S, iters=a.iters, seed=s, judge=judge)
+    judge.close()
     H = [r for h in rep["screen"].values() for r in h]
     rep["summary"] = {
         "mean_best_fit_surrogate": float(np.mean([r["best_fit_surrogate"] for r in H])),
@@ -231,6 +282,8 @@ def main(argv=None):
         "bold_corr_error": float(np.mean([r["bold_corr_error"] for r in H])),
         "corr_pred_vs_sim": float(np.mean([r["corr_pred_vs_sim"] for r in H])),
         "speedup_per_proposal": float(np.median([r["speedup_per_proposal"] for r in H])),
+        "final_gain_rmse": {k: h[-1]["gain_rmse"] for k, h in rep["screen"].items()},
+        "final_best_fit": {k: h[-1]["best_fit_so_far"] for k, h in rep["screen"].items()},
     }
     log(f"[summary] {json.dumps(rep['summary'])}")
     if a.out:

@@ -172,6 +172,7 @@ dtb_status validate(const dtb_desc* s) {
   if (s->record_steps < 1) return fail(DTB_ERR_INVALID, "record_steps must be >= 1");
   if (s->gather_bundle_syn != 0 && (s->gather_bundle_syn < 4096 || s->gather_bundle_syn > kBundleMaxSyn))
     return fail(DTB_ERR_INVALID, "gather_bundle_syn must be 0 or in [4096, 2^20-1]");
+  if (s->gather_unroll < 0 || s->gather_unroll > 3) return fail(DTB_ERR_INVALID, "gather_unroll must be 0 .. 3");
   if (!(s->dt_ms > 0.f) || !finite_f(s->dt_ms)) return fail(DTB_ERR_INVALID, "dt_ms must be finite and > 0");
   for (int u = 0; u < 4; ++u) {
     if (!(s->tau_ms[u] > 0.f) || !finite_f(s->tau_ms[u]))
@@ -305,6 +306,14 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     while (c > 0 && c < kTile) {
       T.push_back(pad);
       ++c;
+    }
+    // store each tile plane-major: lane l of a wavefront holds sorted entries
+    // l, 64 + l, 128 + l, 192 + l, so each of its four bitmap loads covers 64
+    // consecutive sources
+    uint32_t tmp[kTile];
+    for (size_t t0 = 0; t0 < T.size(); t0 += kTile) {
+      for (int e = 0; e < kTile; ++e) tmp[(e & 63) * 4 + (e >> 6)] = T[t0 + e];
+      std::copy(tmp, tmp + kTile, T.begin() + t0);
     }
   });
   int64_t ntiles = 0;
@@ -452,6 +461,7 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
   d.n_ptypes = desc->n_ptypes;
   d.member = desc->member;
   d.wtype = desc->wtype;
+  d.unroll = desc->gather_unroll ? desc->gather_unroll : kGatherUnroll;
   d.rec = desc->record_steps;
   d.slots = std::max(d.rec, d.max_delay) + 1;
   d.bg_w = desc->bg_w;

@@ -24,8 +24,9 @@ constexpr int kCompactBlock = 256;  // threads of the compaction kernel
 //  * the weight stream, in CSR order (= the fixed summation order), the sign
 //    bit marking an inhibitory presynaptic neuron;
 //  * the lookup stream: the same synapses sorted by (delay, source), cut into
-//    tiles of 256 entries (a wavefront loads one tile as one 16-byte load per
-//    lane: lane l holds entries 4l .. 4l+3).  Entry = source delta (12 bits,
+//    tiles of 256 entries stored plane-major (a wavefront loads one tile as
+//    one 16-byte load per lane: lane l holds sorted entries l, 64+l, 128+l,
+//    192+l).  Entry = source delta (12 bits,
 //    relative to the previous entry of the tile; the first entry has delta 0)
 //    << 20 | position of the synapse in the bundle's CSR range (20 bits).
 //    Padding entries (the tail of a tile) have delta 0 and position nsyn,
@@ -38,20 +39,18 @@ constexpr uint32_t kMaxDelta = (1u << (32 - kPosBits)) - 1u;  // 4095
 constexpr int64_t kBundleMaxSyn = int64_t(kPosMask);         // synapses 0 .. 2^20 - 2, padding at nsyn
 constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap words of the largest bundle
 
-// Gather launch shape: threads per workgroup, tiles per wavefront per round
-// (per register set) and the wavefronts per SIMD the register allocation
-// must allow.  The default bundle fills the LDS hit bitmap (128 KB of the
-// CU's 160 KB), one 1024-thread workgroup per CU; four rounds of tiles and
-// two of bitmap words per wavefront are in registers at a time.  DTB_GATHER_NT selects
-// non-temporal loads for the data each step reads once.
+// Gather launch shape: threads per workgroup, the default lookup tiles per
+// wavefront per round (the kernel is compiled for 1, 2 and 3; the handle
+// picks one) and whether the data each step reads once is loaded
+// non-temporally.  The default bundle fills the LDS hit bitmap (128 KB of
+// the CU's 160 KB): one 1024-thread workgroup per CU.  With one tile per
+// round the kernel fits 64 VGPRs, so two workgroups share a CU when their
+// bundles leave the LDS for it.
 #ifndef DTB_GATHER_THREADS
 #define DTB_GATHER_THREADS 1024
 #endif
 #ifndef DTB_GATHER_UNROLL
 #define DTB_GATHER_UNROLL 3
-#endif
-#ifndef DTB_GATHER_WAVES_PER_EU
-#define DTB_GATHER_WAVES_PER_EU 4
 #endif
 #ifndef DTB_GATHER_NT
 #define DTB_GATHER_NT 1
@@ -61,7 +60,6 @@ constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap w
 #endif
 constexpr int kGatherThreads = DTB_GATHER_THREADS;
 constexpr int kGatherUnroll = DTB_GATHER_UNROLL;
-constexpr int kGatherWavesPerEU = DTB_GATHER_WAVES_PER_EU;
 constexpr int64_t kBundleDefaultSyn = DTB_GATHER_BUNDLE_SYN;
 static_assert(kBundleDefaultSyn <= kBundleMaxSyn, "bundle positions are 20 bits");
 
@@ -91,6 +89,7 @@ struct DeviceNet {
   int64_t n = 0, n_pad = 0, words = 0, words_pad = 0, nnz = 0;
   int32_t n_regions = 0, max_delay = 0, n_ptypes = 0, member = 0;
   int32_t wtype = 0, rec = 0;       // rec = record_steps
+  int32_t unroll = 3;               // gather lookup tiles per wavefront per round (1 .. 3)
   int32_t slots = 0;                // spike-bitmap ring slots: max(rec, D) + 1
   int32_t poisson_K = 0, poisson_cap = 1;
   int64_t compact_blocks = 0;

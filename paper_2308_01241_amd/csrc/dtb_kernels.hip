@@ -298,21 +298,26 @@ __device__ inline void stream_store(T* p, T v) {
 }
 
 // One round of delivery tests over kU tiles already in registers: rebuild
-// the sources (wavefront prefix sum of the deltas on top of the tile's first
-// source) and issue the kU x 4 bitmap loads.
+// the sources (a wavefront prefix sum of the deltas per plane of 64 entries,
+// on top of the tile's first source) and issue the kU x 4 bitmap loads, each
+// over 64 consecutive sources.
 template <int kU>
 __device__ inline void gather_lookups(const u32x4 (&tv)[kU], const uint32_t (&h)[kU], const uint32_t* bitmaps,
                                       int64_t words_pad, int32_t t_mod, int32_t slots, uint32_t wmax,
                                       uint32_t (&src)[kU][4], uint32_t (&word)[kU][4]) {
 #pragma unroll
   for (int u = 0; u < kU; ++u) {
-    const uint32_t d0 = tv[u].x >> kPosBits, d1 = tv[u].y >> kPosBits, d2 = tv[u].z >> kPosBits,
-                   d3 = tv[u].w >> kPosBits;
-    const uint32_t incl = wave_incl_scan_dpp(d0 + d1 + d2 + d3);
-    src[u][3] = (h[u] & 0x3FFFFFFu) + incl;  // the lane's last source
-    src[u][2] = src[u][3] - d3;
-    src[u][1] = src[u][2] - d2;
-    src[u][0] = src[u][1] - d1;
+    // plane c holds sorted entries 64 c .. 64 c + 63, one per lane
+    const uint32_t e[4] = {tv[u].x, tv[u].y, tv[u].z, tv[u].w};
+    uint32_t incl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) incl[c] = wave_incl_scan_dpp(e[c] >> kPosBits);
+    uint32_t base = h[u] & 0x3FFFFFFu;  // the tile's first source
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      src[u][c] = base + incl[c];
+      base += uint32_t(__builtin_amdgcn_readlane(int(incl[c]), 63));  // the plane's total
+    }
     // spikes of step t - d + 1 arrive now; steps before 0 map to unwritten (zero) slots
     int32_t slot = t_mod - int32_t(h[u] >> 26);
     if (slot < 0) slot += slots;
@@ -344,8 +349,8 @@ __device__ inline void gather_hits(const u32x4 (&tv)[kU], const uint32_t (&src)[
   }
 }
 
-template <bool kBF16>
-__global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kGatherWavesPerEU)))
+template <bool kBF16, int kU>
+__global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kU == 1 ? 8 : 4)))
 void k_gather(
     int64_t n, int64_t n_bundles, int64_t n_pad, const int64_t* __restrict__ step,
     const Bundle* __restrict__ bundles, const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
@@ -377,7 +382,6 @@ void k_gather(
   // rotate (the loop body is four stages).  Tile indices past the end are
   // clamped to the last tile, which then is processed again (the OR is
   // idempotent), so every load is unconditional.
-  constexpr int kU = kGatherUnroll;
   constexpr int kS = (kGatherThreads / 64) * kU;  // tiles per round of the workgroup
   const int nt = B.ntiles;
   const u32x4* tp = reinterpret_cast<const u32x4*>(tiles + B.tile0 * kTile) + lane;
@@ -642,29 +646,48 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const DeviceNet& d, hipStream_t s) {
+namespace {
+
+template <bool kBF16, int kU>
+void launch_gather_as(const DeviceNet& d, hipStream_t s) {
   const unsigned grid = unsigned((d.n_bundles + 7) / 8 * 8);
   const size_t lds = size_t(d.hit_words) * 4;
-  if (d.wtype == DTB_W_BF16)
-    hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
-                       d.step, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
-                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
-  else
-    hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
-                       d.step, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad,
-                       d.slots, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
+  hipLaunchKernelGGL((k_gather<kBF16, kU>), dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
+                     d.step, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad, d.slots, d.j,
+                     d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
+}
+
+template <bool kBF16>
+hipError_t set_lds_limit_bf() {
+  const int bytes = kHitWords * 4;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kBF16, 1>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kBF16, 2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kBF16, 3>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
+}
+
+}  // namespace
+
+hipError_t launch_gather(const DeviceNet& d, hipStream_t s) {
+  const bool bf = d.wtype == DTB_W_BF16;
+  switch (d.unroll) {
+    case 1: bf ? launch_gather_as<true, 1>(d, s) : launch_gather_as<false, 1>(d, s); break;
+    case 2: bf ? launch_gather_as<true, 2>(d, s) : launch_gather_as<false, 2>(d, s); break;
+    default: bf ? launch_gather_as<true, 3>(d, s) : launch_gather_as<false, 3>(d, s); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t gather_set_lds_limit() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<false>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kHitWords * 4);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kHitWords * 4);
+  hipError_t e = set_lds_limit_bf<false>();
+  if (e == hipSuccess) e = set_lds_limit_bf<true>();
   return e;
 }
-
 
 hipError_t launch_finalize(const DeviceNet& d, hipStream_t s) {
   const float E0 = 0.34f;

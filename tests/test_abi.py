@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_bitmap_words(lib):
-    assert lib.dtb_abi_version() == 1
+    assert lib.dtb_abi_version() == 2
     assert [lib.dtb_bitmap_words(n) for n in (0, 1, 32, 33, 64)] == [0, 1, 1, 2, 2]
     assert isinstance(lib.dtb_last_error(), bytes)
 
@@ -86,6 +86,15 @@ def _mutations():
         n.ptype[0] = 1
     return [col_oob, delay_zero, delay_big, w_neg, w_nan, v0_inf, region_oob, rowptr_dec,
             reset_above, cap_zero, maxdelay_32, lam_big, tau_zero, inh_two, ptype_oob]
+
+
+@pytest.mark.parametrize("kw", [{"unroll": 4}, {"unroll": -1}, {"bundle_syn": 100}, {"bundle_syn": 1 << 20}],
+                         ids=lambda k: "_".join(f"{a}{b}" for a, b in k.items()))
+def test_invalid_launch_shapes_are_rejected(lib, kw):
+    from paper_2308_01241_amd import DtbError, Net
+    with pytest.raises(DtbError) as ei:
+        Net(_base(), **kw)
+    assert ei.value.status == -1
 
 
 @pytest.mark.parametrize("mut", _mutations(), ids=lambda f: f.__name__)
