@@ -52,11 +52,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gather_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) -> float:
-    """Algorithmic bytes of one gather launch: 5 B of index + delay per
-    synapse, the weight of each delivered event, the four gates read and
-    written (32 B per neuron) and the D+1 delayed spike bits per neuron."""
-    return 5.0 * nnz + w_bytes * events + 32.0 * n + n * (max_delay + 1) / 8.0
+def gather_bytes(nnz: int, n: int, max_delay: int) -> float:
+    """Algorithmic bytes of one launch of the delivery-test kernel: 5 B of
+    index + delay per synapse, the D+1 delayed spike bits per neuron, and
+    the one result bit per synapse it hands to the sums."""
+    return 5.0 * nnz + n * (max_delay + 1) / 8.0 + nnz / 8.0
+
+
+def sums_bytes(nnz: int, n: int, events: float, w_bytes: int) -> float:
+    """Algorithmic bytes of one launch of the sums kernel: row pointers
+    (8 B per row), the result bits, the weight of each delivered event and
+    the four gates read and written."""
+    return 8.0 * n + nnz / 8.0 + w_bytes * events + 32.0 * n
+
+
+def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) -> float:
+    """Algorithmic bytes of one whole step as the pull method needs them:
+    index + delay per synapse, the delivered weights, the neuron state read
+    and written with its parameter index, and the delayed spike bits."""
+    return 5.0 * nnz + w_bytes * events + n * (2 * 21 + 2) + n * (max_delay + 1) / 8.0
 
 
 def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0)):
@@ -319,14 +333,20 @@ def main():
     head = res[rates[0]]
     n_neu, n_syn, n_del = net.n, net.nnz, net.max_delay
     wb = 2 if args.wtype == "bf16" else 4
-    kg = head["kernels"]["gather"]
-    g_ms = kg["ms"] / max(1, kg["launches"])
+    per = {k: v["ms"] / max(1, v["launches"]) for k, v in head["kernels"].items()}
     ev_step = head["events"] / args.steps
-    B = gather_bytes(n_syn, n_neu, n_del, ev_step, wb)
-    achieved = B / (g_ms * 1e-3) / 1e9
+    B = gather_bytes(n_syn, n_neu, n_del)
+    achieved = B / (per["gather"] * 1e-3) / 1e9
+    Bs = sums_bytes(n_syn, n_neu, ev_step, wb)
+    Bt = step_bytes(n_syn, n_neu, n_del, ev_step, wb)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_gather",
-            "algorithmic_bytes_per_launch": B, "avg_launch_ms": g_ms}
+            "algorithmic_bytes_per_launch": B, "avg_launch_ms": per["gather"],
+            "sums": {"algorithmic_bytes_per_launch": Bs, "avg_launch_ms": per["sums"],
+                     "achieved": round(Bs / (per["sums"] * 1e-3) / 1e9, 1)},
+            "step": {"algorithmic_bytes": Bt, "ms": head["ms_per_step"],
+                     "achieved": round(Bt / (head["ms_per_step"] * 1e-3) / 1e9, 1),
+                     "frac": round(Bt / (head["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     forms = {}
     if not args.no_forms and args.wtype == "f32":
         r0 = rates[0]

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 2
+#define DTB_ABI_VERSION 3
 
 typedef enum {
   DTB_OK = 0,
@@ -192,8 +192,9 @@ dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int6
  * Sec. VI-C): while enabled, every kernel launch of dtb_step is bracketed by
  * a pair of hipEvents recorded on the handle's stream.  dtb_read_timing
  * synchronizes, returns the summed durations in ms and the number of timed
- * launches per kernel, in the order neuron update, compaction, gather,
- * finalize (double [4], int64 [4]; either may be NULL), and clears them. */
+ * launches per kernel, in the order neuron update, compaction, gather
+ * (delivery tests), sums (per-row sums, background, gates), finalize
+ * (double [5], int64 [5]; either may be NULL), and clears them. */
 dtb_status dtb_set_timing(dtb_net* net, int enable);
 dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches);
 

@@ -99,7 +99,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 2:
+    if lib.dtb_abi_version() != 3:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

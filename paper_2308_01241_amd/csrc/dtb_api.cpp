@@ -123,8 +123,8 @@ struct dtb_net {
   int32_t graph_steps = 0;
   // kernel timing: event pairs per kernel kind, reused after each read
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[4];
-  size_t ev_used[4] = {0, 0, 0, 0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kTimedKernels];
+  size_t ev_used[kTimedKernels] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -316,20 +316,35 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
       std::copy(tmp, tmp + kTile, T.begin() + t0);
     }
   });
-  int64_t ntiles = 0;
+  int64_t ntiles = 0, hwords = 0;
   int32_t hw = 2 * (kGatherThreads / 64);  // the block totals reuse the hit bitmap's words
   for (int64_t q = 0; q < nb; ++q) {
     bl[q].tile0 = ntiles;
     bl[q].ntiles = int32_t(bheads[q].size());
+    bl[q].hbit0 = 32 * hwords;  // each bundle's hit words start on a word of their own
+    hwords += (bl[q].nsyn >> 5) + 1;
     ntiles += bl[q].ntiles;
     hw = std::max(hw, int32_t(bl[q].nsyn >> 5) + 1);
   }
   d.n_bundles = nb;
   d.n_tiles = ntiles;
   d.hit_words = hw;
+  d.hit_total_words = hwords;
+  // the bundle of each 1024-row block's first row (bundles are consecutive row ranges)
+  const int64_t nblk = (n + 1023) / 1024;
+  std::vector<int32_t> blk(size_t(std::max<int64_t>(1, nblk)), 0);
+  {
+    int64_t q = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+      while (bl[q].row1 <= b * 1024) ++q;
+      blk[b] = int32_t(q);
+    }
+  }
   dtb_status st;
   const size_t wsz = d.wtype == DTB_W_BF16 ? 2 : 4;
   if ((st = dalloc(net, &d.bundles, nb)) || (st = dalloc(net, &d.tiles, std::max<int64_t>(1, ntiles) * kTile)) ||
+      (st = dalloc(net, &d.hitbuf, std::max<int64_t>(1, hwords))) ||
+      (st = dalloc(net, &d.block_bundle, int64_t(blk.size()))) ||
       (st = dalloc(net, &d.theads, std::max<int64_t>(1, ntiles))) || (st = dalloc(net, &d.row_ptr, n + 1)))
     return st;
   {
@@ -343,6 +358,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     d.wts = q;
   }
   if ((st = upload(net, d.bundles, bl.data(), nb * sizeof(Bundle))) ||
+      (st = upload(net, d.block_bundle, blk.data(), blk.size() * sizeof(int32_t))) ||
       (st = upload(net, d.row_ptr, s->row_ptr, (n + 1) * sizeof(int64_t))))
     return st;
   for (int64_t q = 0; q < nb; ++q) {
@@ -708,7 +724,7 @@ dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches) {
   if (st) return st;
   hipError_t e = hipStreamSynchronize(net->stream);
   if (e != hipSuccess) return hip_fail(net, e, "hipStreamSynchronize");
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kTimedKernels; ++k) {
     double sum = 0.0;
     for (size_t q = 0; q < net->ev_used[k]; ++q) {
       float x = 0.f;
@@ -739,7 +755,8 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
     hipError_t e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
     if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
     if (e == hipSuccess) e = timed(net, 2, [&] { return launch_gather(d, net->stream); });
-    if (e == hipSuccess) e = timed(net, 3, [&] { return launch_finalize(d, net->stream); });
+    if (e == hipSuccess) e = timed(net, 3, [&] { return launch_sums(d, net->stream); });
+    if (e == hipSuccess) e = timed(net, 4, [&] { return launch_finalize(d, net->stream); });
     if (e != hipSuccess) return hip_fail(net, e, "kernel launch");
     net->t = t + 1;
   }
@@ -764,6 +781,7 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
       e = launch_neuron_update(d, nullptr, net->stream);
       if (e == hipSuccess) e = launch_compact(d, net->stream);
       if (e == hipSuccess) e = launch_gather(d, net->stream);
+      if (e == hipSuccess) e = launch_sums(d, net->stream);
       if (e == hipSuccess) e = launch_finalize(d, net->stream);
     }
     hipGraph_t g = nullptr;

@@ -59,6 +59,7 @@ constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap w
 #define DTB_GATHER_BUNDLE_SYN 1048575
 #endif
 constexpr int kGatherThreads = DTB_GATHER_THREADS;
+constexpr int kTimedKernels = 5;  // neuron update, compaction, gather, sums, finalize
 constexpr int kGatherUnroll = DTB_GATHER_UNROLL;
 constexpr int64_t kBundleDefaultSyn = DTB_GATHER_BUNDLE_SYN;
 static_assert(kBundleDefaultSyn <= kBundleMaxSyn, "bundle positions are 20 bits");
@@ -73,6 +74,7 @@ struct Bundle {
   int64_t tile0;        // first tile of the bundle's lookup stream
   int32_t ntiles;       // tiles of the lookup stream
   int32_t nsyn;         // synapses of the bundle
+  int64_t hbit0;        // bit of the hit buffer that holds the bundle's synapse 0 (a multiple of 32)
 };
 
 // Derived per-type constants in the order the neuron update reads them.
@@ -115,6 +117,10 @@ struct DeviceNet {
   uint32_t* tiles = nullptr;        // [n_tiles][kTile] lookup entries
   uint32_t* theads = nullptr;       // [n_tiles] tile headers
   Bundle* bundles = nullptr;        // [n_bundles]
+  int32_t* block_bundle = nullptr;  // [ceil(n / 1024)] bundle of each 1024-row block's first row
+  uint32_t* hitbuf = nullptr;       // [hit_total_words] delivery-test results: per bundle, one bit per
+                                    // synapse in CSR order (from bit hbit0), rewritten every step
+  int64_t hit_total_words = 0;
   // history and outputs
   uint32_t* raster = nullptr;       // [slots][words_pad] spike bitmaps: the delay ring
   int32_t* counts = nullptr;        // [slots][n_regions]
@@ -138,6 +144,7 @@ struct DeviceNet {
 // captured once and replayed; k_finalize (last of a step) advances it.
 hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s);
 hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
+hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
 hipError_t launch_gather(const DeviceNet& d, hipStream_t s);
 hipError_t launch_finalize(const DeviceNet& d, hipStream_t s);
 hipError_t gather_set_lds_limit();

@@ -7,12 +7,14 @@
 //                    bitmaps), per-population spike counts;
 //   k_compact        ascending spike-id list from the bitmap (ballot
 //                    popcounts, block scan, decoupled look-back);
-//   k_gather         pull over each row's in-edges through the delay ring
-//                    (J_intra) - delivery tests in (delay, source) order,
-//                    sums in each row's CSR order - plus the Poisson count
-//                    that stands in for the spikes of other partitions
-//                    (J_inter), then the gate update (jump + exact decay);
-//   k_finalize       per-step event totals.
+//   k_gather         delivery tests of the pull over each row's in-edges
+//                    through the delay ring (J_intra), in (delay, source)
+//                    order, into a hit bitmap per bundle;
+//   k_sums           per row: delivered weights in CSR order, the Poisson
+//                    count that stands in for the spikes of other
+//                    partitions (J_inter), the gate update (jump + exact
+//                    decay);
+//   k_finalize       per-step event totals, BOLD, ring slot, step counter.
 //
 // Everything is FP32 except the integer work (ids, delays, ballots, counts,
 // RNG).  The file is compiled with -ffp-contract=off: every fused
@@ -249,21 +251,22 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
 }
 
 // ------------------------------------------------------------------ gather
-// One workgroup (16 wavefronts) per bundle of rows.
-//  Phase 1 - delivery tests.  The bundle's lookup stream is sorted by
-//    (delay, source); a wavefront takes one 64-entry tile per load, rebuilds
-//    the sources by a prefix sum of the 12-bit deltas, reads the spike bit of
-//    step t - d + 1 from that step's bitmap (monotone addresses, so the
-//    cache lines of the bitmaps are swept rather than hit at random) and
-//    sets the synapse's bit in the LDS hit bitmap (integer OR: order-free).
-//  Phase 2 - sums.  Each lane takes rows of the bundle; for a row it visits
-//    the set hit bits in ascending position, which is the row's CSR order,
-//    loads only those weights and accumulates E and I in FP32 - the fixed
-//    per-neuron summation order - then adds the background count and
-//    updates the four gates.
-// Workgroups are mapped XCD-aware: the blocks an XCD receives (blockIdx
-// congruent mod 8) take a contiguous range of bundles, so bundles of the
-// same population (same source set) share that XCD's L2.
+// The pull over each row's in-edges (J_intra) in two kernels.
+//  k_gather - delivery tests, one workgroup (16 wavefronts) per bundle of
+//    rows.  The bundle's lookup stream is sorted by (delay, source); a
+//    wavefront takes 256-entry tiles, rebuilds the sources by prefix sums of
+//    the 12-bit deltas, reads the spike bit of step t - d + 1 from that
+//    step's slot of the delay ring (monotone addresses, so the cache lines
+//    of the bitmaps are swept rather than hit at random) and sets the
+//    synapse's bit in the LDS hit bitmap (integer OR: order-free).  The
+//    finished bitmap goes to the hit buffer in one coalesced pass.
+//  k_sums - one thread per row visits the row's set hit bits in ascending
+//    position, which is its CSR order, loads only those weights and
+//    accumulates E and I in FP32 - the fixed per-neuron summation order -
+//    then adds the background count and updates the four gates.
+// Gather workgroups are mapped XCD-aware: the blocks an XCD receives
+// (blockIdx congruent mod 8) take a contiguous range of bundles, so bundles
+// of the same population (same source set) share that XCD's L2.
 // Inclusive prefix sum over the 64 lanes of a wavefront with DPP row shifts
 // (within each 16-lane row) and the row broadcasts of lanes 15 and 31.
 __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
@@ -349,17 +352,13 @@ __device__ inline void gather_hits(const u32x4 (&tv)[kU], const uint32_t (&src)[
   }
 }
 
-template <bool kBF16, int kU>
+template <int kU>
 __global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kU == 1 ? 8 : 4)))
-void k_gather(
-    int64_t n, int64_t n_bundles, int64_t n_pad, const int64_t* __restrict__ step,
-    const Bundle* __restrict__ bundles, const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
-    const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v, const uint32_t* __restrict__ bitmaps,
-    int64_t words_pad, int32_t slots, float* __restrict__ j, float a0, float a1, float a2, float a3,
-    float bg_w, const uint32_t* __restrict__ poisson, int K, int64_t* __restrict__ ev_ring,
-    int32_t* __restrict__ bad) {
+void k_gather(int64_t n_bundles, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
+              const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
+              const uint32_t* __restrict__ bitmaps, int64_t words_pad, int32_t slots,
+              uint32_t* __restrict__ hitbuf, int64_t* __restrict__ ev_ring) {
   extern __shared__ uint32_t s_hits[];
-  const int64_t t = step[0];
   const int32_t t_mod = int32_t(step[1]);
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(t_mod) * kStripes * 2;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -440,58 +439,85 @@ void k_gather(
   }
   __syncthreads();
 
-  // ---- phase 2: sums in CSR order, background, gates
-  // Rows are software-pipelined: the next row's CSR bounds and gates are
-  // loaded while the current row is summed.  A row's hit positions are
-  // collected first (up to kHitBatch at a time) so their weight loads issue
-  // together; the adds then run in ascending position, the row's CSR order.
+  // ---- hand the delivery tests to the sums: the bundle's hit words, and
+  // the delivered events (set bits below the padding bit at nsyn)
+  uint32_t ev = 0;
+  uint32_t* __restrict__ dst = hitbuf + (B.hbit0 >> 5);
+  for (int q = tid; q < hw; q += kGatherThreads) {
+    const uint32_t w = s_hits[q];
+    stream_store(dst + q, w);
+    ev += uint32_t(__popc(q == hw - 1 ? w & ((1u << (B.nsyn & 31)) - 1u) : w));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ev += __shfl_down(ev, off);
+  __syncthreads();  // every hit word is read
+  if (lane == 0) s_hits[tid >> 6] = ev;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t r = 0;
+    for (int w = 0; w < kGatherThreads / 64; ++w) r += s_hits[w];
+    int64_t* dsts = ev_slot + 2 * (blockIdx.x & (kStripes - 1));
+    if (r) atomicAdd(reinterpret_cast<unsigned long long*>(dsts), (unsigned long long)r);
+  }
+}
+
+// ------------------------------------------------------------------- sums
+// One thread per neuron (row): the delivered weights in the row's CSR order
+// (the fixed per-neuron summation order), then the background count
+// (Philox4x64-10, counter (t, i, member, 0) with i the neuron's index inside
+// its member network), then the four gates (exact decay + jump).  The row's
+// delivery tests are the bits hbit0 + (k - syn0) of its bundle in the hit
+// buffer.
+constexpr int kSumsThreads = 1024;
+
+template <bool kBF16>
+__global__ __launch_bounds__(kSumsThreads) void k_sums(
+    int64_t n, int64_t n_pad, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
+    const int32_t* __restrict__ block_bundle, const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v,
+    const uint32_t* __restrict__ hitbuf, float* __restrict__ j, float a0, float a1, float a2, float a3,
+    float bg_w, const uint32_t* __restrict__ poisson, int K, int64_t* __restrict__ ev_ring,
+    int32_t* __restrict__ bad) {
+  __shared__ uint32_t s_bg[kSumsThreads / 64];
+  const int64_t t = step[0];
+  int64_t* __restrict__ ev_slot = ev_ring + int64_t(step[1]) * kStripes * 2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int64_t r = int64_t(blockIdx.x) * kSumsThreads + tid;
   constexpr int kHitBatch = 8;
-  uint32_t ev = 0, evb = 0;
   const float* wf = reinterpret_cast<const float*>(wts_v);
   const uint16_t* wb = reinterpret_cast<const uint16_t*>(wts_v);
-  int64_t r = B.row0 + tid;
-  int64_t k0n = 0, k1n = 0;
-  float jn0 = 0.f, jn1 = 0.f, jn2 = 0.f, jn3 = 0.f;
-  if (r < B.row1) {
-    k0n = stream_load(row_ptr + r) - B.syn0;
-    k1n = stream_load(row_ptr + r + 1) - B.syn0;
-    jn0 = stream_load(j + r);
-    jn1 = stream_load(j + n_pad + r);
-    jn2 = stream_load(j + 2 * n_pad + r);
-    jn3 = stream_load(j + 3 * n_pad + r);
-  }
-  for (; r < B.row1; r += kGatherThreads) {
-    const int k0 = int(k0n), k1 = int(k1n);
-    const float j0 = jn0, j1 = jn1, j2 = jn2, j3 = jn3;
-    const int64_t rn = r + kGatherThreads;
-    if (rn < B.row1) {
-      k0n = stream_load(row_ptr + rn) - B.syn0;
-      k1n = stream_load(row_ptr + rn + 1) - B.syn0;
-      jn0 = stream_load(j + rn);
-      jn1 = stream_load(j + n_pad + rn);
-      jn2 = stream_load(j + 2 * n_pad + rn);
-      jn3 = stream_load(j + 3 * n_pad + rn);
-    }
-    // background Poisson count: Philox4x64-10, key (seed, 0), counter (t, i, member, 0)
-    // with i the neuron's index inside its member network
-    const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - B.member_row0), uint64_t(B.member),
-                                                  0ull, B.seed, 0ull));
+  uint32_t evb = 0;
+  if (r < n) {
+    // the row's bundle: bundles are consecutive row ranges
+    int32_t b = block_bundle[blockIdx.x];
+    while (r >= bundles[b].row1) ++b;
+    const Bundle* B = bundles + b;
+    const int64_t k0 = row_ptr[r], k1 = row_ptr[r + 1];
+    const float j0 = j[r], j1 = j[n_pad + r], j2 = j[2 * n_pad + r], j3 = j[3 * n_pad + r];
+    const uint64_t seed = B->seed;
+    const int64_t mrow0 = B->member_row0;
+    const int32_t member = B->member;
+    const int64_t bit0 = B->hbit0 + (k0 - B->syn0);
+    const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - mrow0), uint64_t(member), 0ull,
+                                                  seed, 0ull));
     float dE = 0.f, dI = 0.f;
-    if (k1 > k0) {
-      int w = k0 >> 5;
-      const int w1 = (k1 - 1) >> 5;
-      uint32_t bits = s_hits[w] & (~0u << (k0 & 31));
+    const int len = int(k1 - k0);
+    if (len > 0) {
+      // bits [bit0, bit0 + len) of the hit buffer, visited in ascending order
+      int64_t w = bit0 >> 5;
+      const int64_t w1 = (bit0 + len - 1) >> 5;
+      uint32_t bits = hitbuf[w] & (~0u << (bit0 & 31));
+      const uint32_t last = ~0u >> (31 - int((bit0 + len - 1) & 31));
       while (true) {
-        // collect up to kHitBatch hit positions of this row, in ascending order
+        // collect up to kHitBatch hit offsets of this row, then load their weights together
         int hp[kHitBatch];
         int nh = 0;
         while (nh < kHitBatch) {
-          if (w == w1) bits &= ~0u >> (31 - ((k1 - 1) & 31));
+          if (w == w1) bits &= last;
           if (bits) {
-            hp[nh++] = w * 32 + __ffs(bits) - 1;
+            hp[nh++] = int((w << 5) + (__ffs(bits) - 1) - bit0);
             bits &= bits - 1u;
           } else if (w < w1) {
-            bits = s_hits[++w];
+            bits = hitbuf[++w];
           } else {
             break;
           }
@@ -500,8 +526,8 @@ void k_gather(
 #pragma unroll
         for (int q = 0; q < kHitBatch; ++q)
           if (q < nh)
-            x[q] = kBF16 ? uint32_t(stream_load(wb + B.syn0 + hp[q])) << 16
-                         : __float_as_uint(stream_load(wf + B.syn0 + hp[q]));
+            x[q] = kBF16 ? uint32_t(stream_load(wb + k0 + hp[q])) << 16
+                         : __float_as_uint(stream_load(wf + k0 + hp[q]));
 #pragma unroll
         for (int q = 0; q < kHitBatch; ++q) {
           if (q < nh) {
@@ -510,47 +536,32 @@ void k_gather(
             else dE += wv;
           }
         }
-        ev += uint32_t(nh);
         if (nh < kHitBatch) break;
       }
     }
     const int c = poisson_count(u, poisson, K);
-    evb += uint32_t(c);
+    evb = uint32_t(c);
     dE = __fmaf_rn(float(c), bg_w, dE);
     const float ja = __fmaf_rn(a0, j0, dE);
     const float jb = __fmaf_rn(a1, j1, dE);
     const float jc = __fmaf_rn(a2, j2, dI);
     const float jd = __fmaf_rn(a3, j3, dI);
-    stream_store(j + r, ja);
-    stream_store(j + n_pad + r, jb);
-    stream_store(j + 2 * n_pad + r, jc);
-    stream_store(j + 3 * n_pad + r, jd);
+    j[r] = ja;
+    j[n_pad + r] = jb;
+    j[2 * n_pad + r] = jc;
+    j[3 * n_pad + r] = jd;
     if (!(isfinite(ja) && isfinite(jb) && isfinite(jc) && isfinite(jd))) atomicOr(bad, 1);
   }
-  // block totals of delivered events, then one striped atomic per block;
-  // the wavefront totals reuse the first words of the hit bitmap
-  uint32_t e = ev, eb = evb;
+  // block total of background events, one striped atomic per block
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    e += __shfl_down(e, off);
-    eb += __shfl_down(eb, off);
-  }
-  __syncthreads();  // every row's hit words are read
-  uint32_t* s_ev = s_hits;
-  if (lane == 0) {
-    s_ev[2 * (tid >> 6)] = e;
-    s_ev[2 * (tid >> 6) + 1] = eb;
-  }
+  for (int off = 32; off > 0; off >>= 1) evb += __shfl_down(evb, off);
+  if (lane == 0) s_bg[tid >> 6] = evb;
   __syncthreads();
   if (tid == 0) {
-    int64_t r = 0, bgs = 0;
-    for (int w = 0; w < kGatherThreads / 64; ++w) {
-      r += s_ev[2 * w];
-      bgs += s_ev[2 * w + 1];
-    }
-    int64_t* dst = ev_slot + 2 * (blockIdx.x & (kStripes - 1));
-    if (r) atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)r);
-    if (bgs) atomicAdd(reinterpret_cast<unsigned long long*>(dst + 1), (unsigned long long)bgs);
+    int64_t tot = 0;
+    for (int q = 0; q < kSumsThreads / 64; ++q) tot += s_bg[q];
+    int64_t* dst = ev_slot + 2 * (blockIdx.x & (kStripes - 1)) + 1;
+    if (tot) atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)tot);
   }
 }
 
@@ -648,45 +659,49 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s) {
 
 namespace {
 
-template <bool kBF16, int kU>
+template <int kU>
 void launch_gather_as(const DeviceNet& d, hipStream_t s) {
   const unsigned grid = unsigned((d.n_bundles + 7) / 8 * 8);
   const size_t lds = size_t(d.hit_words) * 4;
-  hipLaunchKernelGGL((k_gather<kBF16, kU>), dim3(grid), dim3(kGatherThreads), lds, s, d.n, d.n_bundles, d.n_pad,
-                     d.step, d.bundles, d.tiles, d.theads, d.row_ptr, d.wts, d.raster, d.words_pad, d.slots, d.j,
-                     d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K, d.ev, d.bad);
-}
-
-template <bool kBF16>
-hipError_t set_lds_limit_bf() {
-  const int bytes = kHitWords * 4;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kBF16, 1>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kBF16, 2>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kBF16, 3>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  return e;
+  hipLaunchKernelGGL((k_gather<kU>), dim3(grid), dim3(kGatherThreads), lds, s, d.n_bundles, d.step, d.bundles,
+                     d.tiles, d.theads, d.raster, d.words_pad, d.slots, d.hitbuf, d.ev);
 }
 
 }  // namespace
 
 hipError_t launch_gather(const DeviceNet& d, hipStream_t s) {
-  const bool bf = d.wtype == DTB_W_BF16;
   switch (d.unroll) {
-    case 1: bf ? launch_gather_as<true, 1>(d, s) : launch_gather_as<false, 1>(d, s); break;
-    case 2: bf ? launch_gather_as<true, 2>(d, s) : launch_gather_as<false, 2>(d, s); break;
-    default: bf ? launch_gather_as<true, 3>(d, s) : launch_gather_as<false, 3>(d, s); break;
+    case 1: launch_gather_as<1>(d, s); break;
+    case 2: launch_gather_as<2>(d, s); break;
+    default: launch_gather_as<3>(d, s); break;
   }
   return hipGetLastError();
 }
 
 hipError_t gather_set_lds_limit() {
-  hipError_t e = set_lds_limit_bf<false>();
-  if (e == hipSuccess) e = set_lds_limit_bf<true>();
+  const int bytes = kHitWords * 4;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<1>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<2>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<3>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
   return e;
+}
+
+hipError_t launch_sums(const DeviceNet& d, hipStream_t s) {
+  const unsigned grid = unsigned((d.n + kSumsThreads - 1) / kSumsThreads);
+  if (d.wtype == DTB_W_BF16)
+    hipLaunchKernelGGL(k_sums<true>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, d.bundles,
+                       d.block_bundle, d.row_ptr, d.wts, d.hitbuf, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w,
+                       d.poisson, d.poisson_K, d.ev, d.bad);
+  else
+    hipLaunchKernelGGL(k_sums<false>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, d.bundles,
+                       d.block_bundle, d.row_ptr, d.wts, d.hitbuf, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w,
+                       d.poisson, d.poisson_K, d.ev, d.bad);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const DeviceNet& d, hipStream_t s) {
