@@ -289,6 +289,15 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     for (uint64_t kk : key) {
       const uint32_t kd = uint32_t(kk >> 46), src = uint32_t((kk >> 20) & 0x3FFFFFFu);
       const uint32_t pos = uint32_t(kk & kPosMask);
+      // a gap wider than one delta is bridged by skip entries (largest delta,
+      // aimed at the padding bit) while that is cheaper than a fresh tile
+      if (c > 0 && c < kTile && kd == d1 && src - prev > kMaxDelta && src - prev <= kMaxDelta * kMaxSkips) {
+        while (src - prev > kMaxDelta && c < kTile) {
+          T.push_back((kMaxDelta << kPosBits) | pad);
+          prev += kMaxDelta;
+          ++c;
+        }
+      }
       if (c == 0 || c == kTile || kd != d1 || src - prev > kMaxDelta) {
         while (c > 0 && c < kTile) {
           T.push_back(pad);
@@ -330,6 +339,20 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   d.n_tiles = ntiles;
   d.hit_words = hw;
   d.hit_total_words = hwords;
+  // contiguous bundle ranges per XCD with about equal numbers of tiles
+  int64_t xf[9];
+  {
+    xf[0] = 0;
+    int64_t acc = 0, q = 0;
+    for (int x = 1; x < 8; ++x) {
+      const int64_t goal = (ntiles * x + 7) / 8;
+      while (q < nb && acc + bl[q].ntiles <= goal) acc += bl[q++].ntiles;
+      xf[x] = q;
+    }
+    xf[8] = nb;
+    d.xcd_max = 0;
+    for (int x = 0; x < 8; ++x) d.xcd_max = std::max(d.xcd_max, xf[x + 1] - xf[x]);
+  }
   // the bundle of each 1024-row block's first row (bundles are consecutive row ranges)
   const int64_t nblk = (n + 1023) / 1024;
   std::vector<int32_t> blk(size_t(std::max<int64_t>(1, nblk)), 0);
@@ -344,7 +367,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   const size_t wsz = d.wtype == DTB_W_BF16 ? 2 : 4;
   if ((st = dalloc(net, &d.bundles, nb)) || (st = dalloc(net, &d.tiles, std::max<int64_t>(1, ntiles) * kTile)) ||
       (st = dalloc(net, &d.hitbuf, std::max<int64_t>(1, hwords))) ||
-      (st = dalloc(net, &d.block_bundle, int64_t(blk.size()))) ||
+      (st = dalloc(net, &d.block_bundle, int64_t(blk.size()))) || (st = dalloc(net, &d.xcd_first, 9)) ||
       (st = dalloc(net, &d.theads, std::max<int64_t>(1, ntiles))) || (st = dalloc(net, &d.row_ptr, n + 1)))
     return st;
   {
@@ -359,6 +382,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   }
   if ((st = upload(net, d.bundles, bl.data(), nb * sizeof(Bundle))) ||
       (st = upload(net, d.block_bundle, blk.data(), blk.size() * sizeof(int32_t))) ||
+      (st = upload(net, d.xcd_first, xf, sizeof(xf))) ||
       (st = upload(net, d.row_ptr, s->row_ptr, (n + 1) * sizeof(int64_t))))
     return st;
   for (int64_t q = 0; q < nb; ++q) {

@@ -30,12 +30,16 @@ constexpr int kCompactBlock = 256;  // threads of the compaction kernel
 //    relative to the previous entry of the tile; the first entry has delta 0)
 //    << 20 | position of the synapse in the bundle's CSR range (20 bits).
 //    Padding entries (the tail of a tile) have delta 0 and position nsyn,
-//    one past the bundle's last synapse: a bit the sums never read.
+//    one past the bundle's last synapse: a bit the sums never read.  A
+//    source gap wider than 4095 inside a tile is bridged by skip entries
+//    (delta 4095, position nsyn) when it needs at most 64 of them; a wider
+//    gap, or a new delay, starts a new tile.
 //    Tile header = first source of the tile (26 bits) | (delay - 1) << 26.
 constexpr int kTile = 256;
 constexpr int kPosBits = 20;
 constexpr uint32_t kPosMask = (1u << kPosBits) - 1u;
 constexpr uint32_t kMaxDelta = (1u << (32 - kPosBits)) - 1u;  // 4095
+constexpr uint32_t kMaxSkips = 64;  // widest gap bridged by skip entries: 64 deltas
 constexpr int64_t kBundleMaxSyn = int64_t(kPosMask);         // synapses 0 .. 2^20 - 2, padding at nsyn
 constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap words of the largest bundle
 
@@ -118,6 +122,8 @@ struct DeviceNet {
   uint32_t* theads = nullptr;       // [n_tiles] tile headers
   Bundle* bundles = nullptr;        // [n_bundles]
   int32_t* block_bundle = nullptr;  // [ceil(n / 1024)] bundle of each 1024-row block's first row
+  int64_t* xcd_first = nullptr;     // [9] bundles [xcd_first[x], xcd_first[x+1]) go to XCD x (equal tiles)
+  int64_t xcd_max = 0;              // most bundles of one XCD
   uint32_t* hitbuf = nullptr;       // [hit_total_words] delivery-test results: per bundle, one bit per
                                     // synapse in CSR order (from bit hbit0), rewritten every step
   int64_t hit_total_words = 0;

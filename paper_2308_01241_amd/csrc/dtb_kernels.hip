@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
 //    then adds the background count and updates the four gates.
 // Gather workgroups are mapped XCD-aware: the blocks an XCD receives
 // (blockIdx congruent mod 8) take a contiguous range of bundles, so bundles
-// of the same population (same source set) share that XCD's L2.
+// of the same population (same source set) share that XCD's L2; the eight
+// ranges hold about equal numbers of tiles.
 // Inclusive prefix sum over the 64 lanes of a wavefront with DPP row shifts
 // (within each 16-lane row) and the row broadcasts of lanes 15 and 31.
 __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
@@ -354,7 +355,7 @@ __device__ inline void gather_hits(const u32x4 (&tv)[kU], const uint32_t (&src)[
 
 template <int kU>
 __global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kU == 1 ? 8 : 4)))
-void k_gather(int64_t n_bundles, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
+void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
               const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
               const uint32_t* __restrict__ bitmaps, int64_t words_pad, int32_t slots,
               uint32_t* __restrict__ hitbuf, int64_t* __restrict__ ev_ring) {
@@ -363,9 +364,9 @@ void k_gather(int64_t n_bundles, const int64_t* __restrict__ step, const Bundle*
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(t_mod) * kStripes * 2;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t per = (n_bundles + 7) / 8;
-  const int64_t bi = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (bi >= n_bundles) return;  // whole block leaves together
+  const int x = int(blockIdx.x % 8);
+  const int64_t bi = xcd_first[x] + blockIdx.x / 8;
+  if (bi >= xcd_first[x + 1]) return;  // whole block leaves together
   const Bundle B = bundles[bi];
   const int hw = (B.nsyn >> 5) + 1;  // includes the padding bit at position nsyn
   for (int q = tid; q < hw; q += kGatherThreads) s_hits[q] = 0u;
@@ -661,9 +662,9 @@ namespace {
 
 template <int kU>
 void launch_gather_as(const DeviceNet& d, hipStream_t s) {
-  const unsigned grid = unsigned((d.n_bundles + 7) / 8 * 8);
+  const unsigned grid = unsigned(d.xcd_max * 8);
   const size_t lds = size_t(d.hit_words) * 4;
-  hipLaunchKernelGGL((k_gather<kU>), dim3(grid), dim3(kGatherThreads), lds, s, d.n_bundles, d.step, d.bundles,
+  hipLaunchKernelGGL((k_gather<kU>), dim3(grid), dim3(kGatherThreads), lds, s, d.xcd_first, d.step, d.bundles,
                      d.tiles, d.theads, d.raster, d.words_pad, d.slots, d.hitbuf, d.ev);
 }
 
