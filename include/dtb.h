@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 3
+#define DTB_ABI_VERSION 4
 
 typedef enum {
   DTB_OK = 0,
@@ -58,7 +58,9 @@ typedef enum {
   DTB_J_NMDA = 2,
   DTB_J_GABAA = 3,
   DTB_J_GABAB = 4,
-  DTB_REF = 5       /* remaining refractory steps (returned as float32) */
+  DTB_REF = 5,      /* remaining refractory steps (returned as float32) */
+  DTB_I_OU = 6      /* Ornstein-Uhlenbeck background current (float32; 0 while the
+                       Poisson drive is selected) */
 } dtb_field;
 
 /* One row of the neuron property table (Sec. V-D): the configurable
@@ -143,8 +145,23 @@ dtb_status dtb_reset(dtb_net* net);
 
 /* Change the background drive standing in for J_inter (Sec. V-B): mean
  * Poisson count per neuron-step (0 .. 400) and event weight (finite, >= 0).
- * Takes effect from the next step. */
+ * Takes effect from the next step; selects the Poisson drive (leaves the
+ * Ornstein-Uhlenbeck one of dtb_set_background_ou). */
 dtb_status dtb_set_background(dtb_net* net, double bg_lambda, float bg_w);
+
+/* Select the paper's own background model (Sec. III-B: every neuron receives
+ * an uncorrelated Ornstein-Uhlenbeck input current I_ou that keeps the
+ * network active) instead of the Poisson count.  I_ou is added to I_ext in
+ * the membrane equation (I = (I_ext + I_ou) + sum_u ...); after the step's
+ * gates, I_ou <- mu + a (I_ou - mu) + sigma sqrt(1 - a^2) xi with
+ * a = exp(-dt / tau_ms), the exact discretisation of the OU process, and
+ * xi ~ N(0, 1) by Box-Muller from Philox4x64-10, key (seed, 0), counter
+ * (t, i, member, 1): u1 = (hi32(word 0) + 1) / 2^32, u2 = hi32(word 1) / 2^32,
+ * xi = sqrt(-2 ln u1) cos(2 pi u2).  Every neuron's I_ou is set to mu now
+ * (also by dtb_reset while selected).  mu and sigma (>= 0) in the units of
+ * I_ext, tau_ms > 0, all finite; the Poisson drive is off while selected.
+ * Takes effect from the next step. */
+dtb_status dtb_set_background_ou(dtb_net* net, float mu, float sigma, float tau_ms);
 
 /* Teacher forcing (a test hook for the accuracy check of Sec. VII-B): the
  * next n_steps steps take their spikes from bits (host, [n_steps] bitmaps

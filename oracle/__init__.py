@@ -32,7 +32,7 @@ _SRC = os.path.join(_HERE, "dtb_oracle.c")
 _LIB = os.path.join(_HERE, "_oracle.so")
 _lib = None
 
-FIELDS = {"V": 0, "j_AMPA": 1, "j_NMDA": 2, "j_GABAa": 3, "j_GABAb": 4, "ref": 5}
+FIELDS = {"V": 0, "j_AMPA": 1, "j_NMDA": 2, "j_GABAa": 3, "j_GABAb": 4, "ref": 5, "I_ou": 6}
 
 
 def build(force: bool = True) -> str:
@@ -70,6 +70,10 @@ def _load():
         lib.ora_get.argtypes = [P, ctypes.c_int, P]
         lib.ora_set.argtypes = [P, ctypes.c_int, P]
         lib.ora_set_gain.argtypes = [P, P]
+        lib.ora_set_ou.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.ora_set_ou.restype = ctypes.c_int
+        lib.ora_ou_normal.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+        lib.ora_ou_normal.restype = ctypes.c_double
         lib.ora_time.argtypes = [P]
         lib.ora_time.restype = ctypes.c_int64
         lib.ora_philox4x64_10.argtypes = [P, P, P]
@@ -113,6 +117,12 @@ def poisson_table(lam: float, cap: int = 512) -> np.ndarray:
 
 def bg_uniform(seed: int, t: int, i: int, member: int = 0) -> int:
     return int(_load().ora_bg_uniform(seed, t, i, member))
+
+
+def ou_normal(seed: int, t: int, i: int, member: int = 0) -> float:
+    """The standard normal draw of the OU background for (t, i, member):
+    Box-Muller on Philox4x64-10 counter (t, i, member, 1)."""
+    return float(_load().ora_ou_normal(seed, t, i, member))
 
 
 def max_threads() -> int:
@@ -181,6 +191,11 @@ class OracleNet:
 
     def poisson_K(self) -> int:
         return int(self._lib.ora_poisson_K(self._h))
+
+    def set_ou(self, mu: float, sigma: float, tau_ms: float) -> None:
+        """Select the Ornstein-Uhlenbeck background (every I_ou set to mu)."""
+        if self._lib.ora_set_ou(self._h, float(mu), float(sigma), float(tau_ms)) != 0:
+            raise ValueError("need sigma >= 0, tau_ms > 0, finite values")
 
     def set_gain(self, gain) -> None:
         g = np.ascontiguousarray(gain, dtype=np.float64).reshape(self.net.n_regions, 4)

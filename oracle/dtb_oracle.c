@@ -35,6 +35,14 @@
  * are turned into a Poisson(lambda) count by inversion against the table
  * T_k = floor(F(k) 2^32) (F the Poisson CDF, entries kept while below
  * 2^32 - 1): c = #{k : u >= T_k}.
+ *
+ * Alternative background (the paper's own, Sec. III-B): an uncorrelated
+ * Ornstein-Uhlenbeck current I_ou per neuron, added to Iext in step 1
+ * (I = (Iext + I_ou) + sum_u ...), advanced after step 4 by the exact
+ * discretisation I_ou <- mu + a (I_ou - mu) + sigma sqrt(1 - a^2) xi,
+ * a = exp(-dt / tau); xi by Box-Muller from Philox counter (t, i, member, 1):
+ * u1 = (hi32(word 0) + 1) 2^-32, u2 = hi32(word 1) 2^-32,
+ * xi = sqrt(-2 ln u1) cos(2 pi u2).  The Poisson drive is off meanwhile.
  */
 #include <math.h>
 #include <stdint.h>
@@ -103,6 +111,17 @@ uint32_t ora_bg_uniform(uint64_t seed, int64_t t, int64_t i, int64_t member) {
   return (uint32_t)(out[0] >> 32);
 }
 
+/* standard normal draw of the OU background: Box-Muller on Philox stream 1 */
+double ora_ou_normal(uint64_t seed, int64_t t, int64_t i, int64_t member) {
+  uint64_t ctr[4] = {(uint64_t)t, (uint64_t)i, (uint64_t)member, 1};
+  uint64_t key[2] = {seed, 0};
+  uint64_t out[4];
+  ora_philox4x64_10(ctr, key, out);
+  const double u1 = ((double)(out[0] >> 32) + 1.0) * 0x1p-32;
+  const double u2 = (double)(out[1] >> 32) * 0x1p-32;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
+}
+
 /* ------------------------------------------------------------- network */
 
 typedef struct {
@@ -138,12 +157,17 @@ typedef struct {
   int32_t* ref;
   uint8_t* ring; /* [max_delay][n] */
   double* gain;  /* [n_regions][4] */
+  /* Ornstein-Uhlenbeck background (ou_on) */
+  int ou_on;
+  double ou_mu, ou_a, ou_s;
+  double* ou; /* [n] */
 } ora_net;
 
 void ora_destroy(ora_net* h) {
   if (!h) return;
   free(h->C); free(h->gL); free(h->EL); free(h->Vth); free(h->Vreset); free(h->Iext);
   free(h->g); free(h->nref); free(h->V); free(h->j); free(h->ref); free(h->ring); free(h->gain);
+  free(h->ou);
   free(h);
 }
 
@@ -189,6 +213,22 @@ ora_net* ora_create(const ora_input* in) {
 
 int64_t ora_time(const ora_net* h) { return h->t; }
 
+/* select the OU background (every I_ou set to mu); returns -1 on bad input */
+int ora_set_ou(ora_net* h, double mu, double sigma, double tau_ms) {
+  if (!(sigma >= 0.0) || !(tau_ms > 0.0) || !isfinite(mu) || !isfinite(sigma) || !isfinite(tau_ms)) return -1;
+  if (!h->ou) {
+    h->ou = malloc(sizeof(double) * h->in.n);
+    if (!h->ou) return -1;
+  }
+  h->ou_on = 1;
+  h->ou_mu = mu;
+  h->ou_a = exp(-h->in.dt_ms / tau_ms);
+  h->ou_s = sigma * sqrt(1.0 - h->ou_a * h->ou_a);
+  h->K = 0; /* no Poisson drive */
+  for (int64_t i = 0; i < h->in.n; i++) h->ou[i] = mu;
+  return 0;
+}
+
 int ora_set_gain(ora_net* h, const double* gain) {
   for (int r = 0; r < h->in.n_regions; r++)
     for (int u = 0; u < 4; u++) h->gain[4 * r + u] = gain[4 * r + u];
@@ -226,6 +266,7 @@ int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_r
     double Vt = NAN;
     if (r <= 0) {
       double I = h->Iext[p];
+      if (h->ou_on) I += h->ou[i];
       for (int u = 0; u < 4; u++)
         I += h->g[4 * p + u] * h->gain[4 * reg + u] * h->j[(size_t)u * n + i] * (in->E[u] - V);
       Vt = V + in->dt_ms / h->C[p] * (-h->gL[p] * (V - h->EL[p]) + I);
@@ -269,6 +310,9 @@ int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_r
     h->j[1 * (size_t)n + i] = h->a[1] * h->j[1 * (size_t)n + i] + dE;
     h->j[2 * (size_t)n + i] = h->a[2] * h->j[2 * (size_t)n + i] + dI;
     h->j[3 * (size_t)n + i] = h->a[3] * h->j[3 * (size_t)n + i] + dI;
+    if (h->ou_on)
+      h->ou[i] = h->ou_mu + h->ou_a * (h->ou[i] - h->ou_mu) +
+                 h->ou_s * ora_ou_normal(in->seed, t, i, in->member);
   }
   if (ev_rec) *ev_rec = er;
   if (ev_bg) *ev_bg = eb;
@@ -282,9 +326,14 @@ int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_r
   return 0;
 }
 
-/* field: 0 = V, 1..4 = gates AMPA NMDA GABAa GABAb, 5 = refractory counter */
+/* field: 0 = V, 1..4 = gates AMPA NMDA GABAa GABAb, 5 = refractory counter,
+   6 = OU current (0 while the Poisson drive is selected) */
 int ora_get(const ora_net* h, int field, double* out) {
   const int64_t n = h->in.n;
+  if (field == 6) {
+    for (int64_t i = 0; i < n; i++) out[i] = h->ou_on ? h->ou[i] : 0.0;
+    return 0;
+  }
   if (field == 0) memcpy(out, h->V, sizeof(double) * n);
   else if (field >= 1 && field <= 4) memcpy(out, h->j + (size_t)(field - 1) * n, sizeof(double) * n);
   else if (field == 5) for (int64_t i = 0; i < n; i++) out[i] = h->ref[i];

@@ -12,7 +12,7 @@ DTB_OK = 0
 STATUS = {0: "DTB_OK", -1: "DTB_ERR_INVALID", -2: "DTB_ERR_OOM", -3: "DTB_ERR_HIP", -4: "DTB_ERR_STATE",
           -5: "DTB_ERR_NUMERIC", -6: "DTB_ERR_UNSUPPORTED"}
 W_F32, W_BF16 = 0, 1
-FIELDS = {"V": 0, "j_AMPA": 1, "j_NMDA": 2, "j_GABAa": 3, "j_GABAb": 4, "ref": 5}
+FIELDS = {"V": 0, "j_AMPA": 1, "j_NMDA": 2, "j_GABAa": 3, "j_GABAb": 4, "ref": 5, "I_ou": 6}
 
 
 class DtbError(RuntimeError):
@@ -51,6 +51,7 @@ SIGNATURES = {
     "dtb_step": ([_P, _I32], ctypes.c_int),
     "dtb_reset": ([_P], ctypes.c_int),
     "dtb_set_background": ([_P, ctypes.c_double, ctypes.c_float], ctypes.c_int),
+    "dtb_set_background_ou": ([_P, ctypes.c_float, ctypes.c_float, ctypes.c_float], ctypes.c_int),
     "dtb_force_spikes": ([_P, _P, _I32], ctypes.c_int),
     "dtb_read_spikes": ([_P, _I64, _I64, _P, ctypes.c_int], ctypes.c_int),
     "dtb_read_spike_ids": ([_P, _P, _I64, ctypes.POINTER(_I64)], ctypes.c_int),
@@ -99,7 +100,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 3:
+    if lib.dtb_abi_version() != 4:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

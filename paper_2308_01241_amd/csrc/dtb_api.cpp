@@ -440,6 +440,15 @@ hipError_t timed(dtb_net* net, int kind, F fn) {
   return e;
 }
 
+// Kernel arguments are captured by value in a graph: parameter changes drop it.
+void drop_graph(dtb_net* net) {
+  if (net->graph_exec) (void)hipGraphExecDestroy(net->graph_exec);
+  if (net->graph) (void)hipGraphDestroy(net->graph);
+  net->graph_exec = nullptr;
+  net->graph = nullptr;
+  net->graph_steps = 0;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -835,6 +844,7 @@ dtb_status dtb_reset(dtb_net* net) {
            {d.bold, size_t(d.n_regions) * 16}, {d.bold_y, size_t(d.n_regions) * 4}}) {
     if (e == hipSuccess) e = hipMemsetAsync(pr.first, 0, pr.second, net->stream);
   }
+  if (e == hipSuccess && d.ou_on) e = launch_fill(d.ou, d.n_pad, d.ou_mu, net->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
   if (e != hipSuccess) return hip_fail(net, e, "reset");
   net->t = 0;
@@ -846,6 +856,8 @@ dtb_status dtb_reset(dtb_net* net) {
 dtb_status dtb_set_background(dtb_net* net, double bg_lambda, float bg_w) {
   dtb_status st = check_net(net);
   if (st) return st;
+  drop_graph(net);
+  net->d.ou_on = 0;
   if (!(bg_lambda >= 0.0) || !(bg_lambda <= 400.0)) return fail(DTB_ERR_INVALID, "bg_lambda must be in [0, 400]");
   if (!(bg_w >= 0.f) || !finite_f(bg_w)) return fail(DTB_ERR_INVALID, "bg_w must be finite and >= 0");
   std::vector<uint32_t> T(kMaxPoisson);
@@ -861,6 +873,25 @@ dtb_status dtb_set_background(dtb_net* net, double bg_lambda, float bg_w) {
   if (K > 0 && (st = upload(net, d.poisson, T.data(), size_t(K) * 4))) return st;
   d.poisson_K = K;
   d.bg_w = bg_w;
+  return DTB_OK;
+}
+
+dtb_status dtb_set_background_ou(dtb_net* net, float mu, float sigma, float tau_ms) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!finite_f(mu) || !finite_f(sigma) || !(sigma >= 0.f) || !finite_f(tau_ms) || !(tau_ms > 0.f))
+    return fail(DTB_ERR_INVALID, "need finite mu, sigma >= 0 and tau_ms > 0");
+  DeviceNet& d = net->d;
+  drop_graph(net);
+  if (!d.ou && (st = dalloc(net, &d.ou, d.n_pad))) return st;
+  const double a = std::exp(-double(d.dt_ms) / double(tau_ms));
+  d.ou_mu = mu;
+  d.ou_a = float(a);
+  d.ou_s = float(double(sigma) * std::sqrt(1.0 - a * a));
+  d.ou_on = 1;
+  d.poisson_K = 0;  // the Poisson drive is off
+  hipError_t e = launch_fill(d.ou, d.n_pad, mu, net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "OU current fill");
   return DTB_OK;
 }
 
@@ -931,6 +962,17 @@ dtb_status dtb_read_state(dtb_net* net, int32_t field, float* dst, int dst_on_de
   if (!dst) return fail(DTB_ERR_INVALID, "dst is NULL");
   const DeviceNet& d = net->d;
   if (field == DTB_V) return copy_out(net, dst, d.V, d.n * 4, dst_on_device);
+  if (field == DTB_I_OU) {
+    if (d.ou_on) return copy_out(net, dst, d.ou, d.n * 4, dst_on_device);
+    if (dst_on_device) {
+      hipError_t e = hipMemsetAsync(dst, 0, d.n * 4, net->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+      if (e != hipSuccess) return hip_fail(net, e, "hipMemsetAsync");
+    } else {
+      std::memset(dst, 0, d.n * 4);
+    }
+    return DTB_OK;
+  }
   if (field >= DTB_J_AMPA && field <= DTB_J_GABAB)
     return copy_out(net, dst, d.j + (field - 1) * d.n_pad, d.n * 4, dst_on_device);
   if (field == DTB_REF) {

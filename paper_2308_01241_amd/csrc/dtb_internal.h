@@ -105,6 +105,10 @@ struct DeviceNet {
   float E[4] = {0, 0, 0, 0};        // reversal potentials
   float bg_w = 0.f;
   uint64_t seed = 0;
+  // Ornstein-Uhlenbeck background (off while ou is null or ou_on == 0)
+  int32_t ou_on = 0;
+  float ou_mu = 0.f, ou_a = 0.f, ou_s = 0.f;  // mean, exp(-dt / tau), sigma sqrt(1 - a^2)
+  float* ou = nullptr;              // [n_pad] I_ou
   // neuron state (SoA) and tables
   float* V = nullptr;               // [n_pad]
   float* V0 = nullptr;              // [n_pad] initial potentials (for dtb_reset)
@@ -153,6 +157,7 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
 hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
 hipError_t launch_gather(const DeviceNet& d, hipStream_t s);
 hipError_t launch_finalize(const DeviceNet& d, hipStream_t s);
+hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s);
 hipError_t gather_set_lds_limit();
 
 }  // namespace dtb

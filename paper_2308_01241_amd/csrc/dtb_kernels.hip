@@ -31,8 +31,10 @@ namespace {
 // ------------------------------------------------------------------ RNG
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
 // 64x64 -> 128-bit products, key bumped by the Weyl constants between rounds.
+// returns output word 0 (the high 32 bits of which are the background draw);
+// *w1 (if given) receives output word 1
 __device__ inline uint64_t philox_hi32_word0(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                             uint64_t k0, uint64_t k1) {
+                                             uint64_t k0, uint64_t k1, uint64_t* w1 = nullptr) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
@@ -49,6 +51,7 @@ __device__ inline uint64_t philox_hi32_word0(uint64_t c0, uint64_t c1, uint64_t 
     c2 = y2;
     c3 = lo0;
   }
+  if (w1) *w1 = c1;
   return c0 >> 32;
 }
 
@@ -63,7 +66,7 @@ __device__ inline int poisson_count(uint32_t u, const uint32_t* __restrict__ T, 
 __global__ __launch_bounds__(1024) void k_neuron_update(
     int64_t n, int64_t n_pad, const int64_t* __restrict__ step, float* __restrict__ V, const float* __restrict__ j,
     uint8_t* __restrict__ ref, const uint16_t* __restrict__ ptype, const int32_t* __restrict__ region,
-    const PType* __restrict__ ptab, const float* __restrict__ gain,
+    const PType* __restrict__ ptab, const float* __restrict__ gain, const float* __restrict__ ou,
     float E0, float E1, float E2, float E3, const uint32_t* __restrict__ forced,
     uint32_t* __restrict__ raster, int64_t words_pad, int32_t* __restrict__ counts, int32_t n_regions,
     uint32_t* __restrict__ cticket, int32_t* __restrict__ bad) {
@@ -84,8 +87,9 @@ __global__ __launch_bounds__(1024) void k_neuron_update(
     const float* gn = gain + 4 * reg;
     float vt = 0.f;
     if (r <= 0) {
-      // I = Iext + sum_u (g_u gain_u) j_u (E_u - V) - gL (V - EL);  V~ = V + dt/C I
+      // I = (Iext + I_ou) + sum_u (g_u gain_u) j_u (E_u - V) - gL (V - EL);  V~ = V + dt/C I
       float I = p.Iext;
+      if (ou) I = I + ou[i];
       I = __fmaf_rn((p.g[0] * gn[0]) * j[i], E0 - v, I);
       I = __fmaf_rn((p.g[1] * gn[1]) * j[n_pad + i], E1 - v, I);
       I = __fmaf_rn((p.g[2] * gn[2]) * j[2 * n_pad + i], E2 - v, I);
@@ -476,8 +480,8 @@ __global__ __launch_bounds__(kSumsThreads) void k_sums(
     int64_t n, int64_t n_pad, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
     const int32_t* __restrict__ block_bundle, const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v,
     const uint32_t* __restrict__ hitbuf, float* __restrict__ j, float a0, float a1, float a2, float a3,
-    float bg_w, const uint32_t* __restrict__ poisson, int K, int64_t* __restrict__ ev_ring,
-    int32_t* __restrict__ bad) {
+    float bg_w, const uint32_t* __restrict__ poisson, int K, float* __restrict__ ou, float ou_mu, float ou_a,
+    float ou_s, int64_t* __restrict__ ev_ring, int32_t* __restrict__ bad) {
   __shared__ uint32_t s_bg[kSumsThreads / 64];
   const int64_t t = step[0];
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(step[1]) * kStripes * 2;
@@ -498,8 +502,9 @@ __global__ __launch_bounds__(kSumsThreads) void k_sums(
     const int64_t mrow0 = B->member_row0;
     const int32_t member = B->member;
     const int64_t bit0 = B->hbit0 + (k0 - B->syn0);
-    const uint32_t u = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - mrow0), uint64_t(member), 0ull,
-                                                  seed, 0ull));
+    const uint32_t u = ou ? 0u
+                          : uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - mrow0), uint64_t(member), 0ull,
+                                                       seed, 0ull));
     float dE = 0.f, dI = 0.f;
     const int len = int(k1 - k0);
     if (len > 0) {
@@ -552,6 +557,22 @@ __global__ __launch_bounds__(kSumsThreads) void k_sums(
     j[2 * n_pad + r] = jc;
     j[3 * n_pad + r] = jd;
     if (!(isfinite(ja) && isfinite(jb) && isfinite(jc) && isfinite(jd))) atomicOr(bad, 1);
+    if (ou) {
+      // I_ou <- mu + a (I_ou - mu) + s xi, xi by Box-Muller on Philox stream 1
+      uint64_t w1 = 0;
+      const uint32_t h0 = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - mrow0), uint64_t(member), 1ull,
+                                                     seed, 0ull, &w1));
+      const uint32_t h1 = uint32_t(w1 >> 32);
+      // the draw in FP64 (u1, u2 exact), rounded once: a float u1 cannot
+      // resolve ln u1 near 1
+      const double u1 = (double(h0) + 1.0) * 2.3283064365386962890625e-10;  // (0, 1]
+      const double u2 = double(h1) * 2.3283064365386962890625e-10;          // [0, 1)
+      const float xi = float(sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2));
+      const float x = ou[r];
+      const float y = __fmaf_rn(ou_s, xi, __fmaf_rn(ou_a, x - ou_mu, ou_mu));
+      ou[r] = y;
+      if (!isfinite(y)) atomicOr(bad, 1);
+    }
   }
   // block total of background events, one striped atomic per block
 #pragma unroll
@@ -647,7 +668,8 @@ __global__ __launch_bounds__(256) void k_finalize(
 hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s) {
   const unsigned grid = unsigned(d.n_pad / 1024);
   hipLaunchKernelGGL(k_neuron_update, dim3(grid), dim3(1024), 0, s, d.n, d.n_pad, d.step, d.V, d.j, d.ref,
-                     d.ptype, d.region, d.ptab, d.gain, d.E[0], d.E[1], d.E[2], d.E[3], forced, d.raster,
+                     d.ptype, d.region, d.ptab, d.gain, d.ou_on ? d.ou : nullptr, d.E[0], d.E[1], d.E[2], d.E[3],
+                     forced, d.raster,
                      d.words_pad, d.counts, d.n_regions, d.cticket, d.bad);
   return hipGetLastError();
 }
@@ -697,11 +719,24 @@ hipError_t launch_sums(const DeviceNet& d, hipStream_t s) {
   if (d.wtype == DTB_W_BF16)
     hipLaunchKernelGGL(k_sums<true>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, d.bundles,
                        d.block_bundle, d.row_ptr, d.wts, d.hitbuf, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w,
-                       d.poisson, d.poisson_K, d.ev, d.bad);
+                       d.poisson, d.poisson_K, d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
   else
     hipLaunchKernelGGL(k_sums<false>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, d.bundles,
                        d.block_bundle, d.row_ptr, d.wts, d.hitbuf, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w,
-                       d.poisson, d.poisson_K, d.ev, d.bad);
+                       d.poisson, d.poisson_K, d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ __launch_bounds__(256) void k_fill(float* __restrict__ dst, int64_t n, float v) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+}  // namespace
+
+hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, dst, n, v);
   return hipGetLastError();
 }
 

@@ -105,6 +105,10 @@ class Net:
     def set_background(self, bg_lambda: float, bg_w: float) -> None:
         check(self._lib.dtb_set_background(self._h, float(bg_lambda), float(bg_w)))
 
+    def set_background_ou(self, mu: float, sigma: float, tau_ms: float) -> None:
+        """Ornstein-Uhlenbeck background current instead of the Poisson drive."""
+        check(self._lib.dtb_set_background_ou(self._h, float(mu), float(sigma), float(tau_ms)))
+
     def force(self, raster: np.ndarray) -> None:
         """Queue teacher-forced spikes: raster [n_steps, n] of 0/1."""
         r = np.ascontiguousarray(raster, dtype=np.uint8).reshape(-1, self.n)

@@ -226,6 +226,57 @@ def test_launch_shapes_give_identical_results(dtb):
         assert r[3] == runs[0][3]
 
 
+def test_ou_background_free_run_teacher_forced_reset_and_graph(dtb):
+    """The Ornstein-Uhlenbeck background (Sec. III-B) instead of the Poisson
+    drive: free-run raster equal to the reference until a near-threshold tie,
+    V, gates and I_ou within tolerance per step under teacher forcing, reset
+    reproduces the run, graph replays equal eager steps after the switch."""
+    net = netgen.make_network(netgen.small_net(seed_offset=2, bg_lambda=0.0))
+    mu, sigma, tau = 0.6, 0.4, 8.0
+    T = 100
+    o = oracle.OracleNet(net)
+    o.set_ou(mu, sigma, tau)
+    ref = o.run(T, want_margin=True)
+    assert ref["raster"].sum() > 0 and np.all(ref["ev_bg"] == 0)
+    g = _gpu(dtb, net)
+    g.set_background_ou(mu, sigma, tau)
+    g.step(T)
+    _check_raster(g.raster(0, T), ref)
+    first = g.raster(0, T)
+    assert g.counters()["ev_bg"] == 0
+    # teacher forcing with the reference raster
+    o2 = oracle.OracleNet(net)
+    o2.set_ou(mu, sigma, tau)
+    f = _gpu(dtb, net)
+    f.set_background_ou(mu, sigma, tau)
+    np.testing.assert_array_equal(f.state("I_ou"), np.float32(mu))
+    f.force(ref["raster"][:40])
+    for t in range(40):
+        o2.step(forced=ref["raster"][t])
+        f.step(1)
+        jmax = max(np.abs(o2.get(k)).max() for k in FIELDS[1:])
+        for k in FIELDS:
+            floor = 0.0 if k == "V" else 1e-3 * jmax
+            assert _state_close(f.state(k), o2.get(k), floor).all(), (t, k)
+        # relative to the scale of the process (FP32 rounds its sums at |mu| + sigma)
+        assert _state_close(f.state("I_ou"), o2.get("I_ou"), max(abs(mu), sigma)).all(), (t, "I_ou")
+    # reset refills I_ou = mu and reproduces the free run
+    g.reset()
+    g.step(T)
+    np.testing.assert_array_equal(g.raster(0, T), first)
+    # graph replays after the switch equal eager steps
+    h = _gpu(dtb, net)
+    h.run(T)                          # a graph of T steps captured with the Poisson drive
+    h.reset()
+    h.set_background_ou(mu, sigma, tau)
+    h.run(T)
+    np.testing.assert_array_equal(h.raster(0, T), first)
+    # and back to the Poisson drive
+    h.reset()
+    h.set_background(net.bg_lambda, net.bg_w)
+    np.testing.assert_array_equal(h.state("I_ou"), 0.0)
+
+
 def test_reset_reproduces_the_first_run(dtb):
     net = netgen.make_network(netgen.small_net(seed_offset=3))
     g = _gpu(dtb, net)
