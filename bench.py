@@ -73,7 +73,10 @@ def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) ->
     return 5.0 * nnz + w_bytes * events + n * (2 * 21 + 2) + n * (max_delay + 1) / 8.0
 
 
-def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0)):
+OU_BACKGROUND = (0.6, 0.4, 8.0)  # mu, sigma (units of Iext), tau (ms)
+
+
+def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0), ou=None):
     import torch
     import paper_2308_01241_amd as dtb
 
@@ -83,6 +86,8 @@ def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0)):
                 bundle_syn=shape[0], unroll=shape[1])
     torch.cuda.synchronize()
     log(f"[bench] {rate} Hz: created in {time.time() - t0:.1f}s; warmup {warmup}")
+    if ou is not None:
+        g.set_background_ou(*ou)
     g.step(warmup)
     g.sync()
     c0 = g.counters()
@@ -357,6 +362,12 @@ def main():
                          "gather_ms": bf["kernels"]["gather"]["ms"] / max(1, bf["kernels"]["gather"]["launches"]),
                          "rate_error_vs_f32": rate_error(bf["region_rates"], res[r0]["region_rates"])}
         log(f"[bench] bf16: {json.dumps(forms['bf16'])}")
+        ou = run_rate(net, r0, 0.0, args.steps, args.warmup, "f32", shape, ou=OU_BACKGROUND)
+        forms["ou_background"] = {"mu_sigma_tau_ms": list(OU_BACKGROUND), "events_per_s": ou["events_per_s"],
+                                  "ms_per_step": ou["ms_per_step"], "rtf": ou["rtf"],
+                                  "mean_rate_hz": ou["mean_rate_hz"],
+                                  "sums_ms": ou["kernels"]["sums"]["ms"] / max(1, ou["kernels"]["sums"]["launches"])}
+        log(f"[bench] ou background: {json.dumps(forms['ou_background'])}")
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (FP64 reference, bounded sample)")

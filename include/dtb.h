@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 4
+#define DTB_ABI_VERSION 5
 
 typedef enum {
   DTB_OK = 0,
@@ -171,6 +171,36 @@ dtb_status dtb_set_background_ou(dtb_net* net, float mu, float sigma, float tau_
  * after any forcing still pending; at most record_steps pending steps. */
 dtb_status dtb_force_spikes(dtb_net* net, const uint32_t* bits, int32_t n_steps);
 
+/* J_inter (Sec. V-B, the equation splitting the input of neuron i into
+ * J_intra over presynaptic neurons on the same GPU and J_inter over those on
+ * other GPUs): give the partition a second in-edge block whose sources are
+ * n_remote neurons of other partitions, and replay their spikes
+ * (dtb_push_remote_spikes) in place of the exchange.  The block is a CSR
+ * over the n local rows: row_ptr int64 [n+1] (row_ptr[0] = 0,
+ * row_ptr[n] = nnz, non-decreasing), col int32 [nnz] in [0, n_remote),
+ * w float32 [nnz] finite >= 0, delay uint8 [nnz] in [1, max_delay] ms,
+ * remote_is_inh uint8 [n_remote] (nonzero = the remote source is
+ * inhibitory, its weight goes to the GABA gates).  Host arrays, copied (the
+ * caller keeps ownership).  Each row's input is then the local in-edges in
+ * CSR order, then the remote ones in CSR order, then the background; a
+ * delivered remote spike counts as a recurrent event.  Every step then runs
+ * the remote block's delivery tests on a second stream of the library's,
+ * concurrent with the update, compaction and local delivery tests, and joins
+ * it before the sums.  Only on a single-member handle before its first step
+ * (or right after dtb_reset); once per handle (DTB_ERR_STATE otherwise);
+ * n_remote in [1, 2^26 - 1].  dtb_run is unavailable on such a handle. */
+dtb_status dtb_set_remote_block(dtb_net* net, int64_t n_remote, int64_t nnz, const int64_t* row_ptr,
+                                const int32_t* col, const float* w, const uint8_t* delay,
+                                const uint8_t* remote_is_inh);
+
+/* Queue the remote spikes of the next n_steps steps: bits (host,
+ * [n_steps][dtb_bitmap_words(n_remote)] uint32; bit m of step q = remote
+ * neuron m spiked at that step; bits past n_remote are ignored).  Each
+ * dtb_step consumes one queued step and fails with DTB_ERR_STATE when none
+ * is queued; at most record_steps pending steps; dtb_reset drops them.
+ * Synchronizes the handle's stream. */
+dtb_status dtb_push_remote_spikes(dtb_net* net, const uint32_t* bits, int32_t n_steps);
+
 /* Spike bitmaps of steps [t0, t1) (the "spikes sequence" of Sec. V-B),
  * [t1-t0][dtb_bitmap_words(n)] uint32 into dst.  Requires
  * now - record_steps <= t0 <= t1 <= now (now = steps taken). */
@@ -210,8 +240,9 @@ dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int6
  * a pair of hipEvents recorded on the handle's stream.  dtb_read_timing
  * synchronizes, returns the summed durations in ms and the number of timed
  * launches per kernel, in the order neuron update, compaction, gather
- * (delivery tests), sums (per-row sums, background, gates), finalize
- * (double [5], int64 [5]; either may be NULL), and clears them. */
+ * (delivery tests), sums (per-row sums, background, gates), finalize,
+ * remote gather (the remote block's delivery tests, timed on the second
+ * stream) (double [6], int64 [6]; either may be NULL), and clears them. */
 dtb_status dtb_set_timing(dtb_net* net, int enable);
 dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches);
 

@@ -176,4 +176,43 @@ def make_network(spec: NetSpec) -> Network:
                    seed=int(spec.bg_seed), member=int(spec.member), region_start=start, name=spec.name)
 
 
+@dataclasses.dataclass
+class RemoteBlock:
+    """In-edges of a partition's n rows from n_remote neurons held by other
+    partitions (the J_inter sources of Sec. V-B)."""
+    n_remote: int
+    row_ptr: np.ndarray      # int64 [n+1]
+    col: np.ndarray          # int32 [nnz] remote source id
+    w: np.ndarray            # float32 [nnz]
+    delay: np.ndarray        # uint8 [nnz] in [1, max_delay]
+    is_inh: np.ndarray       # uint8 [n_remote]
+
+
+def make_remote_block(n: int, n_remote: int, k_remote, max_delay: int = 5, w_mu: float = -1.0,
+                      w_sigma: float = 0.5, e_frac: float = 0.8, seed: int = 11) -> RemoteBlock:
+    """k_remote in-edges per row (an int, or an int array [n] for a ragged
+    block) drawn uniformly from the remote sources, uniform integer delays in
+    [1, max_delay], log-normal weights; the first round(e_frac n_remote)
+    remote sources are excitatory."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = np.broadcast_to(np.asarray(k_remote, dtype=np.int64), (n,))
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(k, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    col = rng.integers(0, n_remote, size=nnz, dtype=np.int32)
+    delay = rng.integers(1, max_delay + 1, size=nnz, dtype=np.uint8)
+    w = np.exp(rng.normal(w_mu, w_sigma, size=nnz)).astype(np.float32)
+    is_inh = np.zeros(n_remote, dtype=np.uint8)
+    is_inh[int(np.floor(e_frac * n_remote + 0.5)):] = 1
+    return RemoteBlock(n_remote=int(n_remote), row_ptr=row_ptr, col=col, w=w, delay=delay, is_inh=is_inh)
+
+
+def remote_raster(n_steps: int, n_remote: int, rate_hz: float, dt_ms: float = 1.0, seed: int = 12) -> np.ndarray:
+    """Replayed remote spikes: independent Bernoulli(rate dt) per neuron-step,
+    uint8 [n_steps, n_remote]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = rate_hz * dt_ms * 1e-3
+    return (rng.random((n_steps, n_remote), dtype=np.float32) < p).astype(np.uint8)
+
+
 from .configs import *  # noqa: E402,F401,F403

@@ -70,6 +70,10 @@ def _load():
         lib.ora_get.argtypes = [P, ctypes.c_int, P]
         lib.ora_set.argtypes = [P, ctypes.c_int, P]
         lib.ora_set_gain.argtypes = [P, P]
+        lib.ora_set_remote.argtypes = [P, ctypes.c_int64, P, P, P, P, P]
+        lib.ora_set_remote.restype = ctypes.c_int
+        lib.ora_give_remote.argtypes = [P, P]
+        lib.ora_give_remote.restype = ctypes.c_int
         lib.ora_set_ou.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         lib.ora_set_ou.restype = ctypes.c_int
         lib.ora_ou_normal.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
@@ -197,6 +201,24 @@ class OracleNet:
         if self._lib.ora_set_ou(self._h, float(mu), float(sigma), float(tau_ms)) != 0:
             raise ValueError("need sigma >= 0, tau_ms > 0, finite values")
 
+    def set_remote(self, block) -> None:
+        """Add a remote in-edge block (J_inter, Sec. V-B): ``block`` has
+        n_remote, row_ptr [n+1], col, w, delay and is_inh [n_remote]."""
+        rp = np.ascontiguousarray(block.row_ptr, dtype=np.int64)
+        if rp.shape != (self.net.n + 1,):
+            raise ValueError("remote row_ptr must have n + 1 entries")
+        arrs = [rp, np.ascontiguousarray(block.col, dtype=np.int32), np.ascontiguousarray(block.w, dtype=np.float32),
+                np.ascontiguousarray(block.delay, dtype=np.uint8), np.ascontiguousarray(block.is_inh, dtype=np.uint8)]
+        if self._lib.ora_set_remote(self._h, int(block.n_remote), *[_p(a) for a in arrs]) != 0:
+            raise ValueError("oracle: invalid remote block (or already set)")
+        self.n_remote = int(block.n_remote)
+
+    def give_remote(self, spikes) -> None:
+        """Spikes [n_remote] of the remote sources at the coming step."""
+        s = np.ascontiguousarray(spikes, dtype=np.uint8).reshape(self.n_remote)
+        if self._lib.ora_give_remote(self._h, _p(s)) != 0:
+            raise ValueError("oracle: no remote block")
+
     def set_gain(self, gain) -> None:
         g = np.ascontiguousarray(gain, dtype=np.float64).reshape(self.net.n_regions, 4)
         self._lib.ora_set_gain(self._h, _p(g))
@@ -213,6 +235,8 @@ class OracleNet:
         r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
         rc = self._lib.ora_step(self._h, _p(f), _p(r), 0 if r is None else len(r), _p(spikes),
                                 _p(margin), _p(counts), ctypes.byref(er), ctypes.byref(eb))
+        if rc == -2:
+            raise ValueError("oracle step: the remote spikes of this step were not given")
         if rc != 0:
             raise ValueError("oracle step: a row subset needs a forced raster")
         return {"spikes": spikes, "margin": margin, "counts": counts,
@@ -230,9 +254,11 @@ class OracleNet:
     def state(self) -> dict:
         return {k: self.get(k) for k in FIELDS}
 
-    def run(self, n_steps: int, forced=None, want_state=False, want_margin=False):
+    def run(self, n_steps: int, forced=None, want_state=False, want_margin=False, remote=None):
         """Run n steps; returns raster [n_steps, n] (uint8), counts [n_steps, R],
-        ev_rec/ev_bg [n_steps], optionally per-step states and margins."""
+        ev_rec/ev_bg [n_steps], optionally per-step states and margins.
+        remote: [n_steps, n_remote] spikes of the remote sources (with a
+        remote block)."""
         n = self.net.n
         raster = np.zeros((n_steps, n), dtype=np.uint8)
         counts = np.zeros((n_steps, self.net.n_regions), dtype=np.int64)
@@ -240,6 +266,8 @@ class OracleNet:
         states = [] if want_state else None
         margins = np.full((n_steps, n), np.nan) if want_margin else None
         for s in range(n_steps):
+            if remote is not None:
+                self.give_remote(remote[s])
             o = self.step(None if forced is None else forced[s], want_margin=want_margin)
             raster[s] = o["spikes"]
             counts[s] = o["counts"]

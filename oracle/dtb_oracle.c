@@ -161,6 +161,16 @@ typedef struct {
   int ou_on;
   double ou_mu, ou_a, ou_s;
   double* ou; /* [n] */
+  /* remote in-edge block (J_inter of Sec. V-B): sources are n_remote neurons
+     of other partitions whose spikes are given step by step */
+  int64_t n_remote;
+  int64_t* r_row_ptr; /* [n+1] */
+  int32_t* r_col;
+  float* r_w;
+  uint8_t* r_delay;
+  uint8_t* r_inh;     /* [n_remote] */
+  uint8_t* r_ring;    /* [max_delay][n_remote] */
+  int64_t r_given;    /* step whose remote spikes are in the ring (-1: none) */
 } ora_net;
 
 void ora_destroy(ora_net* h) {
@@ -168,6 +178,7 @@ void ora_destroy(ora_net* h) {
   free(h->C); free(h->gL); free(h->EL); free(h->Vth); free(h->Vreset); free(h->Iext);
   free(h->g); free(h->nref); free(h->V); free(h->j); free(h->ref); free(h->ring); free(h->gain);
   free(h->ou);
+  free(h->r_row_ptr); free(h->r_col); free(h->r_w); free(h->r_delay); free(h->r_inh); free(h->r_ring);
   free(h);
 }
 
@@ -229,6 +240,45 @@ int ora_set_ou(ora_net* h, double mu, double sigma, double tau_ms) {
   return 0;
 }
 
+/* Add the remote in-edge block: CSR over the n local rows (row_ptr [n+1],
+   col [nnz] in [0, n_remote), w, delay in [1, max_delay]) and the remote
+   sources' inhibitory flags.  The arrays are copied.  From then on every step
+   needs ora_give_remote first.  Returns -1 on bad input or a second call. */
+int ora_set_remote(ora_net* h, int64_t n_remote, const int64_t* row_ptr, const int32_t* col,
+                   const float* w, const uint8_t* delay, const uint8_t* inh) {
+  const int64_t n = h->in.n;
+  if (h->r_row_ptr || n_remote < 1 || row_ptr[0] != 0) return -1;
+  const int64_t nnz = row_ptr[n];
+  for (int64_t i = 0; i < n; i++)
+    if (row_ptr[i + 1] < row_ptr[i]) return -1;
+  for (int64_t k = 0; k < nnz; k++)
+    if (col[k] < 0 || col[k] >= n_remote || delay[k] < 1 || delay[k] > h->in.max_delay) return -1;
+  h->r_row_ptr = malloc(sizeof(int64_t) * (n + 1));
+  h->r_col = malloc(sizeof(int32_t) * (nnz + 1));
+  h->r_w = malloc(sizeof(float) * (nnz + 1));
+  h->r_delay = malloc(nnz + 1);
+  h->r_inh = malloc(n_remote);
+  h->r_ring = calloc((size_t)n_remote * h->in.max_delay, 1);
+  if (!h->r_row_ptr || !h->r_col || !h->r_w || !h->r_delay || !h->r_inh || !h->r_ring) return -1;
+  memcpy(h->r_row_ptr, row_ptr, sizeof(int64_t) * (n + 1));
+  memcpy(h->r_col, col, sizeof(int32_t) * nnz);
+  memcpy(h->r_w, w, sizeof(float) * nnz);
+  memcpy(h->r_delay, delay, nnz);
+  memcpy(h->r_inh, inh, n_remote);
+  h->n_remote = n_remote;
+  h->r_given = -1;
+  return 0;
+}
+
+/* The spikes [n_remote] (0/1) the remote sources emit at the coming step. */
+int ora_give_remote(ora_net* h, const uint8_t* spikes) {
+  if (!h->r_row_ptr) return -1;
+  uint8_t* slot = h->r_ring + (size_t)(h->t % h->in.max_delay) * h->n_remote;
+  for (int64_t m = 0; m < h->n_remote; m++) slot[m] = spikes[m] ? 1 : 0;
+  h->r_given = h->t;
+  return 0;
+}
+
 int ora_set_gain(ora_net* h, const double* gain) {
   for (int r = 0; r < h->in.n_regions; r++)
     for (int u = 0; u < 4; u++) h->gain[4 * r + u] = gain[4 * r + u];
@@ -252,6 +302,7 @@ int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_r
   const int D = in->max_delay;
   const int64_t t = h->t;
   if (rows && !forced) return -1;
+  if (h->r_row_ptr && h->r_given != t) return -2; /* remote spikes of step t not given */
   const int64_t nr = rows ? n_rows : n;
   uint8_t* slot_now = h->ring + (size_t)(t % D) * n;
 
@@ -301,6 +352,19 @@ int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_r
         if (in->is_inh[m]) dI += (double)in->w[k];
         else dE += (double)in->w[k];
         er++;
+      }
+    }
+    /* J_inter: the remote in-edges, after the local ones, in CSR order */
+    if (h->r_row_ptr) {
+      for (int64_t k = h->r_row_ptr[i]; k < h->r_row_ptr[i + 1]; k++) {
+        const int32_t m = h->r_col[k];
+        const int64_t te = t - (int64_t)h->r_delay[k] + 1;
+        const int64_t sl = ((te % D) + D) % D;
+        if (h->r_ring[(size_t)sl * h->n_remote + m]) {
+          if (h->r_inh[m]) dI += (double)h->r_w[k];
+          else dE += (double)h->r_w[k];
+          er++;
+        }
       }
     }
     const int c = poisson_count(ora_bg_uniform(in->seed, t, i, in->member), h->T, h->K);

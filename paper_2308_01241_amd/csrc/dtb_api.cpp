@@ -124,7 +124,14 @@ struct dtb_net {
   // kernel timing: event pairs per kernel kind, reused after each read
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kTimedKernels];
-  size_t ev_used[kTimedKernels] = {0, 0, 0, 0, 0};
+  size_t ev_used[kTimedKernels] = {};
+  // remote in-edge block (J_inter): its gather runs on a second stream,
+  // forked from and joined back into the handle's stream every step
+  bool remote = false;
+  hipStream_t comm = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  int64_t rq_head = 0;     // queue row of the first pending remote step
+  int64_t rq_pending = 0;  // remote steps pushed and not yet consumed
 };
 
 namespace {
@@ -241,13 +248,25 @@ void parallel_items(int64_t n, const std::function<void(int64_t)>& fn) {
 // bundles, each bundle's synapses once in CSR order (weights, sign bit =
 // inhibitory source) and once sorted by (delay, source) as 64-entry tiles of
 // (source delta, CSR position) lookups (see dtb_internal.h).
-dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
-  DeviceNet& d = net->d;
+// One in-edge block: n rows given by row_ptr / col / w / delay, sources
+// marked inhibitory by src_inh[col]; bundle_syn as gather_bundle_syn.
+struct BlockInput {
+  int64_t n, nnz;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* w;
+  const uint8_t* delay;
+  const uint8_t* src_inh;
+  int32_t bundle_syn;
+};
+
+dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {
+  const DeviceNet& d = net->d;
   const int64_t n = s->n;
   const std::vector<int64_t>& mrow = net->member_row0;
   // 1. bundles of consecutive rows
   const int64_t max_rows = std::min<int64_t>(65536, std::max<int64_t>(64, (n + 511) / 512));
-  const int64_t max_syn = s->gather_bundle_syn ? int64_t(s->gather_bundle_syn) : kBundleDefaultSyn;
+  const int64_t max_syn = s->bundle_syn ? int64_t(s->bundle_syn) : kBundleDefaultSyn;
   std::vector<Bundle> bl;
   size_t mq = 0;  // member of row r
   for (int64_t r = 0; r < n;) {
@@ -261,7 +280,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     b.seed = net->member_seed[mq];
     while (r < mend && r - b.row0 < max_rows && s->row_ptr[r + 1] - b.syn0 <= max_syn) ++r;
     // with the default size, a longer row still gets a bundle of its own
-    if (r == b.row0 && !s->gather_bundle_syn && s->row_ptr[r + 1] - b.syn0 <= kBundleMaxSyn) ++r;
+    if (r == b.row0 && !s->bundle_syn && s->row_ptr[r + 1] - b.syn0 <= kBundleMaxSyn) ++r;
     if (r == b.row0)
       return fail(DTB_ERR_UNSUPPORTED, "row " + std::to_string(r) + " has more than " +
                                            std::to_string(max_syn) + " synapses (gather_bundle_syn)");
@@ -335,10 +354,10 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     ntiles += bl[q].ntiles;
     hw = std::max(hw, int32_t(bl[q].nsyn >> 5) + 1);
   }
-  d.n_bundles = nb;
-  d.n_tiles = ntiles;
-  d.hit_words = hw;
-  d.hit_total_words = hwords;
+  cb.n_bundles = nb;
+  cb.n_tiles = ntiles;
+  cb.hit_words = hw;
+  cb.hit_total_words = hwords;
   // contiguous bundle ranges per XCD with about equal numbers of tiles
   int64_t xf[9];
   {
@@ -350,8 +369,8 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
       xf[x] = q;
     }
     xf[8] = nb;
-    d.xcd_max = 0;
-    for (int x = 0; x < 8; ++x) d.xcd_max = std::max(d.xcd_max, xf[x + 1] - xf[x]);
+    cb.xcd_max = 0;
+    for (int x = 0; x < 8; ++x) cb.xcd_max = std::max(cb.xcd_max, xf[x + 1] - xf[x]);
   }
   // the bundle of each 1024-row block's first row (bundles are consecutive row ranges)
   const int64_t nblk = (n + 1023) / 1024;
@@ -365,10 +384,10 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
   }
   dtb_status st;
   const size_t wsz = d.wtype == DTB_W_BF16 ? 2 : 4;
-  if ((st = dalloc(net, &d.bundles, nb)) || (st = dalloc(net, &d.tiles, std::max<int64_t>(1, ntiles) * kTile)) ||
-      (st = dalloc(net, &d.hitbuf, std::max<int64_t>(1, hwords))) ||
-      (st = dalloc(net, &d.block_bundle, int64_t(blk.size()))) || (st = dalloc(net, &d.xcd_first, 9)) ||
-      (st = dalloc(net, &d.theads, std::max<int64_t>(1, ntiles))) || (st = dalloc(net, &d.row_ptr, n + 1)))
+  if ((st = dalloc(net, &cb.bundles, nb)) || (st = dalloc(net, &cb.tiles, std::max<int64_t>(1, ntiles) * kTile)) ||
+      (st = dalloc(net, &cb.hitbuf, std::max<int64_t>(1, hwords))) ||
+      (st = dalloc(net, &cb.block_bundle, int64_t(blk.size()))) || (st = dalloc(net, &cb.xcd_first, 9)) ||
+      (st = dalloc(net, &cb.theads, std::max<int64_t>(1, ntiles))) || (st = dalloc(net, &cb.row_ptr, n + 1)))
     return st;
   {
     void* q = nullptr;
@@ -378,17 +397,17 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
       return fail(DTB_ERR_OOM, "hipMalloc of weights failed");
     }
     net->allocs.push_back(q);
-    d.wts = q;
+    cb.wts = q;
   }
-  if ((st = upload(net, d.bundles, bl.data(), nb * sizeof(Bundle))) ||
-      (st = upload(net, d.block_bundle, blk.data(), blk.size() * sizeof(int32_t))) ||
-      (st = upload(net, d.xcd_first, xf, sizeof(xf))) ||
-      (st = upload(net, d.row_ptr, s->row_ptr, (n + 1) * sizeof(int64_t))))
+  if ((st = upload(net, cb.bundles, bl.data(), nb * sizeof(Bundle))) ||
+      (st = upload(net, cb.block_bundle, blk.data(), blk.size() * sizeof(int32_t))) ||
+      (st = upload(net, cb.xcd_first, xf, sizeof(xf))) ||
+      (st = upload(net, cb.row_ptr, s->row_ptr, (n + 1) * sizeof(int64_t))))
     return st;
   for (int64_t q = 0; q < nb; ++q) {
     if (bl[q].ntiles == 0) continue;
-    if ((st = upload(net, d.tiles + bl[q].tile0 * kTile, btiles[q].data(), btiles[q].size() * 4)) ||
-        (st = upload(net, d.theads + bl[q].tile0, bheads[q].data(), bheads[q].size() * 4)))
+    if ((st = upload(net, cb.tiles + bl[q].tile0 * kTile, btiles[q].data(), btiles[q].size() * 4)) ||
+        (st = upload(net, cb.theads + bl[q].tile0, bheads[q].data(), bheads[q].size() * 4)))
       return st;
     std::vector<uint32_t>().swap(btiles[q]);
     std::vector<uint32_t>().swap(bheads[q]);
@@ -402,7 +421,7 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
     parallel_for(k1 - k0, [&](int64_t a, int64_t b) {
       for (int64_t q = a; q < b; ++q) {
         const int64_t k = k0 + q;
-        const bool inh = s->is_inh[s->col[k]] != 0;
+        const bool inh = s->src_inh[s->col[k]] != 0;
         if (wsz == 4) {
           uint32_t u;
           std::memcpy(&u, &s->w[k], 4);
@@ -415,15 +434,21 @@ dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
         }
       }
     });
-    if ((st = upload(net, static_cast<uint8_t*>(d.wts) + k0 * wsz, hwt.data(), hwt.size()))) return st;
+    if ((st = upload(net, static_cast<uint8_t*>(cb.wts) + k0 * wsz, hwt.data(), hwt.size()))) return st;
   }
   return DTB_OK;
 }
 
+dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
+  BlockInput in{s->n, s->nnz, s->row_ptr, s->col, s->w, s->delay, s->is_inh, s->gather_bundle_syn};
+  return build_block(net, net->d.loc, &in);
+}
+
 // launch `fn`, bracketed by a pair of events when timing is on
 template <typename F>
-hipError_t timed(dtb_net* net, int kind, F fn) {
+hipError_t timed(dtb_net* net, int kind, F fn, hipStream_t st = nullptr) {
   if (!net->timing) return fn();
+  if (!st) st = net->stream;
   auto& pool = net->ev_pool[kind];
   if (net->ev_used[kind] == pool.size()) {
     hipEvent_t a, b;
@@ -434,9 +459,9 @@ hipError_t timed(dtb_net* net, int kind, F fn) {
     pool.emplace_back(a, b);
   }
   auto& pr = pool[net->ev_used[kind]++];
-  hipError_t e = hipEventRecord(pr.first, net->stream);
+  hipError_t e = hipEventRecord(pr.first, st);
   if (e == hipSuccess) e = fn();
-  if (e == hipSuccess) e = hipEventRecord(pr.second, net->stream);
+  if (e == hipSuccess) e = hipEventRecord(pr.second, st);
   return e;
 }
 
@@ -463,6 +488,12 @@ int64_t dtb_bitmap_words(int64_t n) { return n <= 0 ? 0 : (n + 31) / 32; }
 void dtb_destroy(dtb_net* net) {
   if (!net) return;
   (void)hipStreamSynchronize(net->stream);
+  if (net->comm) {
+    (void)hipStreamSynchronize(net->comm);
+    (void)hipStreamDestroy(net->comm);
+  }
+  if (net->fork_ev) (void)hipEventDestroy(net->fork_ev);
+  if (net->join_ev) (void)hipEventDestroy(net->join_ev);
   for (auto& pool : net->ev_pool)
     for (auto& pr : pool) {
       (void)hipEventDestroy(pr.first);
@@ -779,15 +810,36 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
   DeviceNet& d = net->d;
   for (int32_t q = 0; q < n_steps; ++q) {
     const int64_t t = net->t;
+    if (net->remote && net->rq_pending == 0)
+      return fail(DTB_ERR_STATE, "no remote spikes pushed for step " + std::to_string(t));
     const uint32_t* forced = nullptr;
     if (net->force_pending > 0) {
       forced = d.force + (net->force_head % (d.rec + 1)) * d.words_pad;
       net->force_head++;
       net->force_pending--;
     }
-    hipError_t e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
+    hipError_t e = hipSuccess;
+    if (net->remote) {
+      // J_inter on the second stream: this step's remote bitmap from the
+      // queue into the remote ring, then the remote block's delivery tests,
+      // concurrent with the update, compaction and J_intra delivery tests
+      const uint32_t* row = d.rqueue + (net->rq_head % (d.rec + 1)) * d.rwords_pad;
+      e = hipEventRecord(net->fork_ev, net->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(net->comm, net->fork_ev, 0);
+      if (e == hipSuccess)
+        e = launch_copy_words(d.rraster + (t % d.slots) * d.rwords_pad, row, d.rwords_pad, net->comm);
+      if (e == hipSuccess)
+        e = timed(net, 5, [&] { return launch_gather(d, d.rem, d.rraster, d.rwords_pad, net->comm); }, net->comm);
+      if (e == hipSuccess) e = hipEventRecord(net->join_ev, net->comm);
+      if (e != hipSuccess) return hip_fail(net, e, "remote block launch");
+      net->rq_head++;
+      net->rq_pending--;
+    }
+    if (e == hipSuccess) e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
     if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
-    if (e == hipSuccess) e = timed(net, 2, [&] { return launch_gather(d, net->stream); });
+    if (e == hipSuccess)
+      e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, net->stream); });
+    if (e == hipSuccess && net->remote) e = hipStreamWaitEvent(net->stream, net->join_ev, 0);
     if (e == hipSuccess) e = timed(net, 3, [&] { return launch_sums(d, net->stream); });
     if (e == hipSuccess) e = timed(net, 4, [&] { return launch_finalize(d, net->stream); });
     if (e != hipSuccess) return hip_fail(net, e, "kernel launch");
@@ -801,6 +853,8 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
   if (st) return st;
   if (n_steps < 0) return fail(DTB_ERR_INVALID, "n_steps must be >= 0");
   if (net->force_pending) return fail(DTB_ERR_STATE, "teacher forcing is pending: use dtb_step");
+  if (net->remote)
+    return fail(DTB_ERR_UNSUPPORTED, "a remote in-edge block takes one pushed bitmap per step: use dtb_step");
   if (n_steps == 0) return DTB_OK;
   DeviceNet& d = net->d;
   hipError_t e = hipSuccess;
@@ -813,7 +867,7 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
     for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
       e = launch_neuron_update(d, nullptr, net->stream);
       if (e == hipSuccess) e = launch_compact(d, net->stream);
-      if (e == hipSuccess) e = launch_gather(d, net->stream);
+      if (e == hipSuccess) e = launch_gather(d, d.loc, d.raster, d.words_pad, net->stream);
       if (e == hipSuccess) e = launch_sums(d, net->stream);
       if (e == hipSuccess) e = launch_finalize(d, net->stream);
     }
@@ -845,11 +899,14 @@ dtb_status dtb_reset(dtb_net* net) {
     if (e == hipSuccess) e = hipMemsetAsync(pr.first, 0, pr.second, net->stream);
   }
   if (e == hipSuccess && d.ou_on) e = launch_fill(d.ou, d.n_pad, d.ou_mu, net->stream);
+  if (e == hipSuccess && net->remote) e = launch_copy_words(d.rraster, nullptr, slots * d.rwords_pad, net->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
   if (e != hipSuccess) return hip_fail(net, e, "reset");
   net->t = 0;
   net->force_pending = 0;
   net->force_head = 0;
+  net->rq_pending = 0;
+  net->rq_head = 0;
   return DTB_OK;
 }
 
@@ -913,6 +970,77 @@ dtb_status dtb_force_spikes(dtb_net* net, const uint32_t* bits, int32_t n_steps)
     if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy forced spikes");
     net->force_pending++;
   }
+  return DTB_OK;
+}
+
+dtb_status dtb_set_remote_block(dtb_net* net, int64_t n_remote, int64_t nnz, const int64_t* row_ptr,
+                                const int32_t* col, const float* w, const uint8_t* delay,
+                                const uint8_t* remote_is_inh) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  DeviceNet& d = net->d;
+  if (net->remote) return fail(DTB_ERR_STATE, "the remote block is already set");
+  if (net->t != 0) return fail(DTB_ERR_STATE, "set the remote block before the first step (or after dtb_reset)");
+  if (net->member_row0.size() != 1) return fail(DTB_ERR_UNSUPPORTED, "a remote block needs a single-member handle");
+  if (n_remote < 1 || n_remote > (int64_t(1) << 26) - 1)
+    return fail(DTB_ERR_INVALID, "n_remote must be in [1, 2^26 - 1]");
+  if (nnz < 0 || !row_ptr || (nnz > 0 && (!col || !w || !delay)) || !remote_is_inh)
+    return fail(DTB_ERR_INVALID, "null remote block array");
+  if (row_ptr[0] != 0 || row_ptr[d.n] != nnz) return fail(DTB_ERR_INVALID, "row_ptr must run from 0 to nnz");
+  int64_t bad = find_first(d.n, [&](int64_t i) { return row_ptr[i + 1] < row_ptr[i]; });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "row_ptr decreases at row " + std::to_string(bad));
+  bad = find_first(nnz, [&](int64_t k) { return col[k] < 0 || int64_t(col[k]) >= n_remote; });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "remote col out of range at synapse " + std::to_string(bad));
+  bad = find_first(nnz, [&](int64_t k) { return delay[k] < 1 || delay[k] > d.max_delay; });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "delay out of [1, max_delay] at synapse " + std::to_string(bad));
+  bad = find_first(nnz, [&](int64_t k) { return !(finite_f(w[k]) && w[k] >= 0.f); });
+  if (bad >= 0) return fail(DTB_ERR_INVALID, "weight not finite and >= 0 at synapse " + std::to_string(bad));
+  BlockInput in{d.n, nnz, row_ptr, col, w, delay, remote_is_inh, 0};
+  if ((st = build_block(net, d.rem, &in))) return st;
+  d.n_remote = n_remote;
+  d.rwords_pad = round_up(n_remote, kNeuronPad) / 32;
+  if ((st = dalloc(net, &d.rraster, int64_t(d.slots) * d.rwords_pad)) ||
+      (st = dalloc(net, &d.rqueue, (d.rec + 1) * d.rwords_pad)))
+    return st;
+  hipError_t e = launch_copy_words(d.rraster, nullptr, int64_t(d.slots) * d.rwords_pad, net->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e == hipSuccess) e = hipStreamCreate(&net->comm);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&net->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&net->join_ev, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(net, e, "remote block set-up");
+  drop_graph(net);
+  net->remote = true;
+  net->rq_head = 0;
+  net->rq_pending = 0;
+  return DTB_OK;
+}
+
+dtb_status dtb_push_remote_spikes(dtb_net* net, const uint32_t* bits, int32_t n_steps) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!net->remote) return fail(DTB_ERR_STATE, "no remote block set");
+  if (n_steps < 0 || (n_steps > 0 && !bits)) return fail(DTB_ERR_INVALID, "bad bits / n_steps");
+  DeviceNet& d = net->d;
+  if (net->rq_pending + n_steps > d.rec)
+    return fail(DTB_ERR_INVALID, "more remote steps pending than record_steps");
+  if (net->rq_pending == 0) net->rq_head = 0;
+  const int64_t rw = dtb_bitmap_words(d.n_remote);
+  const uint32_t tail = (d.n_remote & 31) ? (1u << (d.n_remote & 31)) - 1u : ~0u;
+  std::vector<uint32_t> rows(size_t(n_steps) * d.rwords_pad, 0u);
+  for (int32_t q = 0; q < n_steps; ++q) {
+    uint32_t* r = rows.data() + size_t(q) * d.rwords_pad;
+    std::memcpy(r, bits + size_t(q) * rw, size_t(rw) * 4);
+    r[rw - 1] &= tail;  // bits past n_remote are not neurons
+  }
+  for (int32_t q = 0; q < n_steps; ++q) {
+    const int64_t slot = (net->rq_head + net->rq_pending) % (d.rec + 1);
+    hipError_t e = hipMemcpyAsync(d.rqueue + slot * d.rwords_pad, rows.data() + size_t(q) * d.rwords_pad,
+                                  d.rwords_pad * 4, hipMemcpyHostToDevice, net->stream);
+    if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy remote spikes");
+    net->rq_pending++;
+  }
+  hipError_t e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy remote spikes");
   return DTB_OK;
 }
 

@@ -63,7 +63,7 @@ constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap w
 #define DTB_GATHER_BUNDLE_SYN 1048575
 #endif
 constexpr int kGatherThreads = DTB_GATHER_THREADS;
-constexpr int kTimedKernels = 5;  // neuron update, compaction, gather, sums, finalize
+constexpr int kTimedKernels = 6;  // neuron update, compaction, gather, sums, finalize, remote gather
 constexpr int kGatherUnroll = DTB_GATHER_UNROLL;
 constexpr int64_t kBundleDefaultSyn = DTB_GATHER_BUNDLE_SYN;
 static_assert(kBundleDefaultSyn <= kBundleMaxSyn, "bundle positions are 20 bits");
@@ -79,6 +79,28 @@ struct Bundle {
   int32_t ntiles;       // tiles of the lookup stream
   int32_t nsyn;         // synapses of the bundle
   int64_t hbit0;        // bit of the hit buffer that holds the bundle's synapse 0 (a multiple of 32)
+};
+
+// One in-edge block in the gather's layout: the rows' synapses cut into
+// bundles, their lookup tiles, the per-bundle hit words written by the
+// delivery tests, and the CSR row pointers and signed weights the sums read.
+// A partition has its local block (sources = its own neurons) and, with
+// dtb_set_remote_block, a remote block (sources = neurons of other
+// partitions, replayed).
+struct ConnBlock {
+  int64_t n_bundles = 0, n_tiles = 0;
+  int32_t hit_words = 1;            // LDS words of the largest bundle's hit bitmap
+  int64_t hit_total_words = 0;
+  int64_t xcd_max = 0;              // most bundles of one XCD
+  Bundle* bundles = nullptr;        // [n_bundles]
+  int32_t* block_bundle = nullptr;  // [ceil(n / 1024)] bundle of each 1024-row block's first row
+  int64_t* xcd_first = nullptr;     // [9] bundles [xcd_first[x], xcd_first[x+1]) go to XCD x (equal tiles)
+  uint32_t* tiles = nullptr;        // [n_tiles][kTile] lookup entries
+  uint32_t* theads = nullptr;       // [n_tiles] tile headers
+  uint32_t* hitbuf = nullptr;       // [hit_total_words] delivery-test results: per bundle, one bit per
+                                    // synapse in CSR order (from bit hbit0), rewritten every step
+  int64_t* row_ptr = nullptr;       // [n + 1]
+  void* wts = nullptr;              // [nnz] float or bf16, sign bit = inhibitory source
 };
 
 // Derived per-type constants in the order the neuron update reads them.
@@ -99,8 +121,6 @@ struct DeviceNet {
   int32_t slots = 0;                // spike-bitmap ring slots: max(rec, D) + 1
   int32_t poisson_K = 0, poisson_cap = 1;
   int64_t compact_blocks = 0;
-  int64_t n_bundles = 0, n_tiles = 0;
-  int32_t hit_words = 1;            // LDS words of the largest bundle's hit bitmap
   float a[4] = {0, 0, 0, 0};        // exp(-dt / tau_u)
   float E[4] = {0, 0, 0, 0};        // reversal potentials
   float bg_w = 0.f;
@@ -119,18 +139,11 @@ struct DeviceNet {
   PType* ptab = nullptr;            // [n_ptypes]
   float* gain = nullptr;            // [n_regions][4]
   uint32_t* poisson = nullptr;      // [poisson_K]
-  // connection table
-  int64_t* row_ptr = nullptr;       // [n + 1]
-  void* wts = nullptr;              // [nnz] float or bf16, sign bit = inhibitory source
-  uint32_t* tiles = nullptr;        // [n_tiles][kTile] lookup entries
-  uint32_t* theads = nullptr;       // [n_tiles] tile headers
-  Bundle* bundles = nullptr;        // [n_bundles]
-  int32_t* block_bundle = nullptr;  // [ceil(n / 1024)] bundle of each 1024-row block's first row
-  int64_t* xcd_first = nullptr;     // [9] bundles [xcd_first[x], xcd_first[x+1]) go to XCD x (equal tiles)
-  int64_t xcd_max = 0;              // most bundles of one XCD
-  uint32_t* hitbuf = nullptr;       // [hit_total_words] delivery-test results: per bundle, one bit per
-                                    // synapse in CSR order (from bit hbit0), rewritten every step
-  int64_t hit_total_words = 0;
+  // connection tables: local sources, and the optional remote-source block
+  ConnBlock loc, rem;
+  int64_t n_remote = 0, rwords_pad = 0;  // remote neurons; words of one remote bitmap (padded)
+  uint32_t* rraster = nullptr;      // [slots][rwords_pad] remote spike bitmaps: the remote delay ring
+  uint32_t* rqueue = nullptr;       // [rec + 1][rwords_pad] pushed remote bitmaps not yet consumed
   // history and outputs
   uint32_t* raster = nullptr;       // [slots][words_pad] spike bitmaps: the delay ring
   int32_t* counts = nullptr;        // [slots][n_regions]
@@ -155,7 +168,9 @@ struct DeviceNet {
 hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s);
 hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
 hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
-hipError_t launch_gather(const DeviceNet& d, hipStream_t s);
+hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
+                         hipStream_t s);
+hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, int64_t n, hipStream_t s);
 hipError_t launch_finalize(const DeviceNet& d, hipStream_t s);
 hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s);
 hipError_t gather_set_lds_limit();

@@ -468,83 +468,97 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
 
 // ------------------------------------------------------------------- sums
 // One thread per neuron (row): the delivered weights in the row's CSR order
-// (the fixed per-neuron summation order), then the background count
-// (Philox4x64-10, counter (t, i, member, 0) with i the neuron's index inside
-// its member network), then the four gates (exact decay + jump).  The row's
-// delivery tests are the bits hbit0 + (k - syn0) of its bundle in the hit
-// buffer.
+// (the fixed per-neuron summation order) - the local block, then the remote
+// block if there is one - then the background count (Philox4x64-10, counter
+// (t, i, member, 0) with i the neuron's index inside its member network),
+// then the four gates (exact decay + jump).  A row's delivery tests are the
+// bits hbit0 + (k - syn0) of its bundle in the block's hit buffer.
 constexpr int kSumsThreads = 1024;
+
+// the tables one in-edge block hands to the sums
+struct SumBlock {
+  const Bundle* bundles;
+  const int32_t* block_bundle;
+  const int64_t* row_ptr;
+  const void* wts;
+  const uint32_t* hitbuf;
+};
+
+// adds row r's delivered weights of one block to (dE, dI) in CSR order;
+// returns the row's bundle
+template <bool kBF16>
+__device__ inline const Bundle* block_row_sum(const SumBlock& S, int64_t r, float& dE, float& dI) {
+  constexpr int kHitBatch = 8;
+  int32_t b = S.block_bundle[r / kSumsThreads];
+  while (r >= S.bundles[b].row1) ++b;  // bundles are consecutive row ranges
+  const Bundle* B = S.bundles + b;
+  const int64_t k0 = S.row_ptr[r], k1 = S.row_ptr[r + 1];
+  const int len = int(k1 - k0);
+  if (len <= 0) return B;
+  const float* wf = reinterpret_cast<const float*>(S.wts);
+  const uint16_t* wb = reinterpret_cast<const uint16_t*>(S.wts);
+  const int64_t bit0 = B->hbit0 + (k0 - B->syn0);
+  // bits [bit0, bit0 + len) of the hit buffer, visited in ascending order
+  int64_t w = bit0 >> 5;
+  const int64_t w1 = (bit0 + len - 1) >> 5;
+  uint32_t bits = S.hitbuf[w] & (~0u << (bit0 & 31));
+  const uint32_t last = ~0u >> (31 - int((bit0 + len - 1) & 31));
+  while (true) {
+    // collect up to kHitBatch hit offsets of this row, then load their weights together
+    int hp[kHitBatch];
+    int nh = 0;
+    while (nh < kHitBatch) {
+      if (w == w1) bits &= last;
+      if (bits) {
+        hp[nh++] = int((w << 5) + (__ffs(bits) - 1) - bit0);
+        bits &= bits - 1u;
+      } else if (w < w1) {
+        bits = S.hitbuf[++w];
+      } else {
+        break;
+      }
+    }
+    uint32_t x[kHitBatch];
+#pragma unroll
+    for (int q = 0; q < kHitBatch; ++q)
+      if (q < nh)
+        x[q] = kBF16 ? uint32_t(stream_load(wb + k0 + hp[q])) << 16 : __float_as_uint(stream_load(wf + k0 + hp[q]));
+#pragma unroll
+    for (int q = 0; q < kHitBatch; ++q) {
+      if (q < nh) {
+        const float wv = __uint_as_float(x[q] & 0x7FFFFFFFu);
+        if (x[q] >> 31) dI += wv;
+        else dE += wv;
+      }
+    }
+    if (nh < kHitBatch) break;
+  }
+  return B;
+}
 
 template <bool kBF16>
 __global__ __launch_bounds__(kSumsThreads) void k_sums(
-    int64_t n, int64_t n_pad, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
-    const int32_t* __restrict__ block_bundle, const int64_t* __restrict__ row_ptr, const void* __restrict__ wts_v,
-    const uint32_t* __restrict__ hitbuf, float* __restrict__ j, float a0, float a1, float a2, float a3,
-    float bg_w, const uint32_t* __restrict__ poisson, int K, float* __restrict__ ou, float ou_mu, float ou_a,
-    float ou_s, int64_t* __restrict__ ev_ring, int32_t* __restrict__ bad) {
+    int64_t n, int64_t n_pad, const int64_t* __restrict__ step, SumBlock loc, SumBlock rem, int has_rem,
+    float* __restrict__ j, float a0, float a1, float a2, float a3, float bg_w,
+    const uint32_t* __restrict__ poisson, int K, float* __restrict__ ou, float ou_mu, float ou_a, float ou_s,
+    int64_t* __restrict__ ev_ring, int32_t* __restrict__ bad) {
   __shared__ uint32_t s_bg[kSumsThreads / 64];
   const int64_t t = step[0];
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(step[1]) * kStripes * 2;
   const int tid = threadIdx.x, lane = tid & 63;
   const int64_t r = int64_t(blockIdx.x) * kSumsThreads + tid;
-  constexpr int kHitBatch = 8;
-  const float* wf = reinterpret_cast<const float*>(wts_v);
-  const uint16_t* wb = reinterpret_cast<const uint16_t*>(wts_v);
   uint32_t evb = 0;
   if (r < n) {
-    // the row's bundle: bundles are consecutive row ranges
-    int32_t b = block_bundle[blockIdx.x];
-    while (r >= bundles[b].row1) ++b;
-    const Bundle* B = bundles + b;
-    const int64_t k0 = row_ptr[r], k1 = row_ptr[r + 1];
     const float j0 = j[r], j1 = j[n_pad + r], j2 = j[2 * n_pad + r], j3 = j[3 * n_pad + r];
+    float dE = 0.f, dI = 0.f;
+    const Bundle* B = block_row_sum<kBF16>(loc, r, dE, dI);
+    if (has_rem) block_row_sum<kBF16>(rem, r, dE, dI);
     const uint64_t seed = B->seed;
     const int64_t mrow0 = B->member_row0;
     const int32_t member = B->member;
-    const int64_t bit0 = B->hbit0 + (k0 - B->syn0);
     const uint32_t u = ou ? 0u
                           : uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - mrow0), uint64_t(member), 0ull,
                                                        seed, 0ull));
-    float dE = 0.f, dI = 0.f;
-    const int len = int(k1 - k0);
-    if (len > 0) {
-      // bits [bit0, bit0 + len) of the hit buffer, visited in ascending order
-      int64_t w = bit0 >> 5;
-      const int64_t w1 = (bit0 + len - 1) >> 5;
-      uint32_t bits = hitbuf[w] & (~0u << (bit0 & 31));
-      const uint32_t last = ~0u >> (31 - int((bit0 + len - 1) & 31));
-      while (true) {
-        // collect up to kHitBatch hit offsets of this row, then load their weights together
-        int hp[kHitBatch];
-        int nh = 0;
-        while (nh < kHitBatch) {
-          if (w == w1) bits &= last;
-          if (bits) {
-            hp[nh++] = int((w << 5) + (__ffs(bits) - 1) - bit0);
-            bits &= bits - 1u;
-          } else if (w < w1) {
-            bits = hitbuf[++w];
-          } else {
-            break;
-          }
-        }
-        uint32_t x[kHitBatch];
-#pragma unroll
-        for (int q = 0; q < kHitBatch; ++q)
-          if (q < nh)
-            x[q] = kBF16 ? uint32_t(stream_load(wb + k0 + hp[q])) << 16
-                         : __float_as_uint(stream_load(wf + k0 + hp[q]));
-#pragma unroll
-        for (int q = 0; q < kHitBatch; ++q) {
-          if (q < nh) {
-            const float wv = __uint_as_float(x[q] & 0x7FFFFFFFu);
-            if (x[q] >> 31) dI += wv;
-            else dE += wv;
-          }
-        }
-        if (nh < kHitBatch) break;
-      }
-    }
     const int c = poisson_count(u, poisson, K);
     evb = uint32_t(c);
     dE = __fmaf_rn(float(c), bg_w, dE);
@@ -683,20 +697,23 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s) {
 namespace {
 
 template <int kU>
-void launch_gather_as(const DeviceNet& d, hipStream_t s) {
-  const unsigned grid = unsigned(d.xcd_max * 8);
-  const size_t lds = size_t(d.hit_words) * 4;
-  hipLaunchKernelGGL((k_gather<kU>), dim3(grid), dim3(kGatherThreads), lds, s, d.xcd_first, d.step, d.bundles,
-                     d.tiles, d.theads, d.raster, d.words_pad, d.slots, d.hitbuf, d.ev);
+void launch_gather_as(const ConnBlock& cb, const int64_t* step, const uint32_t* bitmaps, int64_t words_pad,
+                      int32_t slots, int64_t* ev, hipStream_t s) {
+  const unsigned grid = unsigned(cb.xcd_max * 8);
+  const size_t lds = size_t(cb.hit_words) * 4;
+  hipLaunchKernelGGL((k_gather<kU>), dim3(grid), dim3(kGatherThreads), lds, s, cb.xcd_first, step, cb.bundles,
+                     cb.tiles, cb.theads, bitmaps, words_pad, slots, cb.hitbuf, ev);
 }
 
 }  // namespace
 
-hipError_t launch_gather(const DeviceNet& d, hipStream_t s) {
+hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
+                         hipStream_t s) {
+  if (cb.n_bundles == 0) return hipSuccess;
   switch (d.unroll) {
-    case 1: launch_gather_as<1>(d, s); break;
-    case 2: launch_gather_as<2>(d, s); break;
-    default: launch_gather_as<3>(d, s); break;
+    case 1: launch_gather_as<1>(cb, d.step, bitmaps, words_pad, d.slots, d.ev, s); break;
+    case 2: launch_gather_as<2>(cb, d.step, bitmaps, words_pad, d.slots, d.ev, s); break;
+    default: launch_gather_as<3>(cb, d.step, bitmaps, words_pad, d.slots, d.ev, s); break;
   }
   return hipGetLastError();
 }
@@ -716,14 +733,32 @@ hipError_t gather_set_lds_limit() {
 
 hipError_t launch_sums(const DeviceNet& d, hipStream_t s) {
   const unsigned grid = unsigned((d.n + kSumsThreads - 1) / kSumsThreads);
+  const SumBlock loc{d.loc.bundles, d.loc.block_bundle, d.loc.row_ptr, d.loc.wts, d.loc.hitbuf};
+  const SumBlock rem{d.rem.bundles, d.rem.block_bundle, d.rem.row_ptr, d.rem.wts, d.rem.hitbuf};
+  const int has_rem = d.rem.n_bundles > 0 ? 1 : 0;
   if (d.wtype == DTB_W_BF16)
-    hipLaunchKernelGGL(k_sums<true>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, d.bundles,
-                       d.block_bundle, d.row_ptr, d.wts, d.hitbuf, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w,
-                       d.poisson, d.poisson_K, d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
+    hipLaunchKernelGGL(k_sums<true>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
+                       d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
+                       d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
   else
-    hipLaunchKernelGGL(k_sums<false>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, d.bundles,
-                       d.block_bundle, d.row_ptr, d.wts, d.hitbuf, d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w,
-                       d.poisson, d.poisson_K, d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
+    hipLaunchKernelGGL(k_sums<false>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
+                       d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
+                       d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ __launch_bounds__(256) void k_copy_words(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                                    int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) dst[i] = src ? src[i] : 0u;
+}
+}  // namespace
+
+// dst[0, n) = src[0, n), or zeros when src is null
+hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_words, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
 

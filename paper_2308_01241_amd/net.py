@@ -60,6 +60,7 @@ class Net:
         self.n_regions = int(roff[-1])
         self.words = int(lib.dtb_bitmap_words(self.n))
         self.record_steps = int(record_steps)
+        self.n_remote = 0
         self.t = 0
 
     @classmethod
@@ -115,15 +116,39 @@ class Net:
         bits = pack_bits(r, self.words)
         check(self._lib.dtb_force_spikes(self._h, _ptr(bits), int(r.shape[0])))
 
+    def set_remote_block(self, block) -> None:
+        """Second in-edge block from n_remote neurons of other partitions
+        (J_inter); their spikes are replayed with push_remote."""
+        keep = [np.ascontiguousarray(block.row_ptr, dtype=np.int64), np.ascontiguousarray(block.col, dtype=np.int32),
+                np.ascontiguousarray(block.w, dtype=np.float32), np.ascontiguousarray(block.delay, dtype=np.uint8),
+                np.ascontiguousarray(block.is_inh, dtype=np.uint8)]
+        if keep[0].shape != (self.n + 1,) or keep[4].shape != (int(block.n_remote),):
+            raise ValueError("remote block shapes do not match n / n_remote")
+        check(self._lib.dtb_set_remote_block(self._h, int(block.n_remote), int(keep[0][-1]),
+                                             *[_ptr(a) for a in keep]))
+        self.n_remote = int(block.n_remote)
+        self.remote_words = (self.n_remote + 31) // 32
+
+    def push_remote(self, raster: np.ndarray) -> None:
+        """Queue the remote spikes of the next steps: raster [n_steps, n_remote] of 0/1."""
+        r = np.ascontiguousarray(raster, dtype=np.uint8).reshape(-1, self.n_remote)
+        self.push_remote_bits(pack_bits(r, self.remote_words))
+
+    def push_remote_bits(self, bits: np.ndarray) -> None:
+        """Queue packed remote spikes [n_steps, ceil(n_remote / 32)] uint32."""
+        b = np.ascontiguousarray(bits, dtype=np.uint32)
+        b = b.reshape(-1, self.remote_words) if self.n_remote else b.reshape(1, -1)
+        check(self._lib.dtb_push_remote_spikes(self._h, _ptr(b), int(b.shape[0])))
+
     def set_timing(self, enable: bool) -> None:
         check(self._lib.dtb_set_timing(self._h, 1 if enable else 0))
 
     def read_timing(self) -> dict:
         """Summed kernel durations (ms) and launch counts since the last read."""
-        ms = np.zeros(5, dtype=np.float64)
-        n = np.zeros(5, dtype=np.int64)
+        ms = np.zeros(6, dtype=np.float64)
+        n = np.zeros(6, dtype=np.int64)
         check(self._lib.dtb_read_timing(self._h, _ptr(ms), _ptr(n)))
-        names = ("neuron_update", "compact", "gather", "sums", "finalize")
+        names = ("neuron_update", "compact", "gather", "sums", "finalize", "remote_gather")
         return {k: {"ms": float(ms[q]), "launches": int(n[q])} for q, k in enumerate(names)}
 
     def sync(self) -> None:
