@@ -76,13 +76,14 @@ def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) ->
 OU_BACKGROUND = (0.6, 0.4, 8.0)  # mu, sigma (units of Iext), tau (ms)
 
 
-def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0), ou=None):
+def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0), ou=None, keep_bits=False):
     import torch
     import paper_2308_01241_amd as dtb
 
     net.bg_lambda = lam
     t0 = time.time()
-    g = dtb.Net(net, wtype=wtype, record_steps=max(steps, 16), stream=torch.cuda.current_stream(),
+    rec = warmup + steps if keep_bits else max(steps, 16)
+    g = dtb.Net(net, wtype=wtype, record_steps=rec, stream=torch.cuda.current_stream(),
                 bundle_syn=shape[0], unroll=shape[1])
     torch.cuda.synchronize()
     log(f"[bench] {rate} Hz: created in {time.time() - t0:.1f}s; warmup {warmup}")
@@ -105,6 +106,7 @@ def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0), ou=None):
     ev = c1["ev_rec"] - c0["ev_rec"]
     spikes = c1["spikes"] - c0["spikes"]
     rates = g.region_rates(g.t - min(steps, g.record_steps), g.t)
+    bits = g.spikes_bits(0, g.t) if keep_bits else None
     g.close()
     del g
     torch.cuda.synchronize()
@@ -112,7 +114,52 @@ def run_rate(net, rate, lam, steps, warmup, wtype, shape=(0, 0), ou=None):
             "events": ev, "events_per_s": ev / wall, "rtf": wall / (steps * net.dt_ms * 1e-3),
             "mean_rate_hz": spikes / (net.n * steps * net.dt_ms * 1e-3),
             "region_rate_spread": [float(np.min(rates)), float(np.max(rates))],
-            "bg_events_per_s": (c1["ev_bg"] - c0["ev_bg"]) / wall, "kernels": kt, "region_rates": rates}
+            "bg_events_per_s": (c1["ev_bg"] - c0["ev_bg"]) / wall, "kernels": kt, "region_rates": rates,
+            "bits": bits}
+
+
+def run_split(net, bits, steps, warmup, k_local=70):
+    """J_intra / J_inter split: the partition keeps each row's first k_local
+    (own-region) in-edges, the cross-region rest becomes a remote block
+    whose sources mirror the partition, and the unsplit run's raster is
+    replayed as the remote spikes (inputs resident in HBM before the timed
+    steps).  Returns the timed rates and whether the raster is the unsplit
+    one bit for bit."""
+    import torch
+    import netgen
+    import paper_2308_01241_amd as dtb
+
+    t0 = time.time()
+    local, blk = netgen.split_remote(net, k_local)
+    g = dtb.Net(local, record_steps=max(steps, 16), stream=torch.cuda.current_stream())
+    g.set_remote_block(blk)
+    del local, blk
+    torch.cuda.synchronize()
+    log(f"[bench] j_inter split: created in {time.time() - t0:.1f}s")
+    g.push_remote_bits(bits[:warmup])
+    g.step(warmup)
+    g.push_remote_bits(bits[warmup:warmup + steps])
+    g.sync()
+    c0 = g.counters()
+    g.read_timing()
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    tic = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tic
+    g.set_timing(False)
+    kt = g.read_timing()
+    c1 = g.counters()
+    same = bool(np.array_equal(g.spikes_bits(warmup, warmup + steps), bits[warmup:warmup + steps]))
+    g.close()
+    del g
+    torch.cuda.synchronize()
+    per = {k: v["ms"] / max(1, v["launches"]) for k, v in kt.items()}
+    ev = c1["ev_rec"] - c0["ev_rec"]
+    return {"k_local": k_local, "k_remote": int(net.row_ptr[1] - net.row_ptr[0]) - k_local, "n_remote": net.n,
+            "events_per_s": ev / wall, "ms_per_step": 1e3 * wall / steps, "kernels_ms_per_step": per,
+            "raster_identical_to_unsplit": same}
 
 
 def rate_error(r, ref):
@@ -331,9 +378,11 @@ def main():
     shape = autotune.lookup(net.n, net.nnz, 1, args.wtype, net.max_delay)
     log(f"[bench] gather shape (bundle_syn, unroll): {shape} (0 = library default)")
     res = {}
+    want_split = not args.no_forms and args.wtype == "f32"
     for r in rates:
-        res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype, shape)
-        log(f"[bench] {r} Hz: {json.dumps({k: v for k, v in res[r].items() if k not in ('kernels', 'region_rates')})}")
+        res[r] = run_rate(net, r, netgen.PARTITION_LAMBDA[r], args.steps, args.warmup, args.wtype, shape,
+                          keep_bits=want_split and r == rates[0])
+        log(f"[bench] {r} Hz: {json.dumps({k: v for k, v in res[r].items() if k not in ('kernels', 'region_rates', 'bits')})}")
         log(f"[bench] {r} Hz kernels: {res[r]['kernels']}")
     head = res[rates[0]]
     n_neu, n_syn, n_del = net.n, net.nnz, net.max_delay
@@ -368,6 +417,13 @@ def main():
                                   "mean_rate_hz": ou["mean_rate_hz"],
                                   "sums_ms": ou["kernels"]["sums"]["ms"] / max(1, ou["kernels"]["sums"]["launches"])}
         log(f"[bench] ou background: {json.dumps(forms['ou_background'])}")
+        bits = head.pop("bits")
+        net.bg_lambda = netgen.PARTITION_LAMBDA[r0]
+        sp = run_split(net, bits, args.steps, args.warmup)
+        del bits
+        sp["speed_vs_unsplit"] = sp["events_per_s"] / head["events_per_s"]
+        forms["j_inter_split"] = sp
+        log(f"[bench] j_inter split: {json.dumps(sp)}")
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (FP64 reference, bounded sample)")
@@ -387,7 +443,7 @@ def main():
                                   f"in-degree 100, delays 1-{n_del}, dt 1 ms, {rates[0]} Hz",
                       "global_batch": 1, "seq_len": args.steps, "parallelism": "single-gpu"},
            "rtf": head["rtf"], "roofline": roof, "cpu_baseline": cpu, "gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None},
-           "rates": {str(r): {k: v for k, v in res[r].items() if k not in ("kernels", "region_rates")}
+           "rates": {str(r): {k: v for k, v in res[r].items() if k not in ("kernels", "region_rates", "bits")}
                      for r in rates},
            "forms": forms or None,
            "kernels_ms_per_step": {k: v["ms"] / max(1, v["launches"]) for k, v in head["kernels"].items()}}

@@ -207,6 +207,29 @@ def make_remote_block(n: int, n_remote: int, k_remote, max_delay: int = 5, w_mu:
     return RemoteBlock(n_remote=int(n_remote), row_ptr=row_ptr, col=col, w=w, delay=delay, is_inh=is_inh)
 
 
+def split_remote(net: Network, k_local: int):
+    """Cut every row of a fixed in-degree network after its first k_local
+    in-edges: the network keeps those (the generator puts the own-region
+    sources first), the rest become a remote block whose sources are the
+    same neuron ids held by a mirror partition.  Replaying the network's
+    own raster as the remote spikes then reproduces the unsplit run."""
+    n = net.n
+    K = int(net.row_ptr[1] - net.row_ptr[0]) if n else 0
+    if not np.array_equal(net.row_ptr, np.arange(n + 1, dtype=np.int64) * K) or not 0 <= k_local <= K:
+        raise ValueError("split_remote needs a fixed in-degree >= k_local")
+    kr = K - k_local
+
+    def cut(a, lo, hi):
+        return np.ascontiguousarray(a.reshape(n, K)[:, lo:hi]).reshape(-1)
+
+    local = dataclasses.replace(net, row_ptr=np.arange(n + 1, dtype=np.int64) * k_local,
+                                col=cut(net.col, 0, k_local), w=cut(net.w, 0, k_local),
+                                delay=cut(net.delay, 0, k_local))
+    blk = RemoteBlock(n_remote=n, row_ptr=np.arange(n + 1, dtype=np.int64) * kr, col=cut(net.col, k_local, K),
+                      w=cut(net.w, k_local, K), delay=cut(net.delay, k_local, K), is_inh=net.is_inh.copy())
+    return local, blk
+
+
 def remote_raster(n_steps: int, n_remote: int, rate_hz: float, dt_ms: float = 1.0, seed: int = 12) -> np.ndarray:
     """Replayed remote spikes: independent Bernoulli(rate dt) per neuron-step,
     uint8 [n_steps, n_remote]."""
