@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 5
+#define DTB_ABI_VERSION 6
 
 typedef enum {
   DTB_OK = 0,
@@ -316,6 +316,32 @@ void dtb_mlp_destroy(dtb_mlp* mlp);
  * last), 1 <= k <= n <= 4096, in ascending order of score. */
 dtb_status dtb_topk(const float* score, int32_t n, int32_t k, int32_t* idx, void* hip_stream,
                     int on_device);
+
+/* ------------------------------------------------- assimilation */
+
+/* One analysis step of an ensemble Kalman filter over hyper-parameters: the
+ * iteration of Sec. V-E that adapts the per-population hyper-parameters of
+ * an ensemble of simulated brain models by tracking BOLD signals (the
+ * paper defers the filter itself to its companion work; this stochastic
+ * EnKF with perturbed observations stands in for it).  Device arrays:
+ * X float32 [n_members][n_params] (in/out; e.g. the gains of a batched
+ * handle, [member][population][channel]), Y float32 [n_members][n_obs] (each
+ * member's predicted observation, e.g. dtb_read_bold of the batch),
+ * y_obs float32 [n_obs].  Host array r_var float32 [n_obs]: observation-error
+ * variances, finite and > 0.  With anomalies A = inflation (X - mean X) and
+ * B = Y - mean Y, C_xy = A^T B / (M-1), C_yy = B^T B / (M-1):
+ *   X_m <- mean X + A_m + C_xy (C_yy + R)^-1 (y_obs + sqrt(r) xi_m - Y_m),
+ * clamped to [lo, hi], xi_m,o ~ N(0, 1) by Box-Muller on Philox4x64-10, key
+ * (seed, 0), counter (iter, m, o, 2) (u1 = (hi32(word 0) + 1) / 2^32,
+ * u2 = hi32(word 1) / 2^32).  FP64 inside, one workgroup, asynchronous on
+ * hip_stream.  A parameter with no spread across members is left exactly
+ * as it is; parameters equal in every member stay equal.  Sizes:
+ * n_members >= 2, n_params >= 1, 1 <= n_obs <= 64 and
+ * 8 (P + O + O^2 + P O + M O) <= 160 KB (DTB_ERR_UNSUPPORTED otherwise);
+ * inflation >= 1 and lo <= hi, all finite (DTB_ERR_INVALID otherwise). */
+dtb_status dtb_enkf_analysis(int32_t n_members, int32_t n_params, int32_t n_obs, float* X, const float* Y,
+                             const float* y_obs, const float* r_var, float inflation, uint64_t seed, int64_t iter,
+                             float lo, float hi, void* hip_stream);
 
 /* Wait for the handle's stream; report asynchronous failures (DTB_ERR_NUMERIC
  * when a non-finite V or gate was produced since the last check). */

@@ -16,6 +16,8 @@ Contents
 * ``bold.py``: Balloon-Windkessel hemodynamics (the BOLD model the paper's
   assimilation uses, Sec. V-E) in FP64.
 * ``mlp.py``: FP64 forward/backward of the surrogate MLP.
+* ``enkf.py``: the ensemble Kalman analysis of the hyper-parameter
+  assimilation in FP64.
 
 Parity status of each function is listed in its docstring ("pinned by ...").
 """
@@ -89,6 +91,8 @@ def _load():
         lib.ora_poisson_K.restype = ctypes.c_int
         lib.ora_decay.argtypes = [P, ctypes.c_int]
         lib.ora_decay.restype = ctypes.c_double
+        lib.ora_normals.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_int64, P]
         lib.ora_max_threads.restype = ctypes.c_int
         lib.ora_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
@@ -127,6 +131,13 @@ def ou_normal(seed: int, t: int, i: int, member: int = 0) -> float:
     """The standard normal draw of the OU background for (t, i, member):
     Box-Muller on Philox4x64-10 counter (t, i, member, 1)."""
     return float(_load().ora_ou_normal(seed, t, i, member))
+
+
+def normals(seed: int, c0: int, n1: int, n2: int, c3: int) -> np.ndarray:
+    """[n1, n2] standard normals, Box-Muller on Philox counter (c0, i, j, c3)."""
+    out = np.zeros((n1, n2), dtype=np.float64)
+    _load().ora_normals(seed, c0, n1, n2, c3, _p(out))
+    return out
 
 
 def max_threads() -> int:

@@ -122,6 +122,21 @@ double ora_ou_normal(uint64_t seed, int64_t t, int64_t i, int64_t member) {
   return sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
 }
 
+/* standard normals out[i][j] = Box-Muller on Philox counter (c0, i, j, c3),
+   i < n1, j < n2 (the perturbed observations of the EnKF use c3 = 2) */
+void ora_normals(uint64_t seed, int64_t c0, int64_t n1, int64_t n2, int64_t c3, double* out) {
+  uint64_t key[2] = {seed, 0};
+  for (int64_t i = 0; i < n1; i++)
+    for (int64_t j = 0; j < n2; j++) {
+      uint64_t ctr[4] = {(uint64_t)c0, (uint64_t)i, (uint64_t)j, (uint64_t)c3};
+      uint64_t w[4];
+      ora_philox4x64_10(ctr, key, w);
+      const double u1 = ((double)(w[0] >> 32) + 1.0) * 0x1p-32;
+      const double u2 = (double)(w[1] >> 32) * 0x1p-32;
+      out[i * n2 + j] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
+    }
+}
+
 /* ------------------------------------------------------------- network */
 
 typedef struct {

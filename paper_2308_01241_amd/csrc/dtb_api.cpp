@@ -1044,6 +1044,27 @@ dtb_status dtb_push_remote_spikes(dtb_net* net, const uint32_t* bits, int32_t n_
   return DTB_OK;
 }
 
+dtb_status dtb_enkf_analysis(int32_t n_members, int32_t n_params, int32_t n_obs, float* X, const float* Y,
+                             const float* y_obs, const float* r_var, float inflation, uint64_t seed, int64_t iter,
+                             float lo, float hi, void* hip_stream) {
+  if (!X || !Y || !y_obs || !r_var) return fail(DTB_ERR_INVALID, "null EnKF array");
+  if (n_members < 2 || n_params < 1 || n_obs < 1 || n_obs > kEnkfMaxObs)
+    return fail(DTB_ERR_INVALID, "EnKF needs n_members >= 2, n_params >= 1, 1 <= n_obs <= 64");
+  if (!(inflation >= 1.f) || !finite_f(inflation) || !(lo <= hi) || !finite_f(lo) || !finite_f(hi))
+    return fail(DTB_ERR_INVALID, "EnKF needs a finite inflation >= 1 and finite lo <= hi");
+  EnkfVar rv{};
+  for (int o = 0; o < n_obs; ++o) {
+    if (!(r_var[o] > 0.f) || !finite_f(r_var[o])) return fail(DTB_ERR_INVALID, "r_var must be finite and > 0");
+    rv.r[o] = r_var[o];
+  }
+  if (enkf_lds_bytes(n_members, n_params, n_obs) > size_t(160) * 1024)
+    return fail(DTB_ERR_UNSUPPORTED, "EnKF sizes exceed the 160 KB of LDS (8 (P + O + O^2 + P O + M O) bytes)");
+  hipError_t e = launch_enkf(n_members, n_params, n_obs, X, Y, y_obs, rv, double(inflation), seed, iter, lo, hi,
+                             static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(DTB_ERR_HIP, std::string("EnKF launch: ") + hipGetErrorString(e));
+  return DTB_OK;
+}
+
 static dtb_status window(dtb_net* net, int64_t t0, int64_t t1) {
   if (t0 < 0 || t1 < t0 || t1 > net->t || t0 < net->t - net->d.rec)
     return fail(DTB_ERR_INVALID, "window [" + std::to_string(t0) + ", " + std::to_string(t1) +

@@ -170,6 +170,14 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
 hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
 hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
                          hipStream_t s);
+// observation-error variances of one EnKF analysis, passed by value
+constexpr int kEnkfMaxObs = 64;
+struct EnkfVar {
+  float r[kEnkfMaxObs];
+};
+size_t enkf_lds_bytes(int M, int P, int O);
+hipError_t launch_enkf(int M, int P, int O, float* X, const float* Y, const float* yobs, const EnkfVar& rvar,
+                       double infl, uint64_t seed, int64_t iter, float lo, float hi, hipStream_t s);
 hipError_t launch_copy_words(uint32_t* dst, const uint32_t* src, int64_t n, hipStream_t s);
 hipError_t launch_finalize(const DeviceNet& d, hipStream_t s);
 hipError_t launch_fill(float* dst, int64_t n, float v, hipStream_t s);

@@ -784,4 +784,122 @@ hipError_t launch_finalize(const DeviceNet& d, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------- EnKF
+// Analysis step of an ensemble Kalman filter over the per-population
+// hyper-parameters (the assimilation of Sec. V-E that adapts the
+// hyper-parameters by tracking BOLD signals; the filter itself is a stand-in
+// for the method the paper defers to its companion work).  One workgroup,
+// FP64 throughout: the matrices are tiny and the ensemble is read from L2.
+// LDS: xbar [P], ybar [O], C [O][O] (C_yy + R, then its Cholesky factor),
+// K [P][O] (C_xy), Z [M][O] (innovations, then (C_yy + R)^-1 d).
+namespace {
+__device__ inline double bm_normal(uint64_t seed, uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3) {
+  uint64_t w1 = 0;
+  const uint32_t h0 = uint32_t(philox_hi32_word0(c0, c1, c2, c3, seed, 0ull, &w1));
+  const double u1 = (double(h0) + 1.0) * 2.3283064365386962890625e-10;        // (0, 1]
+  const double u2 = double(uint32_t(w1 >> 32)) * 2.3283064365386962890625e-10;  // [0, 1)
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2);
+}
+
+__global__ __launch_bounds__(256) void k_enkf(int M, int P, int O, float* __restrict__ X,
+                                              const float* __restrict__ Y, const float* __restrict__ yobs,
+                                              EnkfVar rvar, double infl, uint64_t seed, int64_t iter, float lo,
+                                              float hi) {
+  extern __shared__ double sm[];
+  double* xbar = sm;
+  double* ybar = xbar + P;
+  double* C = ybar + O;
+  double* K = C + O * O;
+  double* Z = K + P * O;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double inv = 1.0 / double(M - 1);
+  for (int p = tid; p < P; p += nt) {
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) s += double(X[int64_t(m) * P + p]);
+    xbar[p] = s / double(M);
+  }
+  for (int o = tid; o < O; o += nt) {
+    double s = 0.0;
+    for (int m = 0; m < M; ++m) s += double(Y[int64_t(m) * O + o]);
+    ybar[o] = s / double(M);
+  }
+  __syncthreads();
+  // ensemble covariances (divisor M - 1); the parameter anomalies inflated
+  for (int q = tid; q < O * O; q += nt) {
+    const int a = q / O, b = q % O;
+    double s = 0.0;
+    for (int m = 0; m < M; ++m)
+      s += (double(Y[int64_t(m) * O + a]) - ybar[a]) * (double(Y[int64_t(m) * O + b]) - ybar[b]);
+    C[q] = s * inv + (a == b ? double(rvar.r[a]) : 0.0);
+  }
+  for (int q = tid; q < P * O; q += nt) {
+    const int p = q / O, o = q % O;
+    double s = 0.0;
+    for (int m = 0; m < M; ++m)
+      s += infl * (double(X[int64_t(m) * P + p]) - xbar[p]) * (double(Y[int64_t(m) * O + o]) - ybar[o]);
+    K[q] = s * inv;
+  }
+  // innovations against perturbed observations y + sqrt(r) xi,
+  // xi ~ N(0, 1) on Philox counter (iter, m, o, 2)
+  for (int q = tid; q < M * O; q += nt) {
+    const int m = q / O, o = q % O;
+    const double xi = bm_normal(seed, uint64_t(iter), uint64_t(m), uint64_t(o), 2ull);
+    Z[q] = double(yobs[o]) + sqrt(double(rvar.r[o])) * xi - double(Y[q]);
+  }
+  __syncthreads();
+  // Cholesky factor of C_yy + R, lower triangle in place, column by column
+  for (int k = 0; k < O; ++k) {
+    if (tid == 0) {
+      double d = C[k * O + k];
+      for (int j = 0; j < k; ++j) d -= C[k * O + j] * C[k * O + j];
+      C[k * O + k] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < O; i += nt) {
+      double s = C[i * O + k];
+      for (int j = 0; j < k; ++j) s -= C[i * O + j] * C[k * O + j];
+      C[i * O + k] = s / C[k * O + k];
+    }
+    __syncthreads();
+  }
+  // each member's z = (L L^T)^-1 d: forward, then backward substitution
+  for (int m = tid; m < M; m += nt) {
+    double* z = Z + int64_t(m) * O;
+    for (int i = 0; i < O; ++i) {
+      double s = z[i];
+      for (int j = 0; j < i; ++j) s -= C[i * O + j] * z[j];
+      z[i] = s / C[i * O + i];
+    }
+    for (int i = O - 1; i >= 0; --i) {
+      double s = z[i];
+      for (int j = i + 1; j < O; ++j) s -= C[j * O + i] * z[j];
+      z[i] = s / C[i * O + i];
+    }
+  }
+  __syncthreads();
+  // x_m <- xbar + infl (x_m - xbar) + C_xy z_m, clamped to [lo, hi]
+  for (int q = tid; q < M * P; q += nt) {
+    const int m = q / P, p = q % P;
+    double u = 0.0;
+    for (int o = 0; o < O; ++o) u += K[p * O + o] * Z[int64_t(m) * O + o];
+    const double x = xbar[p] + infl * (double(X[q]) - xbar[p]) + u;
+    X[q] = float(fmin(fmax(x, double(lo)), double(hi)));
+  }
+}
+}  // namespace
+
+size_t enkf_lds_bytes(int M, int P, int O) {
+  return size_t(8) * (size_t(P) + size_t(O) + size_t(O) * O + size_t(P) * O + size_t(M) * O);
+}
+
+hipError_t launch_enkf(int M, int P, int O, float* X, const float* Y, const float* yobs, const EnkfVar& rvar,
+                       double infl, uint64_t seed, int64_t iter, float lo, float hi, hipStream_t s) {
+  const size_t lds = enkf_lds_bytes(M, P, O);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_enkf),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_enkf, dim3(1), dim3(256), lds, s, M, P, O, X, Y, yobs, rvar, infl, seed, iter, lo, hi);
+  return hipGetLastError();
+}
+
 }  // namespace dtb

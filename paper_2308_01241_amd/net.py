@@ -22,6 +22,30 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _check_device(tensor, n: int) -> None:
+    import torch
+    if not (tensor.is_cuda and tensor.dtype == torch.float32 and tensor.is_contiguous() and tensor.numel() >= n):
+        raise ValueError(f"need a contiguous float32 device tensor of at least {n} elements")
+
+
+def enkf_analysis(X, Y, y_obs, r_var, inflation: float = 1.0, seed: int = 0, it: int = 0,
+                  lo: float = -3.0e38, hi: float = 3.0e38, stream=None) -> None:
+    """One ensemble Kalman analysis on the GPU, in place on X.  X [M, P],
+    Y [M, O], y_obs [O]: contiguous float32 device tensors; r_var: host
+    observation-error variances [O]."""
+    M, P = X.shape
+    O = Y.shape[1]
+    _check_device(X, M * P)
+    _check_device(Y, M * O)
+    _check_device(y_obs, O)
+    if Y.shape[0] != M:
+        raise ValueError("X and Y need one row per member")
+    r = np.ascontiguousarray(r_var, dtype=np.float32).reshape(O)
+    check(load().dtb_enkf_analysis(M, P, O, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                   ctypes.c_void_p(y_obs.data_ptr()), _ptr(r), float(inflation), int(seed),
+                                   int(it), float(lo), float(hi), _stream_handle(stream)))
+
+
 class Net:
     """One partition on the GPU.
 
@@ -92,6 +116,16 @@ class Net:
     def set_gains(self, gains) -> None:
         g = np.ascontiguousarray(gains, dtype=np.float32).reshape(self.n_regions, 4)
         check(self._lib.dtb_set_gains(self._h, _ptr(g), 0))
+
+    def set_gains_from(self, tensor) -> None:
+        """Gains from a device tensor (float32 [n_regions, 4], contiguous)."""
+        _check_device(tensor, self.n_regions * 4)
+        check(self._lib.dtb_set_gains(self._h, ctypes.c_void_p(tensor.data_ptr()), 1))
+
+    def bold_into(self, tensor) -> None:
+        """BOLD of every population into a device tensor (float32 [n_regions])."""
+        _check_device(tensor, self.n_regions)
+        check(self._lib.dtb_read_bold(self._h, ctypes.c_void_p(tensor.data_ptr()), None, 1))
 
     def bold(self, state: bool = False):
         y = np.zeros(self.n_regions, dtype=np.float32)

@@ -1,0 +1,108 @@
+"""GPU parity of the EnKF analysis kernel (hyper-parameter assimilation of
+Sec. V-E) against the FP64 reference on the same inputs and Philox draws,
+and the assimilation loop on a small twin.
+
+Bar: the kernel computes in FP64 and stores float32, so each updated
+parameter must equal the reference rounded to float32 within 2 ulps (plus
+1e-12 of the largest value, for FP64 summation-order differences of
+results near zero);
+parameters without spread and tied parameters are compared exactly."""
+import numpy as np
+import pytest
+
+from oracle import enkf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dtb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2308_01241_amd as m
+    m.load()
+    return m
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("M,P,O", [(64, 80, 20), (2, 1, 1), (3, 7, 5), (128, 256, 32), (1024, 16, 8), (200, 3, 64)])
+def test_enkf_kernel_matches_reference(dtb, M, P, O):
+    import torch
+    rng = np.random.default_rng(M * 1000 + P * 10 + O)
+    X = (1.0 + 0.2 * rng.standard_normal((M, P))).astype(np.float32)
+    Wt = rng.standard_normal((P, O)) / np.sqrt(P)
+    Y = (X.astype(np.float64) @ Wt + 0.05 * rng.standard_normal((M, O))).astype(np.float32)
+    y = (1.0 + rng.standard_normal(O)).astype(np.float32)
+    r = (0.01 + 0.05 * rng.random(O)).astype(np.float32)
+    print(f"enkf parity M={M} P={P} O={O}", flush=True)
+    Xd, Yd, yd = _dev(X), _dev(Y), _dev(y)
+    dtb.enkf_analysis(Xd, Yd, yd, r, inflation=1.02, seed=9, it=4, lo=-10.0, hi=10.0,
+                      stream=torch.cuda.current_stream())
+    got = Xd.cpu().numpy()
+    ref = enkf.analysis(X, Y, y, r, inflation=np.float32(1.02), seed=9, it=4, lo=-10.0, hi=10.0)
+    ref32 = ref.astype(np.float32)
+    tol = 2 * np.spacing(np.abs(ref32)) + 1e-12 * (1.0 + np.abs(ref).max())   # FP64 order differences near 0
+    assert np.all(np.abs(got - ref32) <= tol), float(np.max(np.abs(got - ref32) / tol))
+    assert np.abs(got - X).max() > 1e-3          # the analysis moved the ensemble
+
+
+def test_enkf_kernel_fixed_tied_and_clamped(dtb):
+    import torch
+    rng = np.random.default_rng(3)
+    M, R = 48, 10
+    g = (1.0 + 0.2 * rng.standard_normal((M, R))).astype(np.float32)
+    X = np.ones((M, R, 4), np.float32)
+    X[..., 0] = g
+    X[..., 1] = g
+    X[..., 3] = 0.85
+    Y = (2.0 * g + 0.1 * rng.standard_normal((M, R))).astype(np.float32)
+    Xd = _dev(X.reshape(M, 4 * R))
+    dtb.enkf_analysis(Xd, _dev(Y), _dev(np.full(R, 2.3)), np.full(R, 0.02, np.float32), inflation=1.05,
+                      seed=1, it=0, lo=0.8, hi=1.3, stream=torch.cuda.current_stream())
+    out = Xd.cpu().numpy().reshape(M, R, 4)
+    np.testing.assert_array_equal(out[..., 0], out[..., 1])
+    np.testing.assert_array_equal(out[..., 2], 1.0)
+    np.testing.assert_array_equal(out[..., 3], np.float32(0.85))
+    assert out[..., 0].min() >= 0.8 and out[..., 0].max() <= 1.3
+    ref = enkf.analysis(X.reshape(M, 4 * R), Y, np.full(R, 2.3), np.full(R, 0.02), inflation=np.float32(1.05),
+                        seed=1, it=0, lo=0.8, hi=1.3).astype(np.float32)
+    assert np.all(np.abs(out.reshape(M, -1) - ref) <= 2 * np.spacing(np.abs(ref)))
+
+
+def test_enkf_errors(dtb):
+    import torch
+    X, Y, y = _dev(np.ones((4, 3))), _dev(np.ones((4, 65))), _dev(np.ones(65))
+    with pytest.raises(dtb.DtbError):
+        dtb.enkf_analysis(X, Y, y, np.ones(65, np.float32))               # more than 64 observations
+    Y2, y2 = _dev(np.ones((4, 2))), _dev(np.ones(2))
+    with pytest.raises(dtb.DtbError):
+        dtb.enkf_analysis(X, Y2, y2, np.array([1.0, 0.0], np.float32))    # r must be > 0
+    with pytest.raises(dtb.DtbError):
+        dtb.enkf_analysis(X, Y2, y2, np.ones(2, np.float32), inflation=0.9)
+    with pytest.raises(dtb.DtbError):
+        dtb.enkf_analysis(_dev(np.ones((1, 3))), _dev(np.ones((1, 2))), y2, np.ones(2, np.float32))
+    big = _dev(np.ones((4096, 8)))
+    with pytest.raises(dtb.DtbError):
+        dtb.enkf_analysis(big, _dev(np.ones((4096, 64))), _dev(np.ones(64)), np.ones(64, np.float32))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(300)
+def test_assimilation_loop_recovers_hidden_gains_on_a_small_twin(dtb):
+    """32 samples of a 20,000-neuron, 8-population model track the BOLD of a
+    twin with hidden excitatory gains for 12 windows of 400 steps: the
+    estimated gains are closer to the hidden ones than the prior mean, and
+    re-simulated at the estimate the BOLD fits the twin's better than at the
+    prior mean."""
+    from paper_2308_01241_amd import hmda
+    S = hmda.HmdaSetup(members=32, n=20_000, regions=8, windows=12, window=400)
+    print("hmda small twin", flush=True)
+    rep = hmda.run(S)
+    assert rep["final_gain_rmse"] < 0.7 * rep["prior_gain_rmse"], rep
+    fit = rep["bold_fit_rmse"]
+    assert fit["estimated"] < fit["prior_mean"], fit
+    assert rep["analysis_ms_per_window"] < 5.0
