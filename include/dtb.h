@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 6
+#define DTB_ABI_VERSION 7
 
 typedef enum {
   DTB_OK = 0,
@@ -342,6 +342,33 @@ dtb_status dtb_topk(const float* score, int32_t n, int32_t k, int32_t* idx, void
 dtb_status dtb_enkf_analysis(int32_t n_members, int32_t n_params, int32_t n_obs, float* X, const float* Y,
                              const float* y_obs, const float* r_var, float inflation, uint64_t seed, int64_t iter,
                              float lo, float hi, void* hip_stream);
+
+/* ------------------------------------------------- partitioning */
+
+/* Neuron-to-GPU partition minimising the heaviest inter-GPU traffic
+ * (Sec. V-C, Eq. (2): F(P) = max_j sum_{i != j} D_ij) subject to a disjoint
+ * cover and a per-GPU capacity on the summed vertex sizes (the constraint
+ * after Eq. (2)).  Host only; needs no GPU.  Vertices are groups of neurons
+ * (a population or a piece of one): size double [n_vert] (>= 0, e.g.
+ * bytes), neurons double [n_vert] (> 0), spikes double [n_vert] (spikes per
+ * step, >= 0); synapses between vertices as a CSR by source: e_ptr int64
+ * [n_vert+1], e_dst int32 [ne], e_syn double [ne] (synapse counts, >= 0).
+ * Traffic: a spike of a neuron of u on GPU i goes to GPU j != i once if the
+ * neuron has a target there, probability 1 - exp(-c_uj / n_u) with c_uj
+ * the synapses from u onto j's vertices, so
+ * D_ij = bytes_per_spike sum_{u on i} s_u (1 - exp(-c_uj / n_u)).
+ * Start: init int32 [n_vert] if given, else the greedy fill (one GPU at a
+ * time, the unassigned vertex most connected to it, up to an even share of
+ * the total size); then up to refine_rounds single-vertex moves into or out
+ * of the most loaded GPU, each lowering F (refine_rounds = 0 evaluates the
+ * start).  Outputs: part int32 [n_vert], *F_out, D_out double
+ * [n_gpu][n_gpu] (diagonal 0; either may be NULL).  Errors: DTB_ERR_INVALID
+ * (bad arrays, an init beyond the capacity), DTB_ERR_UNSUPPORTED (a vertex
+ * or the total beyond the capacity, n_vert n_gpu > 2^28). */
+dtb_status dtb_partition(int64_t n_vert, const double* size, const double* neurons, const double* spikes,
+                         const int64_t* e_ptr, const int32_t* e_dst, const double* e_syn, int32_t n_gpu,
+                         double capacity, double bytes_per_spike, const int32_t* init, int32_t refine_rounds,
+                         int32_t* part, double* F_out, double* D_out);
 
 /* Wait for the handle's stream; report asynchronous failures (DTB_ERR_NUMERIC
  * when a non-finite V or gate was produced since the last check). */

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdtb.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dtb_api.cpp", "dtb_kernels.hip", "dtb_mlp.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dtb_api.cpp", "dtb_kernels.hip", "dtb_mlp.hip", "dtb_partition.cpp")]
 ARCH = os.environ.get("DTB_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: every fused multiply-add in the kernels is explicit.
