@@ -125,12 +125,11 @@ struct dtb_net {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kTimedKernels];
   size_t ev_used[kTimedKernels] = {};
-  // second stream of dtb_step: the compaction, and with a remote in-edge
-  // block (J_inter) also its delivery tests, forked from and joined back
-  // into the handle's stream every step
+  // remote in-edge block (J_inter): its delivery tests run on a second
+  // stream, forked from and joined back into the handle's stream every step
   bool remote = false;
   hipStream_t comm = nullptr;
-  hipEvent_t fork_ev = nullptr, upd_ev = nullptr, join_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int64_t rq_head = 0;     // queue row of the first pending remote step
   int64_t rq_pending = 0;  // remote steps pushed and not yet consumed
 };
@@ -494,7 +493,6 @@ void dtb_destroy(dtb_net* net) {
     (void)hipStreamDestroy(net->comm);
   }
   if (net->fork_ev) (void)hipEventDestroy(net->fork_ev);
-  if (net->upd_ev) (void)hipEventDestroy(net->upd_ev);
   if (net->join_ev) (void)hipEventDestroy(net->join_ev);
   for (auto& pool : net->ev_pool)
     for (auto& pr : pool) {
@@ -533,7 +531,6 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
   {
     hipError_t e = hipStreamCreate(&net->comm);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&net->fork_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&net->upd_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&net->join_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
       dtb_destroy(net);
@@ -842,20 +839,19 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
         e = launch_copy_words(d.rraster + (t % d.slots) * d.rwords_pad, row, d.rwords_pad, net->comm);
       if (e == hipSuccess)
         e = timed(net, 5, [&] { return launch_gather(d, d.rem, d.rraster, d.rwords_pad, net->comm); }, net->comm);
+      if (e == hipSuccess) e = hipEventRecord(net->join_ev, net->comm);
       if (e != hipSuccess) return hip_fail(net, e, "remote block launch");
       net->rq_head++;
       net->rq_pending--;
     }
+    // (the compaction stays on the handle's stream: beside the delivery
+    // tests its look-back blocks delay their one-workgroup-per-CU dispatch,
+    // measured slower)
     if (e == hipSuccess) e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
-    // the compaction only reads this step's bitmap: it runs on the second
-    // stream beside the delivery tests and is joined before the sums
-    if (e == hipSuccess) e = hipEventRecord(net->upd_ev, net->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(net->comm, net->upd_ev, 0);
-    if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->comm); }, net->comm);
-    if (e == hipSuccess) e = hipEventRecord(net->join_ev, net->comm);
+    if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
     if (e == hipSuccess)
       e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, net->stream); });
-    if (e == hipSuccess) e = hipStreamWaitEvent(net->stream, net->join_ev, 0);
+    if (e == hipSuccess && net->remote) e = hipStreamWaitEvent(net->stream, net->join_ev, 0);
     if (e == hipSuccess) e = timed(net, 3, [&] { return launch_sums(d, net->stream); });
     if (e == hipSuccess) e = timed(net, 4, [&] { return launch_finalize(d, net->stream); });
     if (e != hipSuccess) return hip_fail(net, e, "kernel launch");

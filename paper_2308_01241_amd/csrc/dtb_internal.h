@@ -53,6 +53,13 @@ constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap w
 #ifndef DTB_GATHER_THREADS
 #define DTB_GATHER_THREADS 1024
 #endif
+// neurons per thread of the neuron update (1, 2 or 4)
+#ifndef DTB_UPDATE_NPT
+#define DTB_UPDATE_NPT 2
+#endif
+constexpr int kUpdateNpt = DTB_UPDATE_NPT;
+static_assert(kUpdateNpt == 1 || kUpdateNpt == 2 || kUpdateNpt == 4, "neurons per thread: 1, 2 or 4");
+
 #ifndef DTB_GATHER_UNROLL
 #define DTB_GATHER_UNROLL 3
 #endif

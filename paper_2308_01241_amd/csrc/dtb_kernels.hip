@@ -62,79 +62,111 @@ __device__ inline int poisson_count(uint32_t u, const uint32_t* __restrict__ T, 
 }
 
 // ----------------------------------------------------------- neuron update
-// One thread per neuron, 1024 threads (16 wavefronts) per block.
-__global__ __launch_bounds__(1024) void k_neuron_update(
+// 1024 neurons per block, kNpt per thread: thread x of the block takes
+// neurons x, x + 1024/kNpt, ...; all their loads are issued before any
+// arithmetic, so each wavefront keeps kNpt neurons' worth of loads in
+// flight.  A wavefront's 64 consecutive neurons of one part form two words
+// of the step's spike bitmap (one ballot).
+template <int kNpt>
+__global__ __launch_bounds__(1024 / kNpt) void k_neuron_update(
     int64_t n, int64_t n_pad, const int64_t* __restrict__ step, float* __restrict__ V, const float* __restrict__ j,
     uint8_t* __restrict__ ref, const uint16_t* __restrict__ ptype, const int32_t* __restrict__ region,
     const PType* __restrict__ ptab, const float* __restrict__ gain, const float* __restrict__ ou,
     float E0, float E1, float E2, float E3, const uint32_t* __restrict__ forced,
     uint32_t* __restrict__ raster, int64_t words_pad, int32_t* __restrict__ counts, int32_t n_regions,
     uint32_t* __restrict__ cticket, int32_t* __restrict__ bad) {
-  __shared__ int s_reg[16];
+  constexpr int kT = 1024 / kNpt;       // threads per block
+  constexpr int kW = kT / 64;           // wavefronts per block
+  __shared__ int s_reg[16];             // per 64-neuron run of the block, in neuron order
   __shared__ int s_cnt[16];
   const int64_t slot = step[1];  // step[0] = t, step[1] = t mod ring slots
   uint32_t* __restrict__ raster_slot = raster + slot * words_pad;
   int32_t* __restrict__ counts_slot = counts + slot * n_regions;
-  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  const int64_t base = int64_t(blockIdx.x) * 1024;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool valid = i < n;
-  int s = 0, reg = 0;
-  if (valid) {
-    const float v = V[i];
-    const int r = ref[i];
-    const PType p = ptab[ptype[i]];
-    reg = region[i];
-    const float* gn = gain + 4 * reg;
-    float vt = 0.f;
-    if (r <= 0) {
-      // I = (Iext + I_ou) + sum_u (g_u gain_u) j_u (E_u - V) - gL (V - EL);  V~ = V + dt/C I
-      float I = p.Iext;
-      if (ou) I = I + ou[i];
-      I = __fmaf_rn((p.g[0] * gn[0]) * j[i], E0 - v, I);
-      I = __fmaf_rn((p.g[1] * gn[1]) * j[n_pad + i], E1 - v, I);
-      I = __fmaf_rn((p.g[2] * gn[2]) * j[2 * n_pad + i], E2 - v, I);
-      I = __fmaf_rn((p.g[3] * gn[3]) * j[3 * n_pad + i], E3 - v, I);
-      I = __fmaf_rn(-p.gL, v - p.EL, I);
-      vt = __fmaf_rn(p.dtC, I, v);
+  bool valid[kNpt];
+  float v[kNpt], x0[kNpt], x1[kNpt], x2[kNpt], x3[kNpt], xo[kNpt];
+  int rr[kNpt], pt[kNpt], rg[kNpt];
+#pragma unroll
+  for (int h = 0; h < kNpt; ++h) {
+    const int64_t i = base + h * kT + threadIdx.x;
+    valid[h] = i < n;
+    v[h] = x0[h] = x1[h] = x2[h] = x3[h] = xo[h] = 0.f;
+    rr[h] = pt[h] = rg[h] = 0;
+    if (valid[h]) {
+      v[h] = V[i];
+      rr[h] = ref[i];
+      pt[h] = ptype[i];
+      rg[h] = region[i];
+      x0[h] = j[i];
+      x1[h] = j[n_pad + i];
+      x2[h] = j[2 * n_pad + i];
+      x3[h] = j[3 * n_pad + i];
+      if (ou) xo[h] = ou[i];
     }
-    if (forced) s = (forced[i >> 5] >> (i & 31)) & 1u;
-    else s = (r <= 0 && vt >= p.Vth) ? 1 : 0;
-    float nv;
-    int nr;
-    if (s) {
-      nv = p.Vreset;
-      nr = p.nref;
-    } else if (r > 0) {
-      nv = p.Vreset;
-      nr = r - 1;
+  }
+#pragma unroll
+  for (int h = 0; h < kNpt; ++h) {
+    const int64_t i = base + h * kT + threadIdx.x;
+    int s = 0;
+    if (valid[h]) {
+      const PType p = ptab[pt[h]];
+      const float* gn = gain + 4 * rg[h];
+      const float vv = v[h];
+      const int r = rr[h];
+      float vt = 0.f;
+      if (r <= 0) {
+        // I = (Iext + I_ou) + sum_u (g_u gain_u) j_u (E_u - V) - gL (V - EL);  V~ = V + dt/C I
+        float I = p.Iext;
+        if (ou) I = I + xo[h];
+        I = __fmaf_rn((p.g[0] * gn[0]) * x0[h], E0 - vv, I);
+        I = __fmaf_rn((p.g[1] * gn[1]) * x1[h], E1 - vv, I);
+        I = __fmaf_rn((p.g[2] * gn[2]) * x2[h], E2 - vv, I);
+        I = __fmaf_rn((p.g[3] * gn[3]) * x3[h], E3 - vv, I);
+        I = __fmaf_rn(-p.gL, vv - p.EL, I);
+        vt = __fmaf_rn(p.dtC, I, vv);
+      }
+      if (forced) s = (forced[i >> 5] >> (i & 31)) & 1u;
+      else s = (r <= 0 && vt >= p.Vth) ? 1 : 0;
+      float nv;
+      int nr;
+      if (s) {
+        nv = p.Vreset;
+        nr = p.nref;
+      } else if (r > 0) {
+        nv = p.Vreset;
+        nr = r - 1;
+      } else {
+        nv = vt;
+        nr = 0;
+      }
+      V[i] = nv;
+      ref[i] = (uint8_t)nr;
+      if (!isfinite(nv)) atomicOr(bad, 1);
+    }
+    // the wavefront's 64 spike predicates are 64 consecutive bits of the bitmap
+    const uint64_t m = __ballot(s);
+    const int run = h * kW + wave;  // 64-neuron run of the block
+    const int64_t first = base + int64_t(run) * 64;
+    if (lane == 0) {
+      raster_slot[first >> 5] = uint32_t(m);
+      raster_slot[(first >> 5) + 1] = uint32_t(m >> 32);
+    }
+    // population counts: one entry per run when it lies in one population
+    const int reg = rg[h];
+    const int r0 = __shfl(reg, 0);
+    const int uniform = __all((!valid[h] || reg == r0) ? 1 : 0);
+    if (uniform) {
+      if (lane == 0) {
+        s_reg[run] = r0;
+        s_cnt[run] = __popcll(m);
+      }
     } else {
-      nv = vt;
-      nr = 0;
-    }
-    V[i] = nv;
-    ref[i] = (uint8_t)nr;
-    if (!isfinite(nv)) atomicOr(bad, 1);
-  }
-  // the wavefront's 64 spike predicates are 64 consecutive bits of the bitmap
-  const uint64_t m = __ballot(s);
-  const int64_t wave_first = int64_t(blockIdx.x) * 1024 + wave * 64;
-  if (lane == 0) {
-    raster_slot[wave_first >> 5] = uint32_t(m);
-    raster_slot[(wave_first >> 5) + 1] = uint32_t(m >> 32);
-  }
-  // population counts: one entry per wavefront when it lies in one population
-  const int r0 = __shfl(reg, 0);
-  const int uniform = __all((!valid || reg == r0) ? 1 : 0);
-  if (uniform) {
-    if (lane == 0) {
-      s_reg[wave] = r0;
-      s_cnt[wave] = __popcll(m);
-    }
-  } else {
-    if (s) atomicAdd(&counts_slot[reg], 1);
-    if (lane == 0) {
-      s_reg[wave] = -1;
-      s_cnt[wave] = 0;
+      if (s) atomicAdd(&counts_slot[reg], 1);
+      if (lane == 0) {
+        s_reg[run] = -1;
+        s_cnt[run] = 0;
+      }
     }
   }
   __syncthreads();
@@ -681,7 +713,8 @@ __global__ __launch_bounds__(256) void k_finalize(
 
 hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s) {
   const unsigned grid = unsigned(d.n_pad / 1024);
-  hipLaunchKernelGGL(k_neuron_update, dim3(grid), dim3(1024), 0, s, d.n, d.n_pad, d.step, d.V, d.j, d.ref,
+  hipLaunchKernelGGL(k_neuron_update<kUpdateNpt>, dim3(grid), dim3(1024 / kUpdateNpt), 0, s, d.n, d.n_pad, d.step,
+                     d.V, d.j, d.ref,
                      d.ptype, d.region, d.ptab, d.gain, d.ou_on ? d.ou : nullptr, d.E[0], d.E[1], d.E[2], d.E[3],
                      forced, d.raster,
                      d.words_pad, d.counts, d.n_regions, d.cticket, d.bad);

@@ -205,3 +205,37 @@ def test_split_partition_replaying_its_own_raster_is_bit_identical(dtb):
         np.testing.assert_array_equal(part.state(f), full.state(f))
     assert part.counters() == full.counters()
     assert full.counters()["spikes"] > 0
+
+
+def test_empty_remote_block_and_single_remote_source(dtb):
+    """Degenerate blocks: no remote synapses at all (every row empty) is the
+    run without a block; a single remote source feeding every row matches
+    the reference."""
+    net, _, _ = _case(4)
+    T = 60
+    empty = netgen.RemoteBlock(n_remote=1, row_ptr=np.zeros(net.n + 1, np.int64), col=np.zeros(0, np.int32),
+                               w=np.zeros(0, np.float32), delay=np.zeros(0, np.uint8), is_inh=np.zeros(1, np.uint8))
+    a = _gpu(dtb, net, empty)
+    a.push_remote(np.ones((T, 1), np.uint8))
+    a.step(T)
+    b = _gpu(dtb, net)
+    b.step(T)
+    np.testing.assert_array_equal(a.raster(0, T), b.raster(0, T))
+    np.testing.assert_array_equal(a.state("V"), b.state("V"))
+    assert a.counters() == b.counters()
+    one = netgen.make_remote_block(net.n, 1, 1, max_delay=net.max_delay, seed=3)
+    rem = (np.arange(T) % 7 == 0).astype(np.uint8)[:, None]
+    o = oracle.OracleNet(net)
+    o.set_remote(one)
+    ref = o.run(T, want_margin=True, remote=rem)
+    g = _gpu(dtb, net, one)
+    g.push_remote(rem)
+    g.step(T)
+    ras = g.raster(0, T)
+    diff = np.nonzero((ras != ref["raster"]).any(axis=1))[0]
+    if len(diff):
+        t = int(diff[0])
+        bad = np.nonzero(ras[t] != ref["raster"][t])[0]
+        assert np.all(ref["margins"][t, bad] < DELTA)
+    else:
+        np.testing.assert_array_equal(g.step_events(0, T)[0], ref["ev_rec"])
