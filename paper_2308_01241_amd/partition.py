@@ -96,3 +96,52 @@ def sequential(g: VertexGraph, n_gpu: int) -> np.ndarray:
     into n_gpu contiguous runs of about equal size."""
     c = np.cumsum(g.size) - 0.5 * g.size
     return np.minimum((c / g.size.sum() * n_gpu).astype(np.int32), n_gpu - 1)
+
+
+def main():
+    """Partition the generator's population graph at N x 20M neurons for each
+    N given and compare with the sequential cut; prints one JSON report."""
+    import argparse
+    import json
+    import time
+
+    import netgen
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, nargs="+", default=[8, 64])
+    ap.add_argument("--per-gpu", type=int, default=20_000_000)
+    ap.add_argument("--chunk", type=int, default=1_000_000)
+    ap.add_argument("--rate", type=float, default=7.0)
+    ap.add_argument("--slack", type=float, default=1.1)
+    ap.add_argument("--out", type=str, default="")
+    a = ap.parse_args()
+    rep = []
+    for N in a.gpus:
+        spec = netgen.partition_spec(n=N * a.per_gpu, n_regions=90)
+        g = region_graph(spec.region_sizes, spec.cross_w, spec.k_in, spec.k_cross, rate_hz=a.rate, chunk=a.chunk)
+        cap = g.size.sum() / N * a.slack
+        seq = sequential(g, N)
+        _, F_seq, D_seq = partition(g, N, g.size.sum(), init=seq, refine_rounds=0)
+        t = time.perf_counter()
+        _, F_greedy, _ = partition(g, N, cap, refine_rounds=0)
+        t_greedy = time.perf_counter() - t
+        t = time.perf_counter()
+        part, F, D = partition(g, N, cap)
+        t_all = time.perf_counter() - t
+        load = np.bincount(part, weights=g.size, minlength=N)
+        rep.append({"n_gpu": N, "neurons": int(spec.n), "vertices": int(len(g.size)),
+                    "F_sequential_MB_per_step": F_seq / 1e6, "F_greedy_MB_per_step": F_greedy / 1e6,
+                    "F_MB_per_step": F / 1e6, "F_ratio_vs_sequential": F / F_seq,
+                    "total_traffic_MB_per_step": float(D.sum()) / 1e6,
+                    "total_traffic_sequential_MB_per_step": float(D_seq.sum()) / 1e6,
+                    "load_max_over_mean": float(load.max() / load.mean()),
+                    "seconds_greedy": t_greedy, "seconds_total": t_all})
+    txt = json.dumps({"capacity_slack": a.slack, "chunk": a.chunk, "rate_hz": a.rate, "runs": rep}, indent=1)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+    print(txt)
+
+
+if __name__ == "__main__":
+    main()
