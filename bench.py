@@ -334,7 +334,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's partition; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU exchange is not part of this build)", file=sys.stderr)
+              f"(the cross-GPU spike exchange is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -47,7 +47,7 @@ typedef enum {
   DTB_ERR_HIP = -3,         /* a HIP runtime call failed (handle becomes sticky-failed) */
   DTB_ERR_STATE = -4,       /* call not valid in the handle's current state */
   DTB_ERR_NUMERIC = -5,     /* non-finite membrane potential or gate detected */
-  DTB_ERR_UNSUPPORTED = -6  /* valid request outside what this build implements */
+  DTB_ERR_UNSUPPORTED = -6  /* valid request outside what the library implements */
 } dtb_status;
 
 typedef enum { DTB_W_F32 = 0, DTB_W_BF16 = 1 } dtb_wtype;
@@ -183,10 +183,12 @@ dtb_status dtb_force_spikes(dtb_net* net, const uint32_t* bits, int32_t n_steps)
  * inhibitory, its weight goes to the GABA gates).  Host arrays, copied (the
  * caller keeps ownership).  Each row's input is then the local in-edges in
  * CSR order, then the remote ones in CSR order, then the background; a
- * delivered remote spike counts as a recurrent event.  Every step then runs
- * the remote block's delivery tests on a second stream of the library's,
- * concurrent with the update, compaction and local delivery tests, and joins
- * it before the sums.  Only on a single-member handle before its first step
+ * delivered remote spike counts as a recurrent event.  Every step then
+ * lands the step's remote bitmap in a remote ring on a second stream of the
+ * library's (where an exchange would deliver it), concurrent with the
+ * update, compaction and local delivery tests, and runs the remote block's
+ * delivery tests after the local ones once that has arrived (the paper's
+ * order: J_intra, then J_inter, then the j and I update).  Only on a single-member handle before its first step
  * (or right after dtb_reset); once per handle (DTB_ERR_STATE otherwise);
  * n_remote in [1, 2^26 - 1].  dtb_run is unavailable on such a handle. */
 dtb_status dtb_set_remote_block(dtb_net* net, int64_t n_remote, int64_t nnz, const int64_t* row_ptr,

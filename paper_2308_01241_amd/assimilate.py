@@ -11,8 +11,8 @@ Pipeline, all on the GPU through the C ABI:
   3. screen - against a synthetic twin target (a member network whose gains
               are hidden: one window at unit gains, then one at the hidden
               gains), each iteration scores many Gaussian proposals with the
-              surrogate, re-simulates the best k as one batch (the judge) and
-              k random proposals the same way (the method without the
+              surrogate, re-simulates the best k as one batch (the check)
+              and k random proposals the same way (the method without the
               surrogate), and moves the proposal mean to the best simulated
               one.
 
@@ -64,7 +64,7 @@ def window_rates(net, S: Setup):
 
 
 def generate(net, S: Setup, n_runs: int, rng):
-    """n_runs x members samples, each run the way the judge simulates a
+    """n_runs x members samples, each run the way the re-simulation check runs a
     proposal: from rest, one window at unit gains, then one window at fresh
     gains.  Returns X [samples, 5 R] (gains, rates of the first window) and
     Y [samples, 2 R] (rates of the second window, BOLD at its end)."""
@@ -137,7 +137,7 @@ def _fit(rates, bold, t_rates, t_bold, sr, sb):
     return np.mean(((rates - t_rates) / sr) ** 2, axis=-1) + np.mean(((bold - t_bold) / sb) ** 2, axis=-1)
 
 
-class Judge:
+class Resim:
     """k + 1 copies of the target network in one batch (member ids 0 .. k, so
     each copy draws its own background): copies 0 .. k-1 simulate k gain
     proposals, copy k is the twin (one window at unit gains, then one at
@@ -171,7 +171,7 @@ class Judge:
         self.net.close()
 
 
-def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096, k=64, seed=0, judge=None,
+def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096, k=64, seed=0, resim=None,
            shrink=0.85):
     """Surrogate-screened search for the hidden gains of a twin target:
     Gaussian proposals around the best simulated proposal so far, their
@@ -180,10 +180,10 @@ def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096,
     from . import topk
     rng = np.random.default_rng(seed)
     R = S.regions
-    own = judge is None
-    judge = judge or Judge(target_net, k, S)
-    # the twin: the judge batch's last copy, run at the hidden gains
-    rs, bs, base = judge(np.ones((k, R, 4), dtype=np.float32), twin_gains=hidden_gains)
+    own = resim is None
+    resim = resim or Resim(target_net, k, S)
+    # the twin: the re-simulation batch's last copy, run at the hidden gains
+    rs, bs, base = resim(np.ones((k, R, 4), dtype=np.float32), twin_gains=hidden_gains)
     t_rates, t_bold, prev = rs[k].copy(), bs[k].copy(), base[k].copy()
     sr, sb = sy.sd[:R], sy.sd[R:]
     mu = np.ones((R, 4), dtype=np.float32)
@@ -201,12 +201,12 @@ def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096,
         best = topk(score, k)
         t_screen = time.perf_counter() - tic
         tic = time.perf_counter()
-        rs, bs, _ = judge(props[best])
+        rs, bs, _ = resim(props[best])
         rs, bs = rs[:k], bs[:k]
         t_sim = time.perf_counter() - tic
         fit_s = _fit(rs, bs, t_rates, t_bold, sr, sb)
         rnd = rng.choice(n_prop, k, replace=False)
-        rr, br, _ = judge(props[rnd])
+        rr, br, _ = resim(props[rnd])
         rr, br = rr[:k], br[:k]
         fit_r = _fit(rr, br, t_rates, t_bold, sr, sb)
         pb = P[best][:, R:]
@@ -228,7 +228,7 @@ def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096,
         hist.append(rec)
         log(f"[screen] {json.dumps(rec)}")
     if own:
-        judge.close()
+        resim.close()
     return hist
 
 
@@ -267,12 +267,12 @@ def main(argv=None):
            "generate_s": gen_s, "train_s": train_s, "held_out": err, "screen": {}}
     target = netgen.make_network(netgen.ensemble_member_spec(41, S.target_n, rate_hz=S.rate_hz,
                                                              n_regions=S.regions))
-    judge = Judge(target, 64, S)
+    resim = Resim(target, 64, S)
     for s in [int(x) for x in a.seeds.split(",")]:
         hidden = np.clip(np.random.default_rng(41 + s).normal(1.0, GAIN_SD, (S.regions, 4)), 0,
                          None).astype(np.float32)
-        rep["screen"][str(s)] = screen(m, sx, sy, target, hidden, S, iters=a.iters, seed=s, judge=judge)
-    judge.close()
+        rep["screen"][str(s)] = screen(m, sx, sy, target, hidden, S, iters=a.iters, seed=s, resim=resim)
+    resim.close()
     H = [r for h in rep["screen"].values() for r in h]
     rep["summary"] = {
         "mean_best_fit_surrogate": float(np.mean([r["best_fit_surrogate"] for r in H])),

@@ -829,29 +829,31 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
     }
     hipError_t e = hipSuccess;
     if (net->remote) {
-      // J_inter on the second stream: this step's remote bitmap from the
-      // queue into the remote ring, then the remote block's delivery tests,
-      // concurrent with the update, compaction and J_intra delivery tests
+      // the arrival of this step's remote spikes on the second stream (the
+      // pushed bitmap from the queue into the remote ring: where an exchange
+      // would land them), concurrent with the update, compaction and J_intra
       const uint32_t* row = d.rqueue + (net->rq_head % (d.rec + 1)) * d.rwords_pad;
       e = hipEventRecord(net->fork_ev, net->stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(net->comm, net->fork_ev, 0);
       if (e == hipSuccess)
         e = launch_copy_words(d.rraster + (t % d.slots) * d.rwords_pad, row, d.rwords_pad, net->comm);
-      if (e == hipSuccess)
-        e = timed(net, 5, [&] { return launch_gather(d, d.rem, d.rraster, d.rwords_pad, net->comm); }, net->comm);
       if (e == hipSuccess) e = hipEventRecord(net->join_ev, net->comm);
       if (e != hipSuccess) return hip_fail(net, e, "remote block launch");
       net->rq_head++;
       net->rq_pending--;
     }
-    // (the compaction stays on the handle's stream: beside the delivery
-    // tests its look-back blocks delay their one-workgroup-per-CU dispatch,
-    // measured slower)
     if (e == hipSuccess) e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
     if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
     if (e == hipSuccess)
       e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, net->stream); });
-    if (e == hipSuccess && net->remote) e = hipStreamWaitEvent(net->stream, net->join_ev, 0);
+    if (e == hipSuccess && net->remote) {
+      // J_inter after J_intra, once the remote spikes are in (the paper's
+      // computing-thread order); its delivery tests OR into their own hit
+      // buffer
+      e = hipStreamWaitEvent(net->stream, net->join_ev, 0);
+      if (e == hipSuccess)
+        e = timed(net, 5, [&] { return launch_gather(d, d.rem, d.rraster, d.rwords_pad, net->stream); });
+    }
     if (e == hipSuccess) e = timed(net, 3, [&] { return launch_sums(d, net->stream); });
     if (e == hipSuccess) e = timed(net, 4, [&] { return launch_finalize(d, net->stream); });
     if (e != hipSuccess) return hip_fail(net, e, "kernel launch");

@@ -19,7 +19,7 @@ measured one; the filter itself is in its companion work.  Here:
   one stochastic-EnKF analysis (`dtb_enkf_analysis`, a stand-in for the
   companion work's filter) updates the gains in place on the device.
 
-The estimate is judged by re-simulation: one batch of three fresh-noise
+The estimate is checked by re-simulation: one batch of three fresh-noise
 copies of the network, at the estimated gains (ensemble mean), at the prior
 mean (all ones) and at the hidden gains (the noise floor), run over the
 whole assimilation period; each copy's BOLD is compared with the twin's.
