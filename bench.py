@@ -304,17 +304,20 @@ def tune_rates(net, rates, steps=400, skip=150, iters=9):
 
 
 def calibrate_copy(gib: float = 1.0):
-    """A plain elementwise pass of known size (reads and writes `gib` GiB),
-    whose FETCH_SIZE / WRITE_SIZE readings scale the counters of the
-    simulator's kernels."""
+    """Passes of known size whose FETCH_SIZE / WRITE_SIZE readings scale the
+    counters of the simulator's kernels: an elementwise add (reads and writes
+    `gib` GiB) and a sum (reads `gib` GiB, writes one value)."""
     import torch
     n = int(gib * (1 << 30)) // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
         torch.add(x, 1.0, out=y)
+    for _ in range(3):
+        s = x.sum()
     torch.cuda.synchronize()
-    return {"calibration": "elementwise add", "bytes_read": 4 * n, "bytes_written": 4 * n}
+    return {"calibration": "elementwise add, then sum", "bytes_read": 4 * n, "bytes_written": 4 * n,
+            "sum_bytes_read": 4 * n, "sum": float(s)}
 
 
 def main():
