@@ -530,10 +530,16 @@ __device__ inline const Bundle* block_row_sum(const SumBlock& S, int64_t r, floa
   const float* wf = reinterpret_cast<const float*>(S.wts);
   const uint16_t* wb = reinterpret_cast<const uint16_t*>(S.wts);
   const int64_t bit0 = B->hbit0 + (k0 - B->syn0);
-  // bits [bit0, bit0 + len) of the hit buffer, visited in ascending order
+  // bits [bit0, bit0 + len) of the hit buffer, visited in ascending order;
+  // the row's first kWords words are loaded together (a row of in-degree 100
+  // spans at most 5), then the window slides one word at a time
+  constexpr int kWords = 8;
   int64_t w = bit0 >> 5;
   const int64_t w1 = (bit0 + len - 1) >> 5;
-  uint32_t bits = S.hitbuf[w] & (~0u << (bit0 & 31));
+  uint32_t win[kWords];
+#pragma unroll
+  for (int q = 0; q < kWords; ++q) win[q] = w + q <= w1 ? S.hitbuf[w + q] : 0u;
+  uint32_t bits = win[0] & (~0u << (bit0 & 31));
   const uint32_t last = ~0u >> (31 - int((bit0 + len - 1) & 31));
   while (true) {
     // collect up to kHitBatch hit offsets of this row, then load their weights together
@@ -545,7 +551,11 @@ __device__ inline const Bundle* block_row_sum(const SumBlock& S, int64_t r, floa
         hp[nh++] = int((w << 5) + (__ffs(bits) - 1) - bit0);
         bits &= bits - 1u;
       } else if (w < w1) {
-        bits = S.hitbuf[++w];
+        ++w;
+#pragma unroll
+        for (int q = 0; q + 1 < kWords; ++q) win[q] = win[q + 1];
+        win[kWords - 1] = w + kWords - 1 <= w1 ? S.hitbuf[w + kWords - 1] : 0u;
+        bits = win[0];
       } else {
         break;
       }
