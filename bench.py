@@ -360,9 +360,11 @@ def main():
     key = autotune.shape_key(net.n, net.nnz, 1, args.wtype, net.max_delay)
     if args.autotune:
         net.bg_lambda = netgen.PARTITION_LAMBDA[rates[0]]
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        cands = (640_000, (1 << 20) - 1) + autotune.aligned_bundle_sizes(net.n, net.nnz, n_cu)
         best, res = autotune.tune(
             lambda b, u: dtb.Net(net, wtype=args.wtype, record_steps=64, stream=torch.cuda.current_stream(),
-                                 bundle_syn=b, unroll=u), key, log=log)
+                                 bundle_syn=b, unroll=u), key, bundles=cands, unrolls=(2, 3), log=log)
         out = {key: {"best": list(best), "ms_per_step": {f"{b}/{u}": v for (b, u), v in res.items()}}}
         del net
         members, gains = ensemble_members(64)
@@ -374,7 +376,9 @@ def main():
             h.set_gains(gains.reshape(-1, 4))
             return h
 
-        best, res = autotune.tune(make, ekey, log=log)
+        ecands = (640_000, (1 << 20) - 1) + autotune.aligned_bundle_sizes(
+            sum(m.n for m in members), sum(m.nnz for m in members), n_cu)
+        best, res = autotune.tune(make, ekey, bundles=ecands, unrolls=(2, 3), log=log)
         out[ekey] = {"best": list(best), "ms_per_step": {f"{b}/{u}": v for (b, u), v in res.items()}}
         print(json.dumps({"autotune": out}), flush=True)
         return

@@ -6,7 +6,8 @@ row's CSR order either way):
 * the bundle size (most synapses per workgroup): it sets the LDS hit bitmap
   per workgroup, hence how many workgroups share a CU, against the number
   of bitmap sweeps (each bundle reads the delayed spike bits of its sources
-  once per delay);
+  once per delay); sizes that make the bundle count a whole number of
+  rounds over the CUs avoid a partly idle last round;
 * the lookup tiles per wavefront per round (1, 2 or 3): bytes in flight per
   wavefront against registers (one tile per round fits 64 VGPRs, i.e. two
   1024-thread workgroups per CU).
@@ -26,6 +27,24 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 BUNDLES = (393_216, 640_000, (1 << 20) - 1)
 UNROLLS = (1, 2, 3)
+
+
+def aligned_bundle_sizes(n: int, nnz: int, n_cu: int, max_syn: int = (1 << 20) - 1, counts=(1, 2)):
+    """Bundle sizes whose bundle count is a whole number of rounds over the
+    CUs (one workgroup per CU at a time): for the smallest k rounds that
+    respect max_syn and the next count - 1 after it, the size that cuts the
+    rows (mean length nnz / n) into at most k * n_cu bundles."""
+    if n <= 0 or nnz <= 0:
+        return ()
+    L = nnz / n
+    k = max(1, -(-nnz // (max_syn * n_cu)))
+    out = []
+    for kk in range(k, k + len(counts)):
+        rows = -(-n // (kk * n_cu))
+        b = int(rows * L + 0.5)
+        if b <= max_syn:
+            out.append(b)
+    return tuple(out)
 
 
 def _arch() -> str:
