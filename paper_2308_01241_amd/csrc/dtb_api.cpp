@@ -555,7 +555,7 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
   d.slots = std::max(d.rec, d.max_delay) + 1;
   d.bg_w = desc->bg_w;
   d.seed = desc->seed;
-  d.compact_blocks = (d.words_pad + 2 * kCompactBlock - 1) / (2 * kCompactBlock);
+  d.compact_blocks = (d.words_pad + kCompactWords * kCompactBlock - 1) / (kCompactWords * kCompactBlock);
   for (int u = 0; u < 4; ++u) {
     d.a[u] = float(std::exp(-double(desc->dt_ms) / double(desc->tau_ms[u])));
     d.E[u] = desc->E[u];

@@ -16,6 +16,7 @@ constexpr int kNeuronPad = 1024;    // neuron arrays padded to this multiple
 constexpr int kStripes = 64;        // striped event counters per step
 constexpr int kMaxPoisson = 512;    // entries of the background inversion table
 constexpr int kCompactBlock = 256;  // threads of the compaction kernel
+constexpr int kCompactWords = 8;    // bitmap words per compaction thread
 
 // ---- gather layout ("bundles") --------------------------------------------
 // Rows are cut into bundles of consecutive rows holding at most

@@ -188,8 +188,10 @@ __global__ __launch_bounds__(1024 / kNpt) void k_neuron_update(
 }
 
 // ---------------------------------------------------------------- compaction
-// Each thread owns 64 neurons (two bitmap words).  Blocks take a dynamic
-// ticket so that a block only waits on blocks that are already running.
+// Each thread owns 32 * kCompactWords neurons (kCompactWords bitmap words),
+// so a block covers 65,536 neurons and the look-back chain stays short.
+// Blocks take a dynamic ticket so that a block only waits on blocks that
+// are already running.
 // Look-back status word: epoch (32) | flag (2: 1 aggregate, 2 prefix) | value (30);
 // one wavefront inspects 64 predecessors per round.
 __device__ inline uint64_t pack_status(uint32_t epoch, uint32_t flag, uint32_t value) {
@@ -215,10 +217,14 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
   if (tid == 0) s_bid = atomicAdd(ticket, 1u);
   __syncthreads();
   const int64_t bid = s_bid;
-  const int64_t w0 = (bid * kCompactBlock + tid) * 2;
-  uint32_t a = w0 < words ? bits[w0] : 0u;
-  uint32_t b = w0 + 1 < words ? bits[w0 + 1] : 0u;
-  const int c = __popc(a) + __popc(b);
+  const int64_t w0 = (bid * kCompactBlock + tid) * kCompactWords;
+  uint32_t wv[kCompactWords];
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < kCompactWords; ++q) {
+    wv[q] = w0 + q < words ? bits[w0 + q] : 0u;
+    c += __popc(wv[q]);
+  }
   int x = c;  // inclusive scan across the wavefront
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -273,16 +279,14 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
   }
   __syncthreads();
   int off = s_excl + wave_off + x - c;
-  const int32_t base = int32_t(w0 * 32);
-  while (a) {
-    const int q = __ffs(a) - 1;
-    ids[off++] = base + q;
-    a &= a - 1u;
-  }
-  while (b) {
-    const int q = __ffs(b) - 1;
-    ids[off++] = base + 32 + q;
-    b &= b - 1u;
+#pragma unroll
+  for (int q = 0; q < kCompactWords; ++q) {
+    uint32_t a = wv[q];
+    const int32_t base = int32_t((w0 + q) * 32);
+    while (a) {
+      ids[off++] = base + (__ffs(a) - 1);
+      a &= a - 1u;
+    }
   }
 }
 
