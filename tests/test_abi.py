@@ -134,3 +134,22 @@ def test_bit_packing_roundtrip():
         i = int(np.argmax(r[0])) if r[0].any() else None
         if i is not None:
             assert (int(b[0, i >> 5]) >> (i & 31)) & 1 == 1
+
+
+def test_remote_and_enkf_validation_without_a_gpu(lib):
+    P = ctypes.c_void_p
+    assert lib.dtb_set_remote_block(None, 10, 0, None, None, None, None, None) == -1
+    assert lib.dtb_push_remote_spikes(None, None, 1) == -1
+    fake = P(16)            # never dereferenced: validation fails first
+    r = np.ones(65, np.float32)
+    rp = P(r.ctypes.data)
+    # null arrays, too many observations, one member, inflation below 1, r <= 0
+    assert lib.dtb_enkf_analysis(4, 3, 2, None, fake, fake, rp, 1.0, 0, 0, 0.0, 1.0, None) == -1
+    assert lib.dtb_enkf_analysis(4, 3, 65, fake, fake, fake, rp, 1.0, 0, 0, 0.0, 1.0, None) == -1
+    assert lib.dtb_enkf_analysis(1, 3, 2, fake, fake, fake, rp, 1.0, 0, 0, 0.0, 1.0, None) == -1
+    assert lib.dtb_enkf_analysis(4, 3, 2, fake, fake, fake, rp, 0.5, 0, 0, 0.0, 1.0, None) == -1
+    assert lib.dtb_enkf_analysis(4, 3, 2, fake, fake, fake, rp, 1.0, 0, 0, 2.0, 1.0, None) == -1
+    bad = np.array([1.0, 0.0], np.float32)
+    assert lib.dtb_enkf_analysis(4, 3, 2, fake, fake, fake, P(bad.ctypes.data), 1.0, 0, 0, 0.0, 1.0, None) == -1
+    # LDS beyond 160 KB is unsupported, before any launch
+    assert lib.dtb_enkf_analysis(4096, 8, 64, fake, fake, fake, rp, 1.0, 0, 0, 0.0, 1.0, None) == -6
