@@ -105,7 +105,13 @@ class Net:
 
     # ------------------------------------------------------------ stepping
     def step(self, n_steps: int = 1) -> None:
-        check(self._lib.dtb_step(self._h, int(n_steps)))
+        st = self._lib.dtb_step(self._h, int(n_steps))
+        if st != 0:
+            # the library may have taken some of the steps before failing
+            steps = ctypes.c_int64(self.t)
+            if self._lib.dtb_read_counters(self._h, ctypes.byref(steps), None, None, None) == 0:
+                self.t = int(steps.value)
+            check(st)
         self.t += int(n_steps)
 
     def run(self, n_steps: int) -> None:

@@ -179,6 +179,10 @@ def test_remote_block_errors(dtb):
     g.step(2)
     with pytest.raises(dtb.DtbError):
         g.step(1)
+    g.push_remote(rem[2:3])
+    with pytest.raises(dtb.DtbError):
+        g.step(3)                                                   # one step taken, then none pushed
+    assert g.t == 3 and g.counters()["steps"] == 3
     m = dtb.Net.batch([net, dataclasses.replace(net, member=1)])
     with pytest.raises(dtb.DtbError):
         m.set_remote_block(netgen.make_remote_block(m.n, 100, 3, max_delay=net.max_delay))
