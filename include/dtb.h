@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 7
+#define DTB_ABI_VERSION 8
 
 typedef enum {
   DTB_OK = 0,
@@ -371,6 +371,28 @@ dtb_status dtb_partition(int64_t n_vert, const double* size, const double* neuro
                          const int64_t* e_ptr, const int32_t* e_dst, const double* e_syn, int32_t n_gpu,
                          double capacity, double bytes_per_spike, const int32_t* init, int32_t refine_rounds,
                          int32_t* part, double* F_out, double* D_out);
+
+/* ------------------------------------------------- checkpoint / resume */
+
+/* Save the handle's dynamic state into host memory so that a run can be
+ * resumed later (a checkpoint of the simulation; the paper keeps the state
+ * variables in GPU memory for the whole run, Sec. V-B): V, gates, refractory
+ * counters, OU currents, gains, the spike-bitmap ring (and the remote ring),
+ * population counts, event counters and totals, the last spike-id list, the
+ * step counter, the BOLD state, and the background settings.  The network
+ * tables are not saved: a state is loaded into a handle created from the
+ * same description (and given the same remote block).  host_buf NULL asks
+ * for the size only (*used); otherwise cap must be at least that size
+ * (DTB_ERR_INVALID, *used set).  Not while teacher forcing or pushed
+ * remote spikes are pending (DTB_ERR_STATE).  Synchronizes the stream. */
+dtb_status dtb_save(dtb_net* net, void* host_buf, size_t cap, size_t* used);
+
+/* Restore a state written by dtb_save (host buffer of len bytes) into a
+ * handle of the same shape (DTB_ERR_INVALID otherwise: other sizes, record
+ * steps, weight type, member count or remote block, a truncated or foreign
+ * buffer).  The next step continues the saved run exactly; pending teacher
+ * forcing and remote spikes are dropped.  Synchronizes the stream. */
+dtb_status dtb_load(dtb_net* net, const void* host_buf, size_t len);
 
 /* Wait for the handle's stream; report asynchronous failures (DTB_ERR_NUMERIC
  * when a non-finite V or gate was produced since the last check). */

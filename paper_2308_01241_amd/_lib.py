@@ -55,6 +55,8 @@ SIGNATURES = {
     "dtb_force_spikes": ([_P, _P, _I32], ctypes.c_int),
     "dtb_set_remote_block": ([_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P, _P, _P], ctypes.c_int),
     "dtb_push_remote_spikes": ([_P, _P, _I32], ctypes.c_int),
+    "dtb_save": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "dtb_load": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
     "dtb_partition": ([ctypes.c_int64, _P, _P, _P, _P, _P, _P, _I32, ctypes.c_double, ctypes.c_double, _P, _I32,
                        _P, _P, _P], ctypes.c_int),
     "dtb_enkf_analysis": ([_I32, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, ctypes.c_uint64, ctypes.c_int64,
@@ -106,7 +108,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 7:
+    if lib.dtb_abi_version() != 8:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

@@ -1205,6 +1205,145 @@ dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int6
   return DTB_OK;
 }
 
+// ------------------------------------------------------ checkpoint / resume
+namespace {
+struct SaveHeader {
+  char magic[8];
+  int32_t abi, wtype;
+  int64_t n, n_pad, words_pad, slots, n_regions, rec, members, n_remote, rwords_pad;
+  int64_t t, total_bytes;
+  int32_t poisson_K, ou_on;
+  float bg_w, ou_mu, ou_a, ou_s;
+};
+constexpr char kSaveMagic[8] = {'D', 'T', 'B', 'S', 'T', 'A', 'T', '1'};
+
+// the handle's dynamic state, in file order: (device pointer, bytes)
+std::vector<std::pair<void*, size_t>> state_sections(const dtb_net* net, int32_t ou_on) {
+  const DeviceNet& d = net->d;
+  const size_t slots = size_t(d.slots), R = size_t(d.n_regions), np = size_t(d.n_pad);
+  std::vector<std::pair<void*, size_t>> v = {
+      {d.V, np * 4},           {d.j, 4 * np * 4},
+      {d.ref, np},             {d.gain, 4 * R * 4},
+      {d.raster, slots * size_t(d.words_pad) * 4},
+      {d.counts, slots * R * 4}, {d.ev, slots * kStripes * 2 * 8},
+      {d.totals, 4 * 8},       {d.ids, np * 4},
+      {d.id_count, 4},         {d.step, 2 * 8},
+      {d.bold, 4 * R * 4},     {d.bold_y, R * 4}};
+  if (ou_on) v.emplace_back(d.ou, np * 4);
+  if (net->remote) v.emplace_back(d.rraster, slots * size_t(d.rwords_pad) * 4);
+  return v;
+}
+}  // namespace
+
+dtb_status dtb_save(dtb_net* net, void* host_buf, size_t cap, size_t* used) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!used) return fail(DTB_ERR_INVALID, "used is NULL");
+  const DeviceNet& d = net->d;
+  if (net->force_pending || net->rq_pending)
+    return fail(DTB_ERR_STATE, "teacher forcing or remote spikes are pending: step them first");
+  const int32_t ou_on = d.ou_on && d.ou ? 1 : 0;
+  const auto sec = state_sections(net, ou_on);
+  size_t total = sizeof(SaveHeader) + size_t(d.poisson_K) * 4;
+  for (auto& x : sec) total += x.second;
+  *used = total;
+  if (!host_buf) return DTB_OK;  // size query
+  if (cap < total) return fail(DTB_ERR_INVALID, "buffer smaller than the state (" + std::to_string(total) + " B)");
+  SaveHeader h{};
+  std::memcpy(h.magic, kSaveMagic, 8);
+  h.abi = DTB_ABI_VERSION;
+  h.wtype = d.wtype;
+  h.n = d.n;
+  h.n_pad = d.n_pad;
+  h.words_pad = d.words_pad;
+  h.slots = d.slots;
+  h.n_regions = d.n_regions;
+  h.rec = d.rec;
+  h.members = int64_t(net->member_row0.size());
+  h.n_remote = net->remote ? d.n_remote : 0;
+  h.rwords_pad = net->remote ? d.rwords_pad : 0;
+  h.t = net->t;
+  h.total_bytes = int64_t(total);
+  h.poisson_K = d.poisson_K;
+  h.ou_on = ou_on;
+  h.bg_w = d.bg_w;
+  h.ou_mu = d.ou_mu;
+  h.ou_a = d.ou_a;
+  h.ou_s = d.ou_s;
+  uint8_t* out = static_cast<uint8_t*>(host_buf);
+  std::memcpy(out, &h, sizeof(h));
+  size_t off = sizeof(h);
+  hipError_t e = hipSuccess;
+  if (d.poisson_K > 0)
+    e = hipMemcpyAsync(out + off, d.poisson, size_t(d.poisson_K) * 4, hipMemcpyDeviceToHost, net->stream);
+  off += size_t(d.poisson_K) * 4;
+  for (auto& x : sec) {
+    if (e == hipSuccess) e = hipMemcpyAsync(out + off, x.first, x.second, hipMemcpyDeviceToHost, net->stream);
+    off += x.second;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "save");
+  return DTB_OK;
+}
+
+dtb_status dtb_load(dtb_net* net, const void* host_buf, size_t len) {
+  dtb_status st = check_net(net);
+  if (st) return st;
+  if (!host_buf || len < sizeof(SaveHeader)) return fail(DTB_ERR_INVALID, "buffer too short for a saved state");
+  SaveHeader h;
+  std::memcpy(&h, host_buf, sizeof(h));
+  DeviceNet& d = net->d;
+  if (std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.abi != DTB_ABI_VERSION)
+    return fail(DTB_ERR_INVALID, "not a saved state of this library version");
+  if (h.wtype != d.wtype || h.n != d.n || h.n_pad != d.n_pad || h.words_pad != d.words_pad || h.slots != d.slots ||
+      h.n_regions != d.n_regions || h.rec != d.rec || h.members != int64_t(net->member_row0.size()) ||
+      h.n_remote != (net->remote ? d.n_remote : 0) || h.rwords_pad != (net->remote ? d.rwords_pad : 0))
+    return fail(DTB_ERR_INVALID, "the saved state belongs to a handle of another shape");
+  if (h.total_bytes < 0 || size_t(h.total_bytes) > len) return fail(DTB_ERR_INVALID, "truncated saved state");
+  if (h.poisson_K < 0 || h.poisson_K > kMaxPoisson || h.t < 0 || h.ou_on < 0 || h.ou_on > 1)
+    return fail(DTB_ERR_INVALID, "corrupt saved state header");
+  size_t total = sizeof(SaveHeader) + size_t(h.poisson_K) * 4;
+  for (auto& x : state_sections(net, h.ou_on)) total += x.second;  // sizes only (d.ou may not exist yet)
+  if (size_t(h.total_bytes) != total) return fail(DTB_ERR_INVALID, "saved state size does not match");
+  // background settings (kernel arguments: the captured graph is dropped)
+  drop_graph(net);
+  if (h.poisson_K > d.poisson_cap) {
+    uint32_t* q = nullptr;
+    if ((st = dalloc(net, &q, h.poisson_K))) return st;
+    d.poisson = q;
+    d.poisson_cap = h.poisson_K;
+  }
+  if (h.ou_on && !d.ou && (st = dalloc(net, &d.ou, d.n_pad))) return st;
+  const uint8_t* in = static_cast<const uint8_t*>(host_buf);
+  size_t off = sizeof(h);
+  hipError_t e = hipSuccess;
+  if (h.poisson_K > 0)
+    e = hipMemcpyAsync(d.poisson, in + off, size_t(h.poisson_K) * 4, hipMemcpyHostToDevice, net->stream);
+  off += size_t(h.poisson_K) * 4;
+  for (auto& x : state_sections(net, h.ou_on)) {
+    if (e == hipSuccess) e = hipMemcpyAsync(x.first, in + off, x.second, hipMemcpyHostToDevice, net->stream);
+    off += x.second;
+  }
+  // compaction look-back words and the failure flag start clean
+  if (e == hipSuccess) e = hipMemsetAsync(d.cstatus, 0, size_t(d.compact_blocks) * 8, net->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.cticket, 0, 4, net->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.bad, 0, 4, net->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "load");
+  d.poisson_K = h.poisson_K;
+  d.bg_w = h.bg_w;
+  d.ou_on = h.ou_on;
+  d.ou_mu = h.ou_mu;
+  d.ou_a = h.ou_a;
+  d.ou_s = h.ou_s;
+  net->t = h.t;
+  net->force_pending = 0;
+  net->force_head = 0;
+  net->rq_pending = 0;
+  net->rq_head = 0;
+  return DTB_OK;
+}
+
 dtb_status dtb_sync(dtb_net* net) {
   dtb_status st = check_net(net);
   if (st) return st;

@@ -180,6 +180,22 @@ class Net:
         b = b.reshape(-1, self.remote_words) if self.n_remote else b.reshape(1, -1)
         check(self._lib.dtb_push_remote_spikes(self._h, _ptr(b), int(b.shape[0])))
 
+    def save(self) -> bytes:
+        """The handle's dynamic state (checkpoint) as bytes."""
+        used = ctypes.c_size_t(0)
+        check(self._lib.dtb_save(self._h, None, 0, ctypes.byref(used)))
+        buf = np.zeros(used.value, dtype=np.uint8)
+        check(self._lib.dtb_save(self._h, _ptr(buf), buf.size, ctypes.byref(used)))
+        return buf.tobytes()
+
+    def load(self, state: bytes) -> None:
+        """Resume from a state returned by save() on a handle of the same shape."""
+        buf = np.frombuffer(state, dtype=np.uint8)
+        check(self._lib.dtb_load(self._h, ctypes.c_void_p(buf.ctypes.data), buf.size))
+        steps = ctypes.c_int64(0)
+        check(self._lib.dtb_read_counters(self._h, ctypes.byref(steps), None, None, None))
+        self.t = int(steps.value)
+
     def set_timing(self, enable: bool) -> None:
         check(self._lib.dtb_set_timing(self._h, 1 if enable else 0))
 

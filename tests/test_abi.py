@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_bitmap_words(lib):
-    assert lib.dtb_abi_version() == 7
+    assert lib.dtb_abi_version() == 8
     assert [lib.dtb_bitmap_words(n) for n in (0, 1, 32, 33, 64)] == [0, 1, 1, 2, 2]
     assert isinstance(lib.dtb_last_error(), bytes)
 
@@ -153,3 +153,9 @@ def test_remote_and_enkf_validation_without_a_gpu(lib):
     assert lib.dtb_enkf_analysis(4, 3, 2, fake, fake, fake, P(bad.ctypes.data), 1.0, 0, 0, 0.0, 1.0, None) == -1
     # LDS beyond 160 KB is unsupported, before any launch
     assert lib.dtb_enkf_analysis(4096, 8, 64, fake, fake, fake, rp, 1.0, 0, 0, 0.0, 1.0, None) == -6
+
+
+def test_checkpoint_validation_without_a_gpu(lib):
+    used = ctypes.c_size_t(0)
+    assert lib.dtb_save(None, None, 0, ctypes.byref(used)) == -1
+    assert lib.dtb_load(None, None, 0) == -1
