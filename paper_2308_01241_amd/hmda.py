@@ -43,7 +43,8 @@ class HmdaSetup:
     regions: int = 20          # populations
     window: int = 800          # steps between BOLD samples (dt = 1 ms)
     windows: int = 30          # assimilation iterations
-    rate_hz: int = 15          # background drive
+    rate_hz: int = 7           # background drive (the partition net's 7 Hz level)
+    bg_lambda: float = 0.24    # background Poisson count per neuron-step (< 0: the rate_hz level)
     prior_sd: float = 0.2      # prior spread of the gains around 1
     hidden_sd: float = 0.2     # spread of the twin's hidden gains around 1
     obs_rel: float = 0.1       # observation error sd, relative to the BOLD signal's rms
@@ -59,7 +60,8 @@ def log(*a):
 
 def _network(S: HmdaSetup):
     import netgen
-    spec = netgen.partition_spec(n=S.n, rate_hz=S.rate_hz, n_regions=S.regions, seeds=(4100, 4101, 4102))
+    spec = netgen.partition_spec(n=S.n, rate_hz=S.rate_hz, n_regions=S.regions, seeds=(4100, 4101, 4102),
+                                 bg_lambda=None if S.bg_lambda < 0 else S.bg_lambda)
     return netgen.make_network(spec)
 
 
@@ -103,6 +105,7 @@ def run(S: HmdaSetup):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     hist = []
     sim_ms = ana_ms = 0.0
+    c_prev = ens.counters()
     for k in range(S.windows):
         ev[0].record(stream)
         ens.set_gains_from(X.view(M * R, 4))
@@ -117,7 +120,12 @@ def run(S: HmdaSetup):
         sim_ms += ev[0].elapsed_time(ev[1])
         ana_ms += ev[1].elapsed_time(ev[2])
         g = X[:, :, 0].cpu().numpy()
+        c_now = ens.counters()
+        spikes, events = c_now["spikes"] - c_prev["spikes"], c_now["ev_rec"] - c_prev["ev_rec"]
+        c_prev = c_now
         rec = {"window": k, "forecast_rmse": float(np.sqrt(np.mean((forecast - yo[k]) ** 2))),
+               "mean_rate_hz": spikes / (M * net.n * S.window * net.dt_ms * 1e-3),
+               "events_per_step": events / S.window,
                "obs_rms": float(np.sqrt(np.mean(yo[k] ** 2))),
                "gain_rmse": float(np.sqrt(np.mean((g.mean(0) - hidden) ** 2))),
                "gain_spread": float(g.std(0).mean())}
