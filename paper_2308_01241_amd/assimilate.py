@@ -47,7 +47,7 @@ class Setup:
     hi: int = 400_000
     regions: int = 20          # populations per member
     window: int = 400          # steps per window (dt = 1 ms)
-    rate_hz: int = 15          # background drive of the members
+    rate_hz: int = 7           # background drive of the members (about 10 Hz)
     target_n: int = 200_000    # size of the twin target
 
 
@@ -242,12 +242,13 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=8)
     ap.add_argument("--seeds", type=str, default="0,1,2")
     ap.add_argument("--target-n", type=int, default=200_000)
+    ap.add_argument("--rate-hz", type=int, default=Setup.rate_hz, help="background drive level of the members")
     ap.add_argument("--out", type=str, default="")
     a = ap.parse_args(argv)
     import netgen
     from . import Net
 
-    S = Setup(members=a.members, window=a.window, target_n=a.target_n)
+    S = Setup(members=a.members, window=a.window, target_n=a.target_n, rate_hz=a.rate_hz)
     t0 = time.time()
     members = member_networks(S)
     net = Net.batch(members, record_steps=2 * S.window, stream=_stream())
@@ -264,6 +265,7 @@ def main(argv=None):
     err = evaluate(m, sx, sy, Xt, Yt, S.regions)
     log(f"[train] held-out error: {json.dumps(err)}")
     rep = {"setup": dataclasses.asdict(S), "samples": int(len(X)), "test_samples": int(len(Xt)),
+           "mean_rate_hz": float(Y[:, :S.regions].mean()),
            "generate_s": gen_s, "train_s": train_s, "held_out": err, "screen": {}}
     target = netgen.make_network(netgen.ensemble_member_spec(41, S.target_n, rate_hz=S.rate_hz,
                                                              n_regions=S.regions))
