@@ -1,9 +1,14 @@
 """Pins of the FP64 Balloon-Windkessel reference (Sec. V-E): exact rest
 under zero input, the closed-form fixed point under constant input (reached
 by long integration), and the steady-state derivatives vanishing there."""
+import json
+import os
+
 import numpy as np
 
 from oracle import bold
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "worked_examples.json")))
 
 
 def test_rest_is_exact_under_zero_input():
@@ -17,9 +22,10 @@ def test_fixed_point_closed_form_values():
     fp, y = bold.fixed_point(7.0)
     assert abs(fp[1] - 1.0853658536585367) < 1e-15
     assert abs(fp[2] - 1.0853658536585367 ** 0.32) < 1e-15
-    assert abs(fp[1] - 1.085366) < 1e-6 and abs(fp[2] - 1.026560) < 1e-6
-    assert abs(fp[3] - 0.960360) < 2e-6
-    assert abs(y - 4.2114e-3) < 1e-6
+    ex = GOLDEN["bold_fixed_point_u007"]
+    assert abs(fp[1] - ex["f"]) < 1e-6 and abs(fp[2] - ex["v"]) < 1e-6
+    assert abs(fp[3] - ex["q"]) < 2e-6
+    assert abs(y - ex["y"]) < 1e-6
 
 
 def test_fixed_point_is_stationary_for_the_euler_map():

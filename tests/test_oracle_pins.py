@@ -2,7 +2,9 @@
 routines (numpy's Philox, scipy's Poisson CDF), closed forms of the model of
 Sec. III-B Eq. (1) under forward Euler (Sec. VI-A), integer invariants of the
 spike delivery, and a dense brute-force formulation on tiny nets."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -12,6 +14,8 @@ import netgen
 import oracle
 from oracle import brute
 from nethelpers import hand_net
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "worked_examples.json")))
 
 
 # ---------------------------------------------------------------- RNG / Poisson
@@ -90,6 +94,7 @@ def test_single_spike_impulse_and_exact_decay(inh, d):
     # tau = 2 ms, 10 steps: e^-5
     if not inh:
         assert abs(js[arrive + 10, 0] - 6.737946999085467e-03) < 1e-15
+        assert abs(js[arrive + 10, 0] - GOLDEN["gate_decay"]["value"]) < 1e-9
 
 
 def test_isi_discrete_closed_form():
@@ -105,16 +110,17 @@ def test_isi_discrete_closed_form():
     gL, Iext = float(np.float32(0.03)), float(np.float32(1.05))
     rho, Vinf = 1.0 - gL, -75.0 + Iext / gL
     nstar = math.ceil(math.log((Vinf + 50.0) / (Vinf + 65.0)) / math.log(rho))
-    assert nstar == 31
+    ex = GOLDEN["isi_discrete"]
+    assert nstar == ex["n_star"]
     assert spikes[0] == nstar - 1          # integrates from step 0
-    assert np.all(np.diff(spikes) == 2 + nstar)
+    assert np.all(np.diff(spikes) == ex["isi_steps"])
     V = np.array([s["V"][0] for s in r["states"]])  # V after step t
     # after 30 integration steps from Vreset (state after step 29)
     np.testing.assert_allclose(V[29], Vinf + rho**30 * (-65.0 - Vinf), rtol=1e-14)
-    assert abs(V[29] - (-50.025)) < 1e-3
+    assert abs(V[29] - ex["V_after_30_steps_mV"]) < 1e-3
     # the step that crosses: Vt = -49.724 mV, margin 0.276 mV
     assert abs(r["margins"][30, 0] - abs(Vinf + rho**31 * (-65.0 - Vinf) + 50.0)) < 1e-12
-    assert abs(r["margins"][30, 0] - 0.276) < 1e-3
+    assert abs(r["margins"][30, 0] - ex["crossing_margin_mV"]) < 1e-3
     # refractory: held at Vreset for the 2 steps after a spike
     s0 = spikes[0]
     assert V[s0] == -65.0 and V[s0 + 1] == -65.0 and V[s0 + 2] == -65.0
@@ -131,7 +137,7 @@ def test_isi_converges_to_continuous_limit():
     spikes = np.nonzero(r["raster"][:, 0])[0]
     isi_ms = np.diff(spikes)[0] * dt
     limit = 2.0 + (1.0 / 0.03) * math.log(25.0 / 10.0)
-    assert abs(limit - 32.543) < 1e-3
+    assert abs(limit - GOLDEN["isi_continuous_limit_ms"]["value"]) < 1e-3
     assert abs(isi_ms - limit) < 3 * dt
 
 
