@@ -1206,6 +1206,8 @@ dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int6
 }
 
 // ------------------------------------------------------ checkpoint / resume
+}  // extern "C"
+
 namespace {
 struct SaveHeader {
   char magic[8];
@@ -1234,6 +1236,8 @@ std::vector<std::pair<void*, size_t>> state_sections(const dtb_net* net, int32_t
   return v;
 }
 }  // namespace
+
+extern "C" {
 
 dtb_status dtb_save(dtb_net* net, void* host_buf, size_t cap, size_t* used) {
   dtb_status st = check_net(net);

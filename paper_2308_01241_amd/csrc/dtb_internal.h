@@ -54,6 +54,14 @@ constexpr int kHitWords = int(kBundleMaxSyn >> 5) + 1;       // LDS hit bitmap w
 #ifndef DTB_GATHER_THREADS
 #define DTB_GATHER_THREADS 1024
 #endif
+// rows per thread of the sums kernel (1 or 2; two rows' loads in flight per
+// thread cost more registers than they hide latency: 0.535 vs 0.488 ms)
+#ifndef DTB_SUMS_ROWS
+#define DTB_SUMS_ROWS 1
+#endif
+constexpr int kSumsRows = DTB_SUMS_ROWS;
+static_assert(kSumsRows == 1 || kSumsRows == 2, "rows per sums thread: 1 or 2");
+
 // neurons per thread of the neuron update (1, 2 or 4)
 #ifndef DTB_UPDATE_NPT
 #define DTB_UPDATE_NPT 2

@@ -509,7 +509,7 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
 // (t, i, member, 0) with i the neuron's index inside its member network),
 // then the four gates (exact decay + jump).  A row's delivery tests are the
 // bits hbit0 + (k - syn0) of its bundle in the block's hit buffer.
-constexpr int kSumsThreads = 1024;
+constexpr int kSumsRowsPerBlock = 1024;  // rows per workgroup (the block table's granularity)
 
 // the tables one in-edge block hands to the sums
 struct SumBlock {
@@ -521,106 +521,173 @@ struct SumBlock {
 };
 
 // adds row r's delivered weights of one block to (dE, dI) in CSR order;
-// returns the row's bundle
-template <bool kBF16>
-__device__ inline const Bundle* block_row_sum(const SumBlock& S, int64_t r, float& dE, float& dI) {
-  constexpr int kHitBatch = 8;
-  int32_t b = S.block_bundle[r / kSumsThreads];
+// A row's walk over one block's hit bits [bit0, bit0 + len), in ascending
+// order: the first kWalkWords words are loaded together (a row of
+// in-degree 100 spans at most 5), then the window slides one word at a
+// time; hits are taken kWalkHits at a time and their weights loaded
+// together.
+constexpr int kWalkWords = 5;
+constexpr int kWalkHits = 4;
+
+struct RowWalk {
+  int64_t k0, bit0, w, w1;
+  int len;
+  uint32_t bits, last;
+  uint32_t win[kWalkWords];
+};
+
+// the row's bundle, CSR range and first hit words
+__device__ inline const Bundle* walk_init(const SumBlock& S, int64_t r, RowWalk& R) {
+  int32_t b = S.block_bundle[r / kSumsRowsPerBlock];
   while (r >= S.bundles[b].row1) ++b;  // bundles are consecutive row ranges
   const Bundle* B = S.bundles + b;
   const int64_t k0 = S.row_ptr[r], k1 = S.row_ptr[r + 1];
-  const int len = int(k1 - k0);
-  if (len <= 0) return B;
-  const float* wf = reinterpret_cast<const float*>(S.wts);
-  const uint16_t* wb = reinterpret_cast<const uint16_t*>(S.wts);
-  const int64_t bit0 = B->hbit0 + (k0 - B->syn0);
-  // bits [bit0, bit0 + len) of the hit buffer, visited in ascending order;
-  // the row's first kWords words are loaded together (a row of in-degree 100
-  // spans at most 5), then the window slides one word at a time
-  constexpr int kWords = 8;
-  int64_t w = bit0 >> 5;
-  const int64_t w1 = (bit0 + len - 1) >> 5;
-  uint32_t win[kWords];
+  R.k0 = k0;
+  R.len = int(k1 - k0);
+  R.bit0 = B->hbit0 + (k0 - B->syn0);
+  R.w = R.bit0 >> 5;
+  R.w1 = (R.bit0 + R.len - 1) >> 5;
 #pragma unroll
-  for (int q = 0; q < kWords; ++q) win[q] = w + q <= w1 ? S.hitbuf[w + q] : 0u;
-  uint32_t bits = win[0] & (~0u << (bit0 & 31));
-  const uint32_t last = ~0u >> (31 - int((bit0 + len - 1) & 31));
-  while (true) {
-    // collect up to kHitBatch hit offsets of this row, then load their weights together
-    int hp[kHitBatch];
-    int nh = 0;
-    while (nh < kHitBatch) {
-      if (w == w1) bits &= last;
-      if (bits) {
-        hp[nh++] = int((w << 5) + (__ffs(bits) - 1) - bit0);
-        bits &= bits - 1u;
-      } else if (w < w1) {
-        ++w;
-#pragma unroll
-        for (int q = 0; q + 1 < kWords; ++q) win[q] = win[q + 1];
-        win[kWords - 1] = w + kWords - 1 <= w1 ? S.hitbuf[w + kWords - 1] : 0u;
-        bits = win[0];
-      } else {
-        break;
-      }
-    }
-    uint32_t x[kHitBatch];
-#pragma unroll
-    for (int q = 0; q < kHitBatch; ++q)
-      if (q < nh)
-        x[q] = kBF16 ? uint32_t(stream_load(wb + k0 + hp[q])) << 16 : __float_as_uint(stream_load(wf + k0 + hp[q]));
-#pragma unroll
-    for (int q = 0; q < kHitBatch; ++q) {
-      if (q < nh) {
-        const float wv = __uint_as_float(x[q] & 0x7FFFFFFFu);
-        if (x[q] >> 31) dI += wv;
-        else dE += wv;
-      }
-    }
-    if (nh < kHitBatch) break;
-  }
+  for (int q = 0; q < kWalkWords; ++q) R.win[q] = R.len > 0 && R.w + q <= R.w1 ? S.hitbuf[R.w + q] : 0u;
+  R.bits = R.win[0] & (~0u << (R.bit0 & 31));
+  R.last = ~0u >> (31 - int((R.bit0 + R.len - 1) & 31));
   return B;
 }
 
+// the next up to kWalkHits hit offsets of the row (fewer: the row is done)
+__device__ inline int walk_collect(const SumBlock& S, RowWalk& R, int (&hp)[kWalkHits]) {
+  int nh = 0;
+  if (R.len <= 0) return 0;
+  while (nh < kWalkHits) {
+    if (R.w == R.w1) R.bits &= R.last;
+    if (R.bits) {
+      hp[nh++] = int((R.w << 5) + (__ffs(R.bits) - 1) - R.bit0);
+      R.bits &= R.bits - 1u;
+    } else if (R.w < R.w1) {
+      ++R.w;
+#pragma unroll
+      for (int q = 0; q + 1 < kWalkWords; ++q) R.win[q] = R.win[q + 1];
+      R.win[kWalkWords - 1] = R.w + kWalkWords - 1 <= R.w1 ? S.hitbuf[R.w + kWalkWords - 1] : 0u;
+      R.bits = R.win[0];
+    } else {
+      break;
+    }
+  }
+  return nh;
+}
+
 template <bool kBF16>
-__global__ __launch_bounds__(kSumsThreads) void k_sums(
+__device__ inline void walk_load(const SumBlock& S, const RowWalk& R, const int (&hp)[kWalkHits], int nh,
+                                 uint32_t (&x)[kWalkHits]) {
+  const float* wf = reinterpret_cast<const float*>(S.wts);
+  const uint16_t* wb = reinterpret_cast<const uint16_t*>(S.wts);
+#pragma unroll
+  for (int q = 0; q < kWalkHits; ++q)
+    if (q < nh)
+      x[q] = kBF16 ? uint32_t(stream_load(wb + R.k0 + hp[q])) << 16 : __float_as_uint(stream_load(wf + R.k0 + hp[q]));
+}
+
+__device__ inline void walk_add(const uint32_t (&x)[kWalkHits], int nh, float& dE, float& dI) {
+#pragma unroll
+  for (int q = 0; q < kWalkHits; ++q) {
+    if (q < nh) {
+      const float wv = __uint_as_float(x[q] & 0x7FFFFFFFu);
+      if (x[q] >> 31) dI += wv;
+      else dE += wv;
+    }
+  }
+}
+
+// adds the delivered weights of one block to the kRows rows of a thread,
+// each row in its CSR order; the rows' first batches of loads are issued
+// together
+template <bool kBF16, int kRows>
+__device__ inline void block_rows_sum(const SumBlock& S, const int64_t (&r)[kRows], const bool (&valid)[kRows],
+                                      float (&dE)[kRows], float (&dI)[kRows], const Bundle* (&B)[kRows]) {
+  RowWalk R[kRows];
+#pragma unroll
+  for (int h = 0; h < kRows; ++h) {
+    if (valid[h]) B[h] = walk_init(S, r[h], R[h]);
+    else R[h].len = 0;
+  }
+  int hp[kRows][kWalkHits];
+  int nh[kRows];
+  uint32_t x[kRows][kWalkHits];
+#pragma unroll
+  for (int h = 0; h < kRows; ++h) nh[h] = walk_collect(S, R[h], hp[h]);
+#pragma unroll
+  for (int h = 0; h < kRows; ++h) walk_load<kBF16>(S, R[h], hp[h], nh[h], x[h]);
+#pragma unroll
+  for (int h = 0; h < kRows; ++h) {
+    walk_add(x[h], nh[h], dE[h], dI[h]);
+    while (nh[h] == kWalkHits) {
+      nh[h] = walk_collect(S, R[h], hp[h]);
+      walk_load<kBF16>(S, R[h], hp[h], nh[h], x[h]);
+      walk_add(x[h], nh[h], dE[h], dI[h]);
+    }
+  }
+}
+
+template <bool kBF16, int kRows>
+__global__ __launch_bounds__(kSumsRowsPerBlock / kRows) void k_sums(
     int64_t n, int64_t n_pad, const int64_t* __restrict__ step, SumBlock loc, SumBlock rem, int has_rem,
     float* __restrict__ j, float a0, float a1, float a2, float a3, float bg_w,
     const uint32_t* __restrict__ poisson, int K, float* __restrict__ ou, float ou_mu, float ou_a, float ou_s,
     int64_t* __restrict__ ev_ring, int32_t* __restrict__ bad) {
-  __shared__ uint32_t s_bg[kSumsThreads / 64];
+  constexpr int kT = kSumsRowsPerBlock / kRows;  // threads per block
+  __shared__ uint32_t s_bg[kT / 64];
   const int64_t t = step[0];
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(step[1]) * kStripes * 2;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int64_t r = int64_t(blockIdx.x) * kSumsThreads + tid;
+  int64_t r[kRows];
+  bool valid[kRows];
+  float dE[kRows], dI[kRows], jv[kRows][4];
+  const Bundle* B[kRows];
+#pragma unroll
+  for (int h = 0; h < kRows; ++h) {
+    r[h] = int64_t(blockIdx.x) * kSumsRowsPerBlock + h * kT + tid;
+    valid[h] = r[h] < n;
+    dE[h] = dI[h] = 0.f;
+    B[h] = nullptr;
+    if (valid[h]) {
+      jv[h][0] = j[r[h]];
+      jv[h][1] = j[n_pad + r[h]];
+      jv[h][2] = j[2 * n_pad + r[h]];
+      jv[h][3] = j[3 * n_pad + r[h]];
+    }
+  }
+  block_rows_sum<kBF16, kRows>(loc, r, valid, dE, dI, B);
+  if (has_rem) {
+    const Bundle* Br[kRows];
+    block_rows_sum<kBF16, kRows>(rem, r, valid, dE, dI, Br);
+  }
   uint32_t evb = 0;
-  if (r < n) {
-    const float j0 = j[r], j1 = j[n_pad + r], j2 = j[2 * n_pad + r], j3 = j[3 * n_pad + r];
-    float dE = 0.f, dI = 0.f;
-    const Bundle* B = block_row_sum<kBF16>(loc, r, dE, dI);
-    if (has_rem) block_row_sum<kBF16>(rem, r, dE, dI);
-    const uint64_t seed = B->seed;
-    const int64_t mrow0 = B->member_row0;
-    const int32_t member = B->member;
+#pragma unroll
+  for (int h = 0; h < kRows; ++h) {
+    if (!valid[h]) continue;
+    const int64_t rr = r[h];
+    const uint64_t seed = B[h]->seed;
+    const int64_t mrow0 = B[h]->member_row0;
+    const int32_t member = B[h]->member;
     const uint32_t u = ou ? 0u
-                          : uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - mrow0), uint64_t(member), 0ull,
+                          : uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(rr - mrow0), uint64_t(member), 0ull,
                                                        seed, 0ull));
     const int c = poisson_count(u, poisson, K);
-    evb = uint32_t(c);
-    dE = __fmaf_rn(float(c), bg_w, dE);
-    const float ja = __fmaf_rn(a0, j0, dE);
-    const float jb = __fmaf_rn(a1, j1, dE);
-    const float jc = __fmaf_rn(a2, j2, dI);
-    const float jd = __fmaf_rn(a3, j3, dI);
-    j[r] = ja;
-    j[n_pad + r] = jb;
-    j[2 * n_pad + r] = jc;
-    j[3 * n_pad + r] = jd;
+    evb += uint32_t(c);
+    const float de = __fmaf_rn(float(c), bg_w, dE[h]);
+    const float ja = __fmaf_rn(a0, jv[h][0], de);
+    const float jb = __fmaf_rn(a1, jv[h][1], de);
+    const float jc = __fmaf_rn(a2, jv[h][2], dI[h]);
+    const float jd = __fmaf_rn(a3, jv[h][3], dI[h]);
+    j[rr] = ja;
+    j[n_pad + rr] = jb;
+    j[2 * n_pad + rr] = jc;
+    j[3 * n_pad + rr] = jd;
     if (!(isfinite(ja) && isfinite(jb) && isfinite(jc) && isfinite(jd))) atomicOr(bad, 1);
     if (ou) {
       // I_ou <- mu + a (I_ou - mu) + s xi, xi by Box-Muller on Philox stream 1
       uint64_t w1 = 0;
-      const uint32_t h0 = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(r - mrow0), uint64_t(member), 1ull,
+      const uint32_t h0 = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(rr - mrow0), uint64_t(member), 1ull,
                                                      seed, 0ull, &w1));
       const uint32_t h1 = uint32_t(w1 >> 32);
       // the draw in FP64 (u1, u2 exact), rounded once: a float u1 cannot
@@ -628,9 +695,9 @@ __global__ __launch_bounds__(kSumsThreads) void k_sums(
       const double u1 = (double(h0) + 1.0) * 2.3283064365386962890625e-10;  // (0, 1]
       const double u2 = double(h1) * 2.3283064365386962890625e-10;          // [0, 1)
       const float xi = float(sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2));
-      const float x = ou[r];
-      const float y = __fmaf_rn(ou_s, xi, __fmaf_rn(ou_a, x - ou_mu, ou_mu));
-      ou[r] = y;
+      const float xo = ou[rr];
+      const float y = __fmaf_rn(ou_s, xi, __fmaf_rn(ou_a, xo - ou_mu, ou_mu));
+      ou[rr] = y;
       if (!isfinite(y)) atomicOr(bad, 1);
     }
   }
@@ -641,7 +708,7 @@ __global__ __launch_bounds__(kSumsThreads) void k_sums(
   __syncthreads();
   if (tid == 0) {
     int64_t tot = 0;
-    for (int q = 0; q < kSumsThreads / 64; ++q) tot += s_bg[q];
+    for (int q = 0; q < kT / 64; ++q) tot += s_bg[q];
     int64_t* dst = ev_slot + 2 * (blockIdx.x & (kStripes - 1)) + 1;
     if (tot) atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)tot);
   }
@@ -779,16 +846,17 @@ hipError_t gather_set_lds_limit() {
 }
 
 hipError_t launch_sums(const DeviceNet& d, hipStream_t s) {
-  const unsigned grid = unsigned((d.n + kSumsThreads - 1) / kSumsThreads);
+  const unsigned grid = unsigned((d.n + kSumsRowsPerBlock - 1) / kSumsRowsPerBlock);
+  constexpr int kT = kSumsRowsPerBlock / kSumsRows;
   const SumBlock loc{d.loc.bundles, d.loc.block_bundle, d.loc.row_ptr, d.loc.wts, d.loc.hitbuf};
   const SumBlock rem{d.rem.bundles, d.rem.block_bundle, d.rem.row_ptr, d.rem.wts, d.rem.hitbuf};
   const int has_rem = d.rem.n_bundles > 0 ? 1 : 0;
   if (d.wtype == DTB_W_BF16)
-    hipLaunchKernelGGL(k_sums<true>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
+    hipLaunchKernelGGL((k_sums<true, kSumsRows>), dim3(grid), dim3(kT), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
                        d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
                        d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
   else
-    hipLaunchKernelGGL(k_sums<false>, dim3(grid), dim3(kSumsThreads), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
+    hipLaunchKernelGGL((k_sums<false, kSumsRows>), dim3(grid), dim3(kT), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
                        d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
                        d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
   return hipGetLastError();
