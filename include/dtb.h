@@ -362,7 +362,8 @@ dtb_status dtb_enkf_analysis(int32_t n_members, int32_t n_params, int32_t n_obs,
  * Start: init int32 [n_vert] if given, else the greedy fill (one GPU at a
  * time, the unassigned vertex most connected to it, up to an even share of
  * the total size); then up to refine_rounds single-vertex moves into or out
- * of the most loaded GPU, each lowering F (refine_rounds = 0 evaluates the
+ * of the most loaded GPU, or swaps with its strongest senders, each lowering
+ * F (refine_rounds = 0 evaluates the
  * start).  Outputs: part int32 [n_vert], *F_out, D_out double
  * [n_gpu][n_gpu] (diagonal 0; either may be NULL).  Cost: the greedy fill
  * scans the unassigned vertices for every placement (O(n_vert^2)) and each

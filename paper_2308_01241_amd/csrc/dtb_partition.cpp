@@ -14,8 +14,9 @@
 //
 // Method: the paper's greedy assignment (fill one GPU at a time with the
 // unassigned vertex most strongly connected to it, up to an even share of
-// the total size), then a local search that moves single vertices into or
-// out of the GPU receiving the most traffic while that lowers F.
+// the total size), then a local search on the GPU receiving the most
+// traffic - single vertices moved into or out of it, or swapped with a
+// strong sender - while that lowers F.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -253,6 +254,26 @@ extern "C" dtb_status dtb_partition(int64_t n_vert, const double* size, const do
     for (int64_t u = 0; u < n_vert && !improved; ++u) {
       if (P.part[u] != js) continue;
       for (int32_t g = 0; g < n_gpu && !improved; ++g) improved = try_move(u, g);
+    }
+    // then swaps of a vertex on js with one of the strongest senders to js,
+    // which keep both GPUs within the capacity when single moves cannot
+    for (int64_t u = 0; u < n_vert && !improved; ++u) {
+      if (P.part[u] != js) continue;
+      for (size_t q = 0; q < cand.size() && q < 64 && !improved; ++q) {
+        const int64_t v = cand[q].second;
+        const int32_t g = P.part[v];
+        if (g == js || P.load[js] - size[u] + size[v] > capacity || P.load[g] - size[v] + size[u] > capacity)
+          continue;
+        P.move(u, g);
+        P.move(v, js);
+        const double f1 = P.F();
+        if (f1 < f0 * (1.0 - 1e-12) || (f1 <= f0 && P.total() < t0 * (1.0 - 1e-12))) {
+          improved = true;
+        } else {
+          P.move(v, g);
+          P.move(u, js);
+        }
+      }
     }
     if (!improved) break;
     if ((round & 63) == 63) P.recompute();  // drop accumulated rounding of the incremental updates
