@@ -363,12 +363,11 @@ dtb_status dtb_enkf_analysis(int32_t n_members, int32_t n_params, int32_t n_obs,
  * time, the unassigned vertex most connected to it, up to an even share of
  * the total size); then up to refine_rounds single-vertex moves into or out
  * of the most loaded GPU, or swaps with its strongest senders, each lowering
- * F (refine_rounds = 0 evaluates the
- * start).  Outputs: part int32 [n_vert], *F_out, D_out double
- * [n_gpu][n_gpu] (diagonal 0; either may be NULL).  Cost: the greedy fill
- * scans the unassigned vertices for every placement (O(n_vert^2)) and each
- * move re-evaluates F (O(n_gpu^2)); meant for up to ~10^4 vertices (1,319
- * vertices on 64 GPUs take 0.12 s).  Errors: DTB_ERR_INVALID
+ * F (refine_rounds = 0 evaluates the start).  Outputs: part int32 [n_vert],
+ * *F_out, D_out double [n_gpu][n_gpu] (diagonal 0; either may be NULL).
+ * Cost: the greedy fill scans the unassigned vertices for every placement
+ * (O(n_vert^2)) and each move re-evaluates F (O(n_gpu^2)); meant for up to
+ * ~10^4 vertices (1,319 vertices on 64 GPUs take 0.3 s).  Errors: DTB_ERR_INVALID
  * (bad arrays, an init beyond the capacity), DTB_ERR_UNSUPPORTED (a vertex
  * or the total beyond the capacity, n_vert n_gpu > 2^28). */
 dtb_status dtb_partition(int64_t n_vert, const double* size, const double* neurons, const double* spikes,
