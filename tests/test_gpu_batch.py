@@ -53,6 +53,27 @@ def test_batch_equals_members_run_alone(dtb):
         np.testing.assert_array_equal(b.region_counts(0, 300)[:, r0:r1], g.region_counts(0, 300))
 
 
+def test_batch_equals_members_run_alone_with_ou_background(dtb):
+    """The OU background draws are keyed by (step, neuron inside the member,
+    member): a member in a batch gets the same I_ou sequence, hence the same
+    raster, as alone, under graph replay too."""
+    sizes = [2500, 3300]
+    mem = _members(sizes)
+    b = dtb.Net.batch(mem, record_steps=200, stream=_stream())
+    b.set_background_ou(0.6, 0.4, 8.0)
+    b.run(200)
+    ras = b.raster(0, 200)
+    ou_b = b.state("I_ou")
+    assert ras.sum() > 0
+    for m, nw in enumerate(mem):
+        g = dtb.Net(nw, record_steps=200, stream=_stream())
+        g.set_background_ou(0.6, 0.4, 8.0)
+        g.step(200)
+        lo, hi = b.neuron_offset[m], b.neuron_offset[m + 1]
+        np.testing.assert_array_equal(ras[:, lo:hi], g.raster(0, 200))
+        np.testing.assert_array_equal(ou_b[lo:hi], g.state("I_ou"))
+
+
 def test_batch_member_with_gains_matches_reference(dtb):
     mem = _members([2000, 2600])
     gains = netgen.ensemble_gains(2, 4, seed=9)
