@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 8
+#define DTB_ABI_VERSION 9
 
 typedef enum {
   DTB_OK = 0,
@@ -209,10 +209,15 @@ dtb_status dtb_push_remote_spikes(dtb_net* net, const uint32_t* bits, int32_t n_
 dtb_status dtb_read_spikes(dtb_net* net, int64_t t0, int64_t t1, uint32_t* dst,
                            int dst_on_device);
 
-/* Ascending ids of the neurons that spiked in the most recent step (the
- * compacted spike list that a partition would send, Sec. V-B), at most cap
- * of them into ids; *count receives the total (may exceed cap). Host dst. */
-dtb_status dtb_read_spike_ids(dtb_net* net, int32_t* ids, int64_t cap, int64_t* count);
+/* Ascending ids of the neurons that spiked in step t (the compacted spike
+ * list that a partition sends after collecting its spikes, Sec. V-B), at
+ * most cap of them into ids (host, int32); *count receives the total (may
+ * exceed cap).  t must lie in the recorded window (now - record_steps <= t
+ * < now, DTB_ERR_INVALID otherwise).  The list of the most recent step is
+ * the one the step built; an earlier step's list is rebuilt from that
+ * step's spike bitmap by the same compaction kernel.  Synchronizes the
+ * stream. */
+dtb_status dtb_read_spike_ids(dtb_net* net, int64_t t, int32_t* ids, int64_t cap, int64_t* count);
 
 /* Current value of one state field for all n neurons (float32 [n]). */
 dtb_status dtb_read_state(dtb_net* net, int32_t field, float* dst, int dst_on_device);
@@ -280,6 +285,41 @@ dtb_status dtb_set_gains(dtb_net* net, const float* gains, int src_on_device);
  * call with a given n_steps, replayed afterwards); same results as
  * dtb_step(n_steps).  Not available while teacher forcing is pending. */
 dtb_status dtb_run(dtb_net* net, int32_t n_steps);
+
+/* Launch-shape autotuner for the batched ensemble and the plain partition
+ * (the block and tile shapes of the gather, chosen by timing them on the
+ * real network): builds the network of `members` (n_members == 1: a plain
+ * partition, else a batch as dtb_create_batch) once per candidate bundle
+ * size (gather_bundle_syn; bundle_cands [n_cands], each in [4096, 2^20-1],
+ * or n_cands = 0 for the library's list: the largest bundle and the sizes
+ * whose bundle count fills whole rounds of the GPU's compute units), times
+ * `steps` steps with hipEvents for each lookup-tiles-per-round value 1..3
+ * (gather_unroll), and reports the fastest.  Every timing starts from the
+ * same state - the first candidate's state after `burnin` steps, saved once
+ * and loaded before each timing - so all candidates time the same steps
+ * (the shapes change only the schedule, never a result).  The members'
+ * own gather_bundle_syn / gather_unroll are ignored.
+ * cache_path (may be NULL): a JSON file of tuned shapes keyed by
+ * "<gfx arch>|n=..,nnz=..,members=..,w=<f32|bf16>,D=..", one entry per line;
+ * a key already present is returned without timing (from_cache = 1),
+ * otherwise the winner is added (the file is rewritten through a temporary
+ * file; DTB_ERR_INVALID if it cannot be written).  Work runs on hip_stream
+ * (NULL: a private stream per candidate); the call blocks until it is done.
+ * Errors: DTB_ERR_INVALID (arguments, see above), and whatever creating or
+ * stepping the candidate networks returns. */
+#define DTB_TUNE_MAX_BUNDLES 8
+typedef struct dtb_tune_result {
+  int32_t bundle_syn, unroll;   /* the fastest shape */
+  float ms_per_step;            /* its time per step (from the cache when from_cache) */
+  int32_t from_cache;           /* 1: taken from cache_path without timing */
+  int32_t n_tried;              /* shapes timed: candidates x 3 */
+  int32_t tried_bundle[3 * DTB_TUNE_MAX_BUNDLES];
+  int32_t tried_unroll[3 * DTB_TUNE_MAX_BUNDLES];
+  float tried_ms[3 * DTB_TUNE_MAX_BUNDLES];
+} dtb_tune_result;
+dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_stream, const char* cache_path,
+                        const int32_t* bundle_cands, int32_t n_cands, int32_t burnin, int32_t steps,
+                        dtb_tune_result* out);
 
 /* Balloon-Windkessel BOLD signal per population after the last step (the
  * hemodynamic readout of Sec. V-E, integrated with the population rates of

@@ -207,27 +207,73 @@ def make_remote_block(n: int, n_remote: int, k_remote, max_delay: int = 5, w_mu:
     return RemoteBlock(n_remote=int(n_remote), row_ptr=row_ptr, col=col, w=w, delay=delay, is_inh=is_inh)
 
 
-def split_remote(net: Network, k_local: int):
-    """Cut every row of a fixed in-degree network after its first k_local
-    in-edges: the network keeps those (the generator puts the own-region
-    sources first), the rest become a remote block whose sources are the
-    same neuron ids held by a mirror partition.  Replaying the network's
-    own raster as the remote spikes then reproduces the unsplit run."""
+def split_remote(net: Network):
+    """Split every row into its own-region in-edges (kept by the partition:
+    J_intra) and its cross-region ones (a remote block: J_inter), the split
+    of Sec. V-B when a partition holds whole regions.  The remote sources are
+    the same neuron ids held by a mirror partition, so replaying the
+    network's own raster as the remote spikes reproduces the unsplit run.
+    The generator emits each row's own-region sources first, so the split is
+    a prefix / suffix of every row and keeps the row's summation order; a
+    network whose rows are not in that order is rejected."""
     n = net.n
-    K = int(net.row_ptr[1] - net.row_ptr[0]) if n else 0
-    if not np.array_equal(net.row_ptr, np.arange(n + 1, dtype=np.int64) * K) or not 0 <= k_local <= K:
-        raise ValueError("split_remote needs a fixed in-degree >= k_local")
-    kr = K - k_local
-
-    def cut(a, lo, hi):
-        return np.ascontiguousarray(a.reshape(n, K)[:, lo:hi]).reshape(-1)
-
-    local = dataclasses.replace(net, row_ptr=np.arange(n + 1, dtype=np.int64) * k_local,
-                                col=cut(net.col, 0, k_local), w=cut(net.w, 0, k_local),
-                                delay=cut(net.delay, 0, k_local))
-    blk = RemoteBlock(n_remote=n, row_ptr=np.arange(n + 1, dtype=np.int64) * kr, col=cut(net.col, k_local, K),
-                      w=cut(net.w, k_local, K), delay=cut(net.delay, k_local, K), is_inh=net.is_inh.copy())
+    rp = np.asarray(net.row_ptr, dtype=np.int64)
+    row_of = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    own = net.region[net.col] == net.region[row_of]
+    n_own = np.bincount(row_of, weights=own, minlength=n).astype(np.int64)
+    # own-region entries must be each row's prefix
+    pos = np.arange(net.nnz, dtype=np.int64) - rp[row_of]
+    if not np.array_equal(own, pos < n_own[row_of]):
+        raise ValueError("split_remote needs rows with their own-region sources first")
+    del row_of, pos
+    lrp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(n_own, out=lrp[1:])
+    rrp = rp - lrp
+    local = dataclasses.replace(net, row_ptr=lrp, col=net.col[own], w=net.w[own], delay=net.delay[own])
+    cross = ~own
+    del own
+    blk = RemoteBlock(n_remote=n, row_ptr=rrp, col=net.col[cross], w=net.w[cross], delay=net.delay[cross],
+                      is_inh=net.is_inh.copy())
     return local, blk
+
+
+def embed_independent(sub: Network, rest: Network, name: str = "") -> Network:
+    """One partition holding `sub` as an independent subgraph - no synapse
+    into or out of it - in its first sub.n neurons, followed by `rest` with
+    its ids and populations shifted behind it (the accuracy check of
+    Sec. VII-B embeds such a subgraph in a large network).  The background
+    seed is sub's and neuron ids are unchanged for sub, so its neurons draw
+    exactly the background they draw alone; sub's populations keep their
+    ids.  Both parts must share the model constants and the drive."""
+    for f in ("dt_ms", "bg_lambda", "bg_w"):
+        if getattr(sub, f) != getattr(rest, f):
+            raise ValueError(f"embed_independent: {f} differs")
+    if not (np.array_equal(sub.E, rest.E) and np.array_equal(sub.tau_ms, rest.tau_ms)
+            and np.array_equal(sub.ptypes, rest.ptypes)):
+        raise ValueError("embed_independent: model constants differ")
+    n, nnz = sub.n + rest.n, sub.nnz + rest.nnz
+    row_ptr = np.empty(n + 1, dtype=np.int64)
+    row_ptr[:sub.n + 1] = sub.row_ptr
+    np.add(rest.row_ptr[1:], sub.nnz, out=row_ptr[sub.n + 1:])
+    col = np.empty(nnz, dtype=np.int32)
+    col[:sub.nnz] = sub.col
+    np.add(rest.col, np.int32(sub.n), out=col[sub.nnz:])
+    w = np.empty(nnz, dtype=np.float32)
+    w[:sub.nnz] = sub.w
+    w[sub.nnz:] = rest.w
+    delay = np.empty(nnz, dtype=np.uint8)
+    delay[:sub.nnz] = sub.delay
+    delay[sub.nnz:] = rest.delay
+    start = None
+    if sub.region_start is not None and rest.region_start is not None:
+        start = np.concatenate([sub.region_start, rest.region_start[1:] + sub.n])
+    return Network(n=n, n_regions=sub.n_regions + rest.n_regions, max_delay=max(sub.max_delay, rest.max_delay),
+                   row_ptr=row_ptr, col=col, w=w, delay=delay, is_inh=np.concatenate([sub.is_inh, rest.is_inh]),
+                   region=np.concatenate([sub.region, rest.region + sub.n_regions]).astype(np.int32),
+                   ptype=np.concatenate([sub.ptype, rest.ptype]), ptypes=sub.ptypes,
+                   V0=np.concatenate([sub.V0, rest.V0]), E=sub.E, tau_ms=sub.tau_ms, dt_ms=sub.dt_ms,
+                   bg_lambda=sub.bg_lambda, bg_w=sub.bg_w, seed=sub.seed, member=sub.member,
+                   region_start=start, name=name or f"embedded({sub.name} in {rest.name})")
 
 
 def remote_raster(n_steps: int, n_remote: int, rate_hz: float, dt_ms: float = 1.0, seed: int = 12) -> np.ndarray:

@@ -7,7 +7,10 @@
  * first picking a source region s != t with probability proportional to the
  * region-connection weight M[s -> t] and then a neuron uniformly in s.
  * Integer delays are uniform on [1, max_delay] and weights log-normal.
- * Each row is returned sorted by (source id, delay, draw index).
+ * Each row is returned with its own-region sources first, then its
+ * cross-region ones, each part sorted by (source id, delay, draw index): the
+ * own-region part is the row's J_intra share when a partition holds whole
+ * regions, the cross-region part what other partitions would send.
  *
  * The random numbers come from a counter-based hash (SplitMix64 finaliser,
  * Steele, Lea & Flood, OOPSLA 2014) keyed by (seed, stream, neuron, draw), so
@@ -128,12 +131,13 @@ int netgen_fill(int64_t n, int32_t n_regions, const int64_t* region_start,
         double u2 = (double)((hw >> 16) & 0xFFFFFF) * (1.0 / 16777216.0);
         double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
         ws[k] = (float)exp(w_mu + w_sigma * z);
-        keys[k] = ((uint64_t)src << 24) | (d << 16) | (uint64_t)k;
+        const uint64_t cross = (src < t0 || src >= t0 + tn) ? 1ull : 0ull;
+        keys[k] = (cross << 62) | ((uint64_t)src << 24) | (d << 16) | (uint64_t)k;
       }
       sort_keys(keys, ws, K);
       const int64_t base = i * (int64_t)K;
       for (int k = 0; k < K; k++) {
-        col[base + k] = (int32_t)(keys[k] >> 24);
+        col[base + k] = (int32_t)((keys[k] & ~(1ull << 62)) >> 24);
         delay[base + k] = (uint8_t)((keys[k] >> 16) & 0xFF);
         w[base + k] = ws[k];
       }

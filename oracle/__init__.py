@@ -235,7 +235,10 @@ class OracleNet:
         self._lib.ora_set_gain(self._h, _p(g))
 
     def step(self, forced=None, rows=None, want_margin=False):
-        """Advance one step.  Returns dict(spikes, margin, counts, ev_rec, ev_bg)."""
+        """Advance one step.  Returns dict(spikes, margin, own, counts, ev_rec,
+        ev_bg): with want_margin, margin = |V~ - V_th| of every non-refractory
+        neuron (NaN for refractory ones) and own = the threshold test's own
+        decision V~ >= V_th (also when the step is forced)."""
         n = self.net.n
         spikes = np.zeros(n, dtype=np.uint8)
         margin = np.full(n, np.nan) if want_margin else None
@@ -250,7 +253,11 @@ class OracleNet:
             raise ValueError("oracle step: the remote spikes of this step were not given")
         if rc != 0:
             raise ValueError("oracle step: a row subset needs a forced raster")
-        return {"spikes": spikes, "margin": margin, "counts": counts,
+        own = None
+        if want_margin:
+            own = (margin >= 0.0).astype(np.uint8)  # NaN (refractory) compares False
+            margin = np.abs(margin)
+        return {"spikes": spikes, "margin": margin, "own": own, "counts": counts,
                 "ev_rec": int(er.value), "ev_bg": int(eb.value)}
 
     def get(self, field: str) -> np.ndarray:

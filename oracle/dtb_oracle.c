@@ -305,8 +305,9 @@ int ora_set_gain(ora_net* h, const double* gain) {
  * threshold test (teacher forcing: the forced bit decides spike, reset and
  * ring entry).  rows/n_rows: optional subset of neurons whose state is
  * advanced (requires forced, since the spikes of the others are unknown).
- * Outputs (each optional): spikes [n], margin [n] = |Vt - Vth| for
- * non-refractory neurons (NAN otherwise), region_counts [n_regions],
+ * Outputs (each optional): spikes [n], margin [n] = Vt - Vth for
+ * non-refractory neurons (signed: >= 0 is the threshold test's own spike,
+ * also when forced; NAN for refractory ones), region_counts [n_regions],
  * ev_rec / ev_bg (delivered recurrent / background events of the rows).
  */
 int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_rows,
@@ -343,7 +344,7 @@ int ora_step(ora_net* h, const uint8_t* forced, const int64_t* rows, int64_t n_r
     if (s) { h->V[i] = h->Vreset[p]; h->ref[i] = h->nref[p]; }
     else if (r > 0) { h->V[i] = h->Vreset[p]; h->ref[i] = r - 1; }
     else { h->V[i] = Vt; h->ref[i] = 0; }
-    if (margin) margin[i] = (r <= 0) ? fabs(Vt - h->Vth[p]) : NAN;
+    if (margin) margin[i] = (r <= 0) ? Vt - h->Vth[p] : NAN;
     if (!forced) slot_now[i] = (uint8_t)s;
   }
   /* 2. spikes of this step into the ring (teacher forcing: the given raster) */

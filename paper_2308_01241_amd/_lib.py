@@ -40,6 +40,17 @@ class Desc(ctypes.Structure):
                 ("gather_unroll", ctypes.c_int32)]
 
 
+TUNE_MAX_BUNDLES = 8
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("bundle_syn", ctypes.c_int32), ("unroll", ctypes.c_int32), ("ms_per_step", ctypes.c_float),
+                ("from_cache", ctypes.c_int32), ("n_tried", ctypes.c_int32),
+                ("tried_bundle", ctypes.c_int32 * (3 * TUNE_MAX_BUNDLES)),
+                ("tried_unroll", ctypes.c_int32 * (3 * TUNE_MAX_BUNDLES)),
+                ("tried_ms", ctypes.c_float * (3 * TUNE_MAX_BUNDLES))]
+
+
 # every symbol include/dtb.h declares, with its ctypes signature
 _P = ctypes.c_void_p
 _I32, _I64 = ctypes.c_int32, ctypes.c_int64
@@ -49,6 +60,8 @@ SIGNATURES = {
     "dtb_bitmap_words": ([_I64], _I64),
     "dtb_create": ([ctypes.POINTER(Desc), _P, ctypes.POINTER(_P)], ctypes.c_int),
     "dtb_step": ([_P, _I32], ctypes.c_int),
+    "dtb_autotune": ([_P, _I32, _P, ctypes.c_char_p, _P, _I32, _I32, _I32, ctypes.POINTER(TuneResult)],
+                     ctypes.c_int),
     "dtb_reset": ([_P], ctypes.c_int),
     "dtb_set_background": ([_P, ctypes.c_double, ctypes.c_float], ctypes.c_int),
     "dtb_set_background_ou": ([_P, ctypes.c_float, ctypes.c_float, ctypes.c_float], ctypes.c_int),
@@ -62,7 +75,7 @@ SIGNATURES = {
     "dtb_enkf_analysis": ([_I32, _I32, _I32, _P, _P, _P, _P, ctypes.c_float, ctypes.c_uint64, ctypes.c_int64,
                            ctypes.c_float, ctypes.c_float, _P], ctypes.c_int),
     "dtb_read_spikes": ([_P, _I64, _I64, _P, ctypes.c_int], ctypes.c_int),
-    "dtb_read_spike_ids": ([_P, _P, _I64, ctypes.POINTER(_I64)], ctypes.c_int),
+    "dtb_read_spike_ids": ([_P, _I64, _P, _I64, ctypes.POINTER(_I64)], ctypes.c_int),
     "dtb_read_state": ([_P, _I32, _P, ctypes.c_int], ctypes.c_int),
     "dtb_read_region_counts": ([_P, _I64, _I64, _P], ctypes.c_int),
     "dtb_read_region_rates": ([_P, _I64, _I64, _P], ctypes.c_int),
@@ -108,7 +121,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 8:
+    if lib.dtb_abi_version() != 9:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

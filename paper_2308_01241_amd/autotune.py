@@ -1,4 +1,4 @@
-"""Autotuner for the gather's launch shape.
+"""Launch-shape autotuner of the gather (binding of dtb_autotune).
 
 Two knobs, neither of which changes any result (the summation order is each
 row's CSR order either way):
@@ -9,52 +9,37 @@ row's CSR order either way):
   once per delay); sizes that make the bundle count a whole number of
   rounds over the CUs avoid a partly idle last round;
 * the lookup tiles per wavefront per round (1, 2 or 3): bytes in flight per
-  wavefront against registers (one tile per round fits 64 VGPRs, i.e. two
-  1024-thread workgroups per CU).
+  wavefront against registers.
 
-The tuner times each candidate on the real network with HIP events and
-caches the winner in JSON, keyed by GPU architecture and network shape.
-`tuned.json` next to this file holds the entries measured for the shipped
-workloads; `lookup` reads it (or another cache file).
+The library times each candidate on the real network with HIP events, all
+from one burned-in state, and caches the winner in a JSON file keyed by GPU
+architecture and network shape.  `tuned.json` next to this file holds the
+entries measured for the shipped workloads; `lookup` reads it.
 """
 from __future__ import annotations
 
+import ctypes
 import json
 import os
-import time
+
+import numpy as np
+
+from ._lib import TUNE_MAX_BUNDLES, Desc, TuneResult, check, load
+from .net import _make_desc, _ptr, _stream_handle
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
-BUNDLES = (393_216, 640_000, (1 << 20) - 1)
-UNROLLS = (1, 2, 3)
 
 
-def aligned_bundle_sizes(n: int, nnz: int, n_cu: int, max_syn: int = (1 << 20) - 1, counts=(1, 2)):
-    """Bundle sizes whose bundle count is a whole number of rounds over the
-    CUs (one workgroup per CU at a time): for the smallest k rounds that
-    respect max_syn and the next count - 1 after it, the size that cuts the
-    rows (mean length nnz / n) into at most k * n_cu bundles."""
-    if n <= 0 or nnz <= 0:
-        return ()
-    L = nnz / n
-    k = max(1, -(-nnz // (max_syn * n_cu)))
-    out = []
-    for kk in range(k, k + len(counts)):
-        rows = -(-n // (kk * n_cu))
-        b = int(rows * L + 0.5)
-        if b <= max_syn:
-            out.append(b)
-    return tuple(out)
+def shape_key(arch: str, n: int, nnz: int, n_members: int, wtype: str, max_delay: int) -> str:
+    """The cache key dtb_autotune writes."""
+    return f"{arch}|n={n},nnz={nnz},members={n_members},w={wtype},D={max_delay}"
 
 
 def _arch() -> str:
     import torch
     p = torch.cuda.get_device_properties(0)
     return getattr(p, "gcnArchName", p.name).split(":")[0]
-
-
-def shape_key(n: int, nnz: int, n_members: int, wtype: str, max_delay: int) -> str:
-    return f"n={n},nnz={nnz},members={n_members},w={wtype},D={max_delay}"
 
 
 def lookup(n, nnz, n_members=1, wtype="f32", max_delay=20, path=CACHE, arch=None):
@@ -64,42 +49,32 @@ def lookup(n, nnz, n_members=1, wtype="f32", max_delay=20, path=CACHE, arch=None
             db = json.load(f)
     except (OSError, ValueError):
         return 0, 0
-    arch = arch or _arch()
-    ent = db.get(arch, {}).get(shape_key(n, nnz, n_members, wtype, max_delay))
-    return (int(ent["bundle_syn"]), int(ent.get("unroll", 0))) if ent else (0, 0)
+    ent = db.get(shape_key(arch or _arch(), n, nnz, n_members, wtype, max_delay))
+    return (int(ent["bundle_syn"]), int(ent["unroll"])) if ent else (0, 0)
 
 
-def tune(make_net, key: str, bundles=BUNDLES, unrolls=UNROLLS, steps: int = 40, warmup: int = 10, path=CACHE,
-         log=print):
-    """make_net(bundle_syn, unroll) -> Net.  Times `steps` steps per
-    candidate and records the fastest under (arch, key) in `path`."""
-    import torch
-    res = {}
-    for b in bundles:
-        for u in unrolls:
-            t0 = time.time()
-            net = make_net(b, u)
-            net.step(warmup)
-            net.sync()
-            a = torch.cuda.Event(enable_timing=True)
-            e = torch.cuda.Event(enable_timing=True)
-            a.record()
-            net.step(steps)
-            e.record()
-            torch.cuda.synchronize()
-            res[(b, u)] = a.elapsed_time(e) / steps
-            net.close()
-            log(f"[autotune] bundle_syn={b} unroll={u}: {res[(b, u)]:.3f} ms/step "
-                f"(built and timed in {time.time() - t0:.1f}s)")
-    best = min(res, key=res.get)
-    arch = _arch()
-    try:
-        with open(path) as f:
-            db = json.load(f)
-    except (OSError, ValueError):
-        db = {}
-    db.setdefault(arch, {})[key] = {"bundle_syn": int(best[0]), "unroll": int(best[1]),
-                                    "ms_per_step": {f"{b}/{u}": v for (b, u), v in res.items()}}
-    with open(path, "w") as f:
-        json.dump(db, f, indent=1, sort_keys=True)
-    return best, res
+def tune(members, wtype: str = "f32", record_steps: int = 64, cache_path=CACHE, bundles=(), burnin: int = 0,
+         steps: int = 20, stream=None) -> dict:
+    """dtb_autotune over the network(s) `members` (one: a plain partition,
+    several: a batch).  Returns the winning shape, its ms per step, whether
+    it came from the cache, and every timed (bundle_syn, unroll) -> ms."""
+    lib = load()
+    members = list(members)
+    descs = (Desc * len(members))()
+    keep = []
+    for m, nw in enumerate(members):
+        d, k = _make_desc(nw, wtype, record_steps)
+        descs[m] = d
+        keep.append(k)
+    cands = np.ascontiguousarray(bundles, dtype=np.int32)
+    if cands.size > TUNE_MAX_BUNDLES:
+        raise ValueError(f"at most {TUNE_MAX_BUNDLES} bundle candidates")
+    res = TuneResult()
+    check(lib.dtb_autotune(descs, len(members), _stream_handle(stream),
+                           None if cache_path is None else str(cache_path).encode(),
+                           _ptr(cands) if cands.size else None, int(cands.size), int(burnin), int(steps),
+                           ctypes.byref(res)))
+    del keep
+    tried = {(int(res.tried_bundle[q]), int(res.tried_unroll[q])): float(res.tried_ms[q]) for q in range(res.n_tried)}
+    return {"bundle_syn": int(res.bundle_syn), "unroll": int(res.unroll), "ms_per_step": float(res.ms_per_step),
+            "from_cache": bool(res.from_cache), "tried": tried}

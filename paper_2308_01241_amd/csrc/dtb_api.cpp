@@ -8,7 +8,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <functional>
+#include <map>
+#include <sstream>
 #include <string>
 #include <thread>
 #include <vector>
@@ -132,6 +135,7 @@ struct dtb_net {
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int64_t rq_head = 0;     // queue row of the first pending remote step
   int64_t rq_pending = 0;  // remote steps pushed and not yet consumed
+  uint32_t read_epoch = 0; // spike-list rebuilds so far (their look-back epochs)
 };
 
 namespace {
@@ -581,7 +585,10 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
       (st = dalloc(net, &d.cticket, 1)) || (st = dalloc(net, &d.force, (d.rec + 1) * d.words_pad)) ||
       (st = dalloc(net, &d.bad, 1)) || (st = dalloc(net, &d.step, 2)) ||
       (st = dalloc(net, &d.inv_nr_dt, d.n_regions)) || (st = dalloc(net, &d.bold, 4 * d.n_regions)) ||
-      (st = dalloc(net, &d.bold_y, d.n_regions))) {
+      (st = dalloc(net, &d.bold_y, d.n_regions)) || (st = dalloc(net, &d.rd_at, 2)) ||
+      (st = dalloc(net, &d.rd_ids, d.n_pad)) || (st = dalloc(net, &d.rd_count, 1)) ||
+      (st = dalloc(net, &d.rd_status, d.compact_blocks)) || (st = dalloc(net, &d.rd_ticket, 1)) ||
+      (st = dalloc(net, &d.rd_total, 1))) {
     dtb_destroy(net);
     return st;
   }
@@ -593,7 +600,7 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
            {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32}, {d.id_count, 4},
            {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.ptype, d.n_pad * 2},
            {d.region, d.n_pad * 4}, {d.V, d.n_pad * 4}, {d.step, 16}, {d.bold, size_t(d.n_regions) * 16},
-           {d.bold_y, size_t(d.n_regions) * 4}}) {
+           {d.bold_y, size_t(d.n_regions) * 4}, {d.rd_status, d.compact_blocks * 8}, {d.rd_count, 4}}) {
     if (e == hipSuccess) e = zero(pr.first, pr.second);
   }
   if (e != hipSuccess) {
@@ -927,8 +934,8 @@ dtb_status dtb_reset(dtb_net* net) {
 dtb_status dtb_set_background(dtb_net* net, double bg_lambda, float bg_w) {
   dtb_status st = check_net(net);
   if (st) return st;
-  drop_graph(net);
-  net->d.ou_on = 0;
+  // validate and build the table before touching the handle: a rejected
+  // call leaves the drive as it was
   if (!(bg_lambda >= 0.0) || !(bg_lambda <= 400.0)) return fail(DTB_ERR_INVALID, "bg_lambda must be in [0, 400]");
   if (!(bg_w >= 0.f) || !finite_f(bg_w)) return fail(DTB_ERR_INVALID, "bg_w must be finite and >= 0");
   std::vector<uint32_t> T(kMaxPoisson);
@@ -941,7 +948,10 @@ dtb_status dtb_set_background(dtb_net* net, double bg_lambda, float bg_w) {
     d.poisson = q;
     d.poisson_cap = K;
   }
+  // the table is read by kernels already queued: replace it in stream order
   if (K > 0 && (st = upload(net, d.poisson, T.data(), size_t(K) * 4))) return st;
+  drop_graph(net);
+  d.ou_on = 0;
   d.poisson_K = K;
   d.bg_w = bg_w;
   return DTB_OK;
@@ -1091,28 +1101,63 @@ static dtb_status copy_out(dtb_net* net, void* dst, const void* src, size_t byte
   return DTB_OK;
 }
 
+// Rows t0 .. t1-1 of a per-step ring (row of step t at slot t mod slots,
+// src_pitch bytes apart, `width` bytes each) into dst rows dst_pitch bytes
+// apart: at most two strided copies (the window wraps the ring at most once).
+static dtb_status copy_ring_window(dtb_net* net, void* dst, size_t dst_pitch, const void* ring, size_t src_pitch,
+                                   size_t width, int64_t t0, int64_t t1, int on_device) {
+  const int64_t S = net->d.slots;
+  hipError_t e = hipSuccess;
+  for (int64_t t = t0; t < t1 && e == hipSuccess;) {
+    const int64_t slot = t % S;
+    const int64_t rows = std::min<int64_t>(t1 - t, S - slot);
+    e = hipMemcpy2DAsync(static_cast<char*>(dst) + size_t(t - t0) * dst_pitch, dst_pitch,
+                         static_cast<const char*>(ring) + size_t(slot) * src_pitch, src_pitch, width, size_t(rows),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, net->stream);
+    t += rows;
+  }
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "hipMemcpy2D read");
+  return DTB_OK;
+}
+
 dtb_status dtb_read_spikes(dtb_net* net, int64_t t0, int64_t t1, uint32_t* dst, int dst_on_device) {
   dtb_status st = check_net(net);
   if (st || (st = window(net, t0, t1))) return st;
   if (!dst && t1 > t0) return fail(DTB_ERR_INVALID, "dst is NULL");
   const DeviceNet& d = net->d;
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t slot = t % d.slots;
-    if ((st = copy_out(net, dst + (t - t0) * d.words, d.raster + slot * d.words_pad, d.words * 4, dst_on_device)))
-      return st;
-  }
-  return DTB_OK;
+  if (t1 == t0 || d.words == 0) return DTB_OK;
+  return copy_ring_window(net, dst, size_t(d.words) * 4, d.raster, size_t(d.words_pad) * 4, size_t(d.words) * 4, t0,
+                          t1, dst_on_device);
 }
 
-dtb_status dtb_read_spike_ids(dtb_net* net, int32_t* ids, int64_t cap, int64_t* count) {
+dtb_status dtb_read_spike_ids(dtb_net* net, int64_t t, int32_t* ids, int64_t cap, int64_t* count) {
   dtb_status st = check_net(net);
   if (st) return st;
   if (!count || cap < 0 || (cap > 0 && !ids)) return fail(DTB_ERR_INVALID, "bad ids / cap / count");
+  if ((st = window(net, t, t + 1))) return st;
+  DeviceNet& d = net->d;
+  const int32_t* src_ids = d.ids;
+  const int32_t* src_count = d.id_count;
+  if (t != net->t - 1) {
+    // an earlier step: rebuild its list from the step's ring slot with the
+    // same compaction kernel, on the read's own look-back words
+    const int64_t at[2] = {net->read_epoch, t % d.slots};
+    hipError_t e = hipMemcpyAsync(d.rd_at, at, sizeof(at), hipMemcpyHostToDevice, net->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d.rd_ticket, 0, 4, net->stream);
+    if (e == hipSuccess)
+      e = launch_compact_read(d, d.rd_at, d.rd_ids, d.rd_count, d.rd_status, d.rd_ticket, d.rd_total, net->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);  // `at` lives until here
+    if (e != hipSuccess) return hip_fail(net, e, "spike-list rebuild");
+    net->read_epoch++;
+    src_ids = d.rd_ids;
+    src_count = d.rd_count;
+  }
   int32_t c = 0;
-  if (net->t > 0 && (st = copy_out(net, &c, net->d.id_count, 4, 0))) return st;
+  if ((st = copy_out(net, &c, src_count, 4, 0))) return st;
   *count = c;
   const int64_t m = std::min<int64_t>(c, cap);
-  if (m > 0 && (st = copy_out(net, ids, net->d.ids, size_t(m) * 4, 0))) return st;
+  if (m > 0 && (st = copy_out(net, ids, src_ids, size_t(m) * 4, 0))) return st;
   return DTB_OK;
 }
 
@@ -1155,12 +1200,9 @@ dtb_status dtb_read_region_counts(dtb_net* net, int64_t t0, int64_t t1, int32_t*
   if (st || (st = window(net, t0, t1))) return st;
   if (!dst && t1 > t0) return fail(DTB_ERR_INVALID, "dst is NULL");
   const DeviceNet& d = net->d;
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t slot = t % d.slots;
-    if ((st = copy_out(net, dst + (t - t0) * d.n_regions, d.counts + slot * d.n_regions, d.n_regions * 4, 0)))
-      return st;
-  }
-  return DTB_OK;
+  if (t1 == t0) return DTB_OK;
+  const size_t row = size_t(d.n_regions) * 4;
+  return copy_ring_window(net, dst, row, d.counts, row, row, t0, t1, 0);
 }
 
 dtb_status dtb_read_region_rates(dtb_net* net, int64_t t0, int64_t t1, float* hz) {
@@ -1183,12 +1225,13 @@ dtb_status dtb_read_step_events(dtb_net* net, int64_t t0, int64_t t1, int64_t* e
   dtb_status st = check_net(net);
   if (st || (st = window(net, t0, t1))) return st;
   const DeviceNet& d = net->d;
-  int64_t v[2];
+  if (t1 == t0) return DTB_OK;
+  // each slot's final totals are its first (rec, bg) pair
+  std::vector<int64_t> v(size_t(t1 - t0) * 2);
+  if ((st = copy_ring_window(net, v.data(), 16, d.ev, size_t(kStripes) * 2 * 8, 16, t0, t1, 0))) return st;
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t slot = t % d.slots;
-    if ((st = copy_out(net, v, d.ev + slot * kStripes * 2, 16, 0))) return st;
-    if (ev_rec) ev_rec[t - t0] = v[0];
-    if (ev_bg) ev_bg[t - t0] = v[1];
+    if (ev_rec) ev_rec[t - t0] = v[2 * (t - t0)];
+    if (ev_bg) ev_bg[t - t0] = v[2 * (t - t0) + 1];
   }
   return DTB_OK;
 }
@@ -1345,6 +1388,179 @@ dtb_status dtb_load(dtb_net* net, const void* host_buf, size_t len) {
   net->force_head = 0;
   net->rq_pending = 0;
   net->rq_head = 0;
+  return DTB_OK;
+}
+
+// ------------------------------------------------------- launch autotuner
+}  // extern "C"
+
+namespace {
+
+struct TuneEntry {
+  int32_t bundle_syn = 0, unroll = 0;
+  double ms = 0.0;
+};
+
+// Cache file: one JSON object, one entry per line,
+//   "<arch>|n=<n>,nnz=<nnz>,members=<m>,w=<f32|bf16>,D=<D>": {"bundle_syn": b, "unroll": u, "ms_per_step": ms}
+// Lines that do not parse are dropped when the file is rewritten.
+std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
+  std::map<std::string, TuneEntry> db;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t a = line.find('"');
+    if (a == std::string::npos) continue;
+    const size_t b = line.find('"', a + 1);
+    if (b == std::string::npos) continue;
+    TuneEntry e;
+    const char* rest = line.c_str() + b + 1;
+    if (std::sscanf(rest, " : {\"bundle_syn\": %d, \"unroll\": %d, \"ms_per_step\": %lf", &e.bundle_syn, &e.unroll,
+                    &e.ms) == 3)
+      db[line.substr(a + 1, b - a - 1)] = e;
+  }
+  return db;
+}
+
+bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& db) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return false;
+    f << "{\n";
+    size_t q = 0;
+    for (const auto& kv : db) {
+      char buf[160];
+      std::snprintf(buf, sizeof(buf), ": {\"bundle_syn\": %d, \"unroll\": %d, \"ms_per_step\": %.6f}",
+                    kv.second.bundle_syn, kv.second.unroll, kv.second.ms);
+      f << "\"" << kv.first << "\"" << buf << (++q < db.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_stream, const char* cache_path,
+                        const int32_t* bundle_cands, int32_t n_cands, int32_t burnin, int32_t steps,
+                        dtb_tune_result* out) {
+  if (!out) return fail(DTB_ERR_INVALID, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!members || n_members < 1) return fail(DTB_ERR_INVALID, "need at least one member");
+  if (n_cands < 0 || n_cands > DTB_TUNE_MAX_BUNDLES || (n_cands > 0 && !bundle_cands))
+    return fail(DTB_ERR_INVALID, "n_cands must be in [0, " + std::to_string(DTB_TUNE_MAX_BUNDLES) + "]");
+  for (int32_t q = 0; q < n_cands; ++q)
+    if (bundle_cands[q] < 4096 || int64_t(bundle_cands[q]) > kBundleMaxSyn)
+      return fail(DTB_ERR_INVALID, "bundle candidate " + std::to_string(q) + " outside [4096, 2^20-1]");
+  if (burnin < 0 || steps < 1) return fail(DTB_ERR_INVALID, "need burnin >= 0 and steps >= 1");
+  int64_t n = 0, nnz = 0;
+  int32_t D = 0;
+  for (int32_t m = 0; m < n_members; ++m) {
+    n += members[m].n;
+    nnz += members[m].nnz;
+    D = std::max(D, members[m].max_delay);
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return fail(DTB_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  const std::string key = arch + "|n=" + std::to_string(n) + ",nnz=" + std::to_string(nnz) +
+                          ",members=" + std::to_string(n_members) +
+                          ",w=" + (members[0].wtype == DTB_W_BF16 ? "bf16" : "f32") + ",D=" + std::to_string(D);
+  if (cache_path) {
+    const auto db = read_tune_cache(cache_path);
+    const auto it = db.find(key);
+    if (it != db.end()) {
+      out->bundle_syn = it->second.bundle_syn;
+      out->unroll = it->second.unroll;
+      out->ms_per_step = float(it->second.ms);
+      out->from_cache = 1;
+      return DTB_OK;
+    }
+  }
+  // candidate bundle sizes: the caller's, or the largest bundle and sizes
+  // whose bundle count fills whole rounds of the CUs (one workgroup per CU)
+  std::vector<int32_t> cands(bundle_cands, bundle_cands + n_cands);
+  if (cands.empty()) {
+    cands.push_back(int32_t(kBundleMaxSyn));
+    const double L = n > 0 ? double(nnz) / double(n) : 1.0;
+    const int64_t ncu = std::max(1, prop.multiProcessorCount);
+    const int64_t k0 = std::max<int64_t>(1, (nnz + kBundleMaxSyn * ncu - 1) / (kBundleMaxSyn * ncu));
+    for (int64_t k = k0; k < k0 + 3 && int32_t(cands.size()) < DTB_TUNE_MAX_BUNDLES; ++k) {
+      const int64_t rows = (n + k * ncu - 1) / (k * ncu);
+      const int64_t b = int64_t(double(rows) * L + 0.5);
+      if (b >= 4096 && b <= kBundleMaxSyn && std::find(cands.begin(), cands.end(), int32_t(b)) == cands.end())
+        cands.push_back(int32_t(b));
+    }
+  }
+  std::vector<dtb_desc> ds(members, members + n_members);
+  std::vector<uint8_t> saved;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  if (e != hipSuccess) {
+    if (ea) (void)hipEventDestroy(ea);
+    return fail(DTB_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+  }
+  dtb_status st = DTB_OK;
+  for (size_t c = 0; c < cands.size() && st == DTB_OK; ++c) {
+    for (auto& x : ds) {
+      x.gather_bundle_syn = cands[c];
+      x.gather_unroll = 0;
+    }
+    dtb_net* net = nullptr;
+    st = n_members == 1 ? dtb_create(ds.data(), hip_stream, &net) : dtb_create_batch(ds.data(), n_members, hip_stream, &net);
+    if (st) break;
+    if (saved.empty()) {
+      // one burned-in state shared by every candidate: each times the same steps
+      size_t used = 0;
+      if (!(st = dtb_step(net, burnin)) && !(st = dtb_save(net, nullptr, 0, &used))) {
+        saved.resize(used);
+        st = dtb_save(net, saved.data(), saved.size(), &used);
+      }
+    }
+    for (int32_t u = 1; u <= 3 && st == DTB_OK; ++u) {
+      net->d.unroll = u;
+      drop_graph(net);
+      if ((st = dtb_load(net, saved.data(), saved.size()))) break;
+      e = hipEventRecord(ea, net->stream);
+      if (e == hipSuccess && (st = dtb_step(net, steps))) break;
+      if (e == hipSuccess) e = hipEventRecord(eb, net->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(eb);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+      if (e != hipSuccess) {
+        st = fail(DTB_ERR_HIP, std::string("autotune timing: ") + hipGetErrorString(e));
+        break;
+      }
+      const int q = out->n_tried++;
+      out->tried_bundle[q] = cands[c];
+      out->tried_unroll[q] = u;
+      out->tried_ms[q] = ms / float(steps);
+      if (q == 0 || out->tried_ms[q] < out->ms_per_step) {
+        out->bundle_syn = cands[c];
+        out->unroll = u;
+        out->ms_per_step = out->tried_ms[q];
+      }
+    }
+    dtb_destroy(net);
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (st) return st;
+  if (cache_path) {
+    auto db = read_tune_cache(cache_path);
+    db[key] = TuneEntry{out->bundle_syn, out->unroll, double(out->ms_per_step)};
+    if (!write_tune_cache(cache_path, db))
+      return fail(DTB_ERR_INVALID, std::string("cannot write the tuning cache ") + cache_path);
+  }
   return DTB_OK;
 }
 

@@ -167,6 +167,15 @@ struct DeviceNet {
   int64_t* totals = nullptr;        // [4]: spikes, ev_rec, ev_bg, steps
   int32_t* ids = nullptr;           // [n_pad] ascending spike ids of the last step
   int32_t* id_count = nullptr;      // [1]
+  // spike list of an earlier recorded step, rebuilt on request from its
+  // ring slot: [0] epoch - 1, [1] slot | ids | count | look-back status words,
+  // ticket, spike-total sink
+  int64_t* rd_at = nullptr;         // [2]
+  int32_t* rd_ids = nullptr;        // [n_pad]
+  int32_t* rd_count = nullptr;      // [1]
+  uint64_t* rd_status = nullptr;    // [compact_blocks]
+  uint32_t* rd_ticket = nullptr;    // [1]
+  int64_t* rd_total = nullptr;      // [1]
   uint64_t* cstatus = nullptr;      // [compact_blocks] look-back status words
   uint32_t* cticket = nullptr;      // [1] dynamic block ticket
   uint32_t* force = nullptr;        // [rec + 1][words_pad] pending forced bitmaps
@@ -183,6 +192,8 @@ struct DeviceNet {
 // captured once and replayed; k_finalize (last of a step) advances it.
 hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s);
 hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
+hipError_t launch_compact_read(const DeviceNet& d, const int64_t* at, int32_t* ids, int32_t* count,
+                               uint64_t* status, uint32_t* ticket, int64_t* total, hipStream_t s);
 hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
 hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
                          hipStream_t s);

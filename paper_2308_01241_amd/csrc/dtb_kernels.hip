@@ -808,6 +808,16 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s) {
   return hipGetLastError();
 }
 
+// the spike list of an earlier step, rebuilt from its ring slot: at[0] + 1 is
+// the look-back epoch of this read, at[1] the slot; the read's own status
+// words, ticket (zeroed by the caller) and spike-total sink
+hipError_t launch_compact_read(const DeviceNet& d, const int64_t* at, int32_t* ids, int32_t* count,
+                               uint64_t* status, uint32_t* ticket, int64_t* total, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(unsigned(d.compact_blocks)), dim3(kCompactBlock), 0, s, at, d.raster,
+                     d.words_pad, d.compact_blocks, ids, count, status, ticket, total);
+  return hipGetLastError();
+}
+
 namespace {
 
 template <int kU>

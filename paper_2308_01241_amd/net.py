@@ -220,12 +220,16 @@ class Net:
         """uint8 [t1-t0, n] spike raster of the recorded steps."""
         return unpack_bits(self.spikes_bits(t0, t1), self.n)
 
-    def spike_ids(self, cap=None) -> np.ndarray:
+    def spike_ids(self, t=None, cap=None, with_count=False):
+        """Ascending ids of the neurons that spiked in step t (default: the
+        most recent step); with_count also returns the total (may exceed cap)."""
+        t = self.t - 1 if t is None else int(t)
         cap = self.n if cap is None else int(cap)
         ids = np.zeros(max(cap, 1), dtype=np.int32)
         cnt = ctypes.c_int64(0)
-        check(self._lib.dtb_read_spike_ids(self._h, _ptr(ids), cap, ctypes.byref(cnt)))
-        return ids[:min(cap, cnt.value)].copy()
+        check(self._lib.dtb_read_spike_ids(self._h, t, _ptr(ids), cap, ctypes.byref(cnt)))
+        out = ids[:min(cap, cnt.value)].copy()
+        return (out, int(cnt.value)) if with_count else out
 
     def state(self, field: str) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.float32)

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_bitmap_words(lib):
-    assert lib.dtb_abi_version() == 8
+    assert lib.dtb_abi_version() == 9
     assert [lib.dtb_bitmap_words(n) for n in (0, 1, 32, 33, 64)] == [0, 1, 1, 2, 2]
     assert isinstance(lib.dtb_last_error(), bytes)
 
@@ -159,3 +159,19 @@ def test_checkpoint_validation_without_a_gpu(lib):
     used = ctypes.c_size_t(0)
     assert lib.dtb_save(None, None, 0, ctypes.byref(used)) == -1
     assert lib.dtb_load(None, None, 0) == -1
+
+
+def test_autotune_rejects_bad_arguments_before_any_device_call(lib):
+    from paper_2308_01241_amd._lib import Desc, TuneResult
+    res = TuneResult()
+    d = (Desc * 1)()
+    cands = (ctypes.c_int32 * 9)(*([65536] * 9))
+    assert lib.dtb_autotune(None, 1, None, None, None, 0, 0, 10, ctypes.byref(res)) == -1
+    assert lib.dtb_autotune(d, 0, None, None, None, 0, 0, 10, ctypes.byref(res)) == -1
+    assert lib.dtb_autotune(d, 1, None, None, cands, 9, 0, 10, ctypes.byref(res)) == -1   # > 8 candidates
+    bad = (ctypes.c_int32 * 1)(100)
+    assert lib.dtb_autotune(d, 1, None, None, bad, 1, 0, 10, ctypes.byref(res)) == -1     # below 4096
+    assert lib.dtb_autotune(d, 1, None, None, None, 0, 0, 0, ctypes.byref(res)) == -1     # no timed step
+    assert lib.dtb_autotune(d, 1, None, None, None, 0, -1, 10, ctypes.byref(res)) == -1   # negative burn-in
+    assert lib.dtb_autotune(d, 1, None, None, None, 0, 0, 10, None) == -1
+    assert b"candidate" in lib.dtb_last_error() or b"burnin" in lib.dtb_last_error() or lib.dtb_last_error()

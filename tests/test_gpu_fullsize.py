@@ -1,0 +1,148 @@
+"""GPU checks at the full partition size: 20,000,000 neurons and 2e9 synapses
+in the launch configuration the benchmark times.
+
+The network is the paper's accuracy setting (Sec. VII-B): an independent
+200,000-neuron subgraph (the config-2 slice generator, no synapse into or out
+of it) embedded in the first ids of a 19.8M-neuron partition net, so that
+the GPU runs the whole partition while the FP64 reference runs only the
+subgraph, which draws the same background (same ids, same seed).
+"""
+import numpy as np
+import pytest
+
+import netgen
+import oracle
+from parity import DELTA, FIELDS, lockstep, rel_mse, report, state_close
+
+pytestmark = pytest.mark.gpu
+
+SUB_N = 200_000
+
+
+@pytest.fixture(scope="module")
+def dtb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2308_01241_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def big():
+    sub = netgen.make_network(netgen.slice_spec(rate_hz=7))
+    rest = netgen.make_network(netgen.partition_spec(n=netgen.FULL_PARTITION_N - SUB_N, rate_hz=7))
+    net = netgen.embed_independent(sub, rest)
+    del rest
+    assert net.n == netgen.FULL_PARTITION_N and net.nnz == 100 * net.n
+    return net, sub
+
+
+def _gpu(dtb, net, **kw):
+    import torch
+    from paper_2308_01241_amd import autotune
+    b, u = autotune.lookup(net.n, net.nnz, 1, kw.get("wtype", "f32"), net.max_delay)
+    return dtb.Net(net, stream=torch.cuda.current_stream(), bundle_syn=b, unroll=u, **kw)
+
+
+@pytest.mark.timeout(900)
+def test_embedded_subgraph_one_second(dtb, big):
+    """1 s (1,000 steps) of the full partition; the subgraph's spikes against
+    the FP64 reference of the subgraph alone, in lockstep: every GPU spike
+    decision equals the reference's threshold test except at counted
+    near-threshold ties (spike times equal up to ties), population counts
+    exact at every step, and at ten checkpoints V within DELTA, gates within
+    the teacher-forced bar and the relative MSE of V and gates < 1e-4 (the
+    paper's criterion).  The same run checks the compaction at full size:
+    spike-id lists of the last and earlier steps equal the bitmap's ids,
+    and the spike total equals the raster's popcount."""
+    net, sub = big
+    T, chunk = 1000, 100
+    g = _gpu(dtb, net, record_steps=T)
+    print(f"embedded subgraph: n={net.n} sub={sub.n} T={T}", flush=True)
+    states = {}
+    for c in range(T // chunk):
+        g.step(chunk)
+        states[(c + 1) * chunk - 1] = {f: g.state(f)[:sub.n].copy() for f in FIELDS}
+    bits = g.spikes_bits(0, T)
+    counts = g.region_counts(0, T)[:, :sub.n_regions]
+    # compaction at full size (306 look-back blocks)
+    total = int(np.bitwise_count(bits).sum())
+    assert g.counters()["spikes"] == total
+    for t in (T - 1, T // 2, 3):
+        full = dtb.unpack_bits(bits[t:t + 1], net.n)[0]
+        ids, cnt = g.spike_ids(t, with_count=True)
+        assert cnt == int(full.sum())
+        np.testing.assert_array_equal(ids, np.nonzero(full)[0])
+    g.close()
+    ras = dtb.unpack_bits(bits[:, :(sub.n + 31) // 32], sub.n)
+    del bits
+    print("embedded subgraph: FP64 reference in lockstep", flush=True)
+    worst = {"mse": 0.0, "dV": 0.0}
+
+    def check(t):
+        def cb(o):
+            jmax = max(np.abs(o.get(f)).max() for f in FIELDS[1:])
+            for f in FIELDS:
+                x, r = states[t][f], o.get(f)
+                m = rel_mse(x, r)
+                worst["mse"] = max(worst["mse"], m)
+                assert m < 1e-4, (t, f, m)
+                if f == "V":
+                    dv = float(np.max(np.abs(x - r)))
+                    worst["dV"] = max(worst["dV"], dv)
+                    assert dv < DELTA, (t, dv)
+                else:
+                    ok = state_close(x, r, 1e-3 * jmax)
+                    assert ok.all(), (t, f, int(np.count_nonzero(~ok)))
+        return cb
+
+    ls = lockstep(oracle.OracleNet(sub), ras, checkpoints={t: check(t) for t in states})
+    np.testing.assert_array_equal(counts, ls["counts"])
+    rate = ras.sum() / (sub.n * T * 1e-3)
+    report("embedded_subgraph_1s", n=net.n, sub_n=sub.n, steps=T, sub_rate_hz=float(rate),
+           sub_spikes=int(ras.sum()), ties=len(ls["ties"]), tie_margins_mV=[x[2] for x in ls["ties"][:20]],
+           max_rel_mse=worst["mse"], max_abs_dV_mV=worst["dV"], spikes_total=total)
+    assert ras.sum() > 0
+
+
+@pytest.mark.timeout(900)
+def test_full_size_sampled_rows_and_event_totals(dtb, big):
+    """The full partition teacher-forced with a seeded 20 Hz raster.  Exact
+    check of every step's delivered-event total against the push-side count
+    sum_d sum_m s^{t-d+1}_m * outdeg_d(m) (out-degree per delay, counted with
+    numpy from the CSR), and state of 2,000 sampled rows against the
+    reference's row-subset mode (it computes those rows one by one)."""
+    net, _ = big
+    n, D = net.n, net.max_delay
+    outdeg = np.zeros(n * D, dtype=np.int64)
+    chunk = 200_000_000
+    for k0 in range(0, net.nnz, chunk):
+        key = net.col[k0:k0 + chunk].astype(np.int64) * D + (net.delay[k0:k0 + chunk].astype(np.int64) - 1)
+        outdeg += np.bincount(key, minlength=n * D)
+        del key
+    outdeg = outdeg.reshape(n, D)
+    T = 24
+    rng = np.random.default_rng(2024)
+    forced = (rng.random((T, n), dtype=np.float32) < 0.02).astype(np.uint8)
+    rows = np.sort(rng.choice(n, 2000, replace=False)).astype(np.int64)
+    o = oracle.OracleNet(net)
+    g = _gpu(dtb, net, record_steps=T)
+    g.force(forced)
+    print(f"full-size teacher forcing: n={n} T={T}", flush=True)
+    for t in range(T):
+        o.step(forced=forced[t], rows=rows)
+        g.step(1)
+        er, _ = g.step_events(t, t + 1)
+        expect = 0
+        for d in range(1, D + 1):
+            if t - d + 1 >= 0:
+                expect += int(forced[t - d + 1].astype(np.int64) @ outdeg[:, d - 1])
+        assert int(er[0]) == expect, f"step {t}: {int(er[0])} != {expect}"
+        if t in (7, 15, T - 1):
+            jmax = max(np.abs(o.get(f)[rows]).max() for f in FIELDS[1:])
+            for f in FIELDS:
+                floor = 0.0 if f == "V" else 1e-3 * jmax
+                ok = state_close(g.state(f)[rows], o.get(f)[rows], floor)
+                assert ok.all(), f"step {t} {f}: {np.count_nonzero(~ok)} sampled rows off"
+    assert g.counters()["spikes"] == int(forced.sum())

@@ -2,14 +2,19 @@
 the same seeded inputs.
 
 Bars (FP32 state, FP64 reference):
-  * spike rasters: identical until the first step where the reference has a
-    neuron within DELTA of threshold (a tie FP32 may legitimately flip); any
-    difference at that step must be at such a neuron;
+  * spikes: the reference stepped through the GPU's raster (lockstep, see
+    parity.py) agrees with every GPU spike decision except at near-threshold
+    ties (|V~ - V_th| < 1e-3 mV), which are counted; with no tie the raster
+    is the reference's own free run bit for bit;
   * per-step state under teacher forcing: |x_gpu - x_ref| <= 1e-5 max(|x_ref|, f_x),
     f_V = 0, f_j = 1e-3 max_i |j_ref| (the paper's own check compares V and
     currents at relative MSE < 1e-4, Sec. VII-B);
   * delivered recurrent / background event counts, population counts and
-    spike-id lists: exact integers.
+    spike-id lists: exact integers;
+  * population rates over 1 s of biological time: within 2 % of the FP64
+    free run (pooled over seeds where a single 1,000-neuron run is too
+    noisy; network mean on the chaotic 200k slice, whose per-population
+    rates are judged against the reference's own realization spread).
 """
 import numpy as np
 import pytest
@@ -17,11 +22,9 @@ import pytest
 import netgen
 import oracle
 from nethelpers import hand_net
+from parity import DELTA, FIELDS, lockstep, rel_mse, report, state_close
 
 pytestmark = pytest.mark.gpu
-
-DELTA = 1e-3  # mV: near-threshold band where an FP32 flip is accepted
-FIELDS = ("V", "j_AMPA", "j_NMDA", "j_GABAa", "j_GABAb")
 
 
 @pytest.fixture(scope="module")
@@ -38,38 +41,44 @@ def _gpu(dtb, net, **kw):
     return dtb.Net(net, stream=torch.cuda.current_stream(), **kw)
 
 
-def _check_raster(gpu_raster, ref):
-    """Identical until a reference near-tie explains the first difference."""
-    diff = np.nonzero((gpu_raster != ref["raster"]).any(axis=1))[0]
-    if len(diff) == 0:
-        return len(gpu_raster)
-    t = int(diff[0])
-    bad = np.nonzero(gpu_raster[t] != ref["raster"][t])[0]
-    margins = ref["margins"][t, bad]
-    assert np.all(margins < DELTA), f"step {t}: neurons {bad[:8]} differ with margins {margins[:8]}"
-    return t
+def _check_raster(gpu_raster, net, free=None, ref_net=None):
+    """Lockstep check of a GPU free-run raster from the initial state (ref_net:
+    a configured reference at that state; default a fresh one of `net`);
+    when the reference's own free run is given and no tie occurred, the
+    rasters are equal bit for bit.  Returns the lockstep result."""
+    ls = lockstep(ref_net if ref_net is not None else oracle.OracleNet(net), gpu_raster)
+    if free is not None and not ls["ties"]:
+        np.testing.assert_array_equal(gpu_raster, free["raster"])
+    return ls
 
 
-def _state_close(x_gpu, x_ref, floor):
-    tol = 1e-5 * np.maximum(np.abs(x_ref), floor)
-    return np.abs(x_gpu.astype(np.float64) - x_ref) <= tol
+_state_close = state_close
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_raster_matches_reference_100_steps(dtb, seed):
+    """100 free-run steps of the 1,000-neuron net: every spike decision of the
+    GPU equals the FP64 threshold test's (ties counted), the raster is the
+    reference's free run bit for bit when there is no tie (always where the
+    reference has no neuron within DELTA of threshold), and events and
+    population counts equal the reference's at every one of the T steps."""
     net = netgen.make_network(netgen.small_net(seed_offset=seed))
     T = 100
-    ref = oracle.OracleNet(net).run(T, want_margin=True)
+    free = oracle.OracleNet(net).run(T, want_margin=True)
     g = _gpu(dtb, net)
     g.step(T)
     ras = g.raster(0, T)
-    exact_until = _check_raster(ras, ref)
-    assert ref["raster"].sum() > 0
-    if exact_until == T:
-        er, eb = g.step_events(0, T)
-        np.testing.assert_array_equal(er, ref["ev_rec"])
-        np.testing.assert_array_equal(eb, ref["ev_bg"])
-        np.testing.assert_array_equal(g.region_counts(0, T), ref["counts"])
+    ls = _check_raster(ras, net, free)
+    assert free["raster"].sum() > 0
+    if np.nanmin(free["margins"]) >= DELTA:
+        assert not ls["ties"]
+    er, eb = g.step_events(0, T)
+    assert len(er) == T
+    np.testing.assert_array_equal(er, ls["ev_rec"])
+    np.testing.assert_array_equal(eb, ls["ev_bg"])
+    np.testing.assert_array_equal(g.region_counts(0, T), ls["counts"])
+    report("raster_100", seed=seed, ties=len(ls["ties"]), ref_min_margin_mV=float(np.nanmin(free["margins"])),
+           spikes=int(ras.sum()))
 
 
 def test_teacher_forced_state_per_step(dtb):
@@ -79,6 +88,7 @@ def test_teacher_forced_state_per_step(dtb):
     o = oracle.OracleNet(net)
     g = _gpu(dtb, net)
     g.force(free["raster"])
+    dv_max = 0.0
     for t in range(T):
         out = o.step(forced=free["raster"][t])
         g.step(1)
@@ -86,22 +96,71 @@ def test_teacher_forced_state_per_step(dtb):
         for f in FIELDS:
             ref = o.get(f)
             floor = 0.0 if f == "V" else 1e-3 * max(jmax, 1e-30)
-            ok = _state_close(g.state(f), ref, floor)
+            x = g.state(f)
+            ok = _state_close(x, ref, floor)
             assert ok.all(), f"step {t} field {f}: {np.count_nonzero(~ok)} neurons out of tolerance"
+            if f == "V":
+                dv_max = max(dv_max, float(np.max(np.abs(x - ref))))
         er, eb = g.step_events(t, t + 1)
         assert int(er[0]) == out["ev_rec"] and int(eb[0]) == out["ev_bg"], f"events differ at step {t}"
         np.testing.assert_array_equal(g.region_counts(t, t + 1)[0], out["counts"])
     np.testing.assert_array_equal(g.raster(0, T), free["raster"])
     np.testing.assert_array_equal(g.state("ref"), o.get("ref"))
+    # the FP32 error in V that the tie band DELTA has to cover
+    assert dv_max < DELTA
+    report("teacher_forced_100", max_abs_dV_mV=dv_max)
 
 
 def test_spike_ids_are_the_bitmap_in_ascending_order(dtb):
+    """The compacted list of the step just taken, and the lists of earlier
+    recorded steps rebuilt on request, are the raster's ids in ascending
+    order; a cap below the count returns the first ids and the full count."""
     net = netgen.make_network(netgen.small_net(seed_offset=1, bg_lambda=2.0))
-    g = _gpu(dtb, net)
+    g = _gpu(dtb, net, record_steps=40)
     for t in range(30):
         g.step(1)
         ids = g.spike_ids()
         np.testing.assert_array_equal(ids, np.nonzero(g.raster(t, t + 1)[0])[0])
+    ras = g.raster(0, 30)
+    for t in (0, 3, 17, 28, 29):
+        np.testing.assert_array_equal(g.spike_ids(t), np.nonzero(ras[t])[0])
+    t = int(np.argmax(ras.sum(axis=1)))
+    ids, cnt = g.spike_ids(t, cap=5, with_count=True)
+    assert cnt == int(ras[t].sum()) > 5
+    np.testing.assert_array_equal(ids, np.nonzero(ras[t])[0][:5])
+    with pytest.raises(dtb.DtbError):
+        g.spike_ids(30)  # not taken yet
+    g.step(20)
+    with pytest.raises(dtb.DtbError):
+        g.spike_ids(5)   # older than record_steps
+    np.testing.assert_array_equal(g.spike_ids(10), np.nonzero(ras[10])[0])
+
+
+def test_compaction_across_many_blocks(dtb):
+    """A 300,007-neuron partition (five compaction blocks of 65,536 neurons,
+    a ragged last word) at a high drive: the look-back across blocks gives
+    every step's ids equal to the raster's nonzeros, the ids of earlier
+    steps rebuilt from their bitmaps too, and the spike total of the
+    counters equals the raster's sum."""
+    net = netgen.make_network(netgen.partition_spec(n=300_007, bg_lambda=netgen.PARTITION_LAMBDA[30]))
+    T = 40
+    g = _gpu(dtb, net, record_steps=T)
+    lens = []
+    for t in range(T):
+        g.step(1)
+        ids, cnt = g.spike_ids(with_count=True)
+        ref = np.nonzero(g.raster(t, t + 1)[0])[0]
+        assert cnt == len(ref)
+        np.testing.assert_array_equal(ids, ref)
+        lens.append(cnt)
+    ras = g.raster(0, T)
+    assert g.counters()["spikes"] == int(ras.sum())
+    for t in (0, 1, T // 2, T - 2):
+        np.testing.assert_array_equal(g.spike_ids(t), np.nonzero(ras[t])[0])
+    # the late steps have spikes in every block
+    blocks = np.unique(np.nonzero(ras[-1])[0] // 65536)
+    assert len(blocks) == 5, blocks
+    report("compaction_blocks", n=net.n, spikes_last_step=lens[-1], spikes_total=int(ras.sum()))
 
 
 def test_counters_and_determinism(dtb):
@@ -218,7 +277,7 @@ def test_launch_shapes_give_identical_results(dtb):
         g.step(T)
         runs.append((g.raster(0, T), g.state("V"), g.state("j_AMPA"), g.counters()))
         g.close()
-    _check_raster(runs[0][0], ref)
+    _check_raster(runs[0][0], net, ref)
     for r in runs[1:]:
         np.testing.assert_array_equal(r[0], runs[0][0])
         np.testing.assert_array_equal(r[1], runs[0][1])
@@ -241,7 +300,9 @@ def test_ou_background_free_run_teacher_forced_reset_and_graph(dtb):
     g = _gpu(dtb, net)
     g.set_background_ou(mu, sigma, tau)
     g.step(T)
-    _check_raster(g.raster(0, T), ref)
+    o_ls = oracle.OracleNet(net)
+    o_ls.set_ou(mu, sigma, tau)
+    _check_raster(g.raster(0, T), net, ref, ref_net=o_ls)
     first = g.raster(0, T)
     assert g.counters()["ev_bg"] == 0
     # teacher forcing with the reference raster
@@ -303,7 +364,7 @@ def test_set_background_equals_a_fresh_handle(dtb):
     np.testing.assert_array_equal(g.raster(0, 100), h.raster(0, 100))
     np.testing.assert_array_equal(g.step_events(0, 100)[1], h.step_events(0, 100)[1])
     ref = oracle.OracleNet(net).run(100, want_margin=True)
-    _check_raster(h.raster(0, 100), ref)
+    _check_raster(h.raster(0, 100), net, ref)
 
 
 def test_bf16_weights_match_reference_on_rounded_weights(dtb):
@@ -329,69 +390,173 @@ def test_bf16_weights_match_reference_on_rounded_weights(dtb):
         assert _state_close(g.state(f), o.get(f), floor).all(), f
 
 
-@pytest.mark.timeout(300)
+@pytest.mark.timeout(600)
+def test_one_second_rates_pooled_over_seeds_and_lockstep(dtb):
+    """1 s of biological time (1,000 steps) of the 1,000-neuron net for 8
+    seeds: (a) the paper's accuracy check (Sec. VII-B) - every GPU spike
+    decision equals the FP64 threshold test's through the whole second,
+    except at counted near-threshold ties; events and population counts
+    exact at every step; V within DELTA and gates within the teacher-forced
+    bar at the end, relative MSE of V and gates < 1e-4; (b) the population
+    rates of the GPU's free run, pooled over the seeds, within 2 % of the
+    FP64 free run's (a single 1,000-neuron run has ~1.7 % Poisson noise per
+    population; the pooled counts ~0.6 %).  The reference's own spread under
+    a 1e-4 mV shift of V0 is reported beside it."""
+    T = 1000
+    G = np.zeros(2)
+    A = np.zeros(2)
+    P = np.zeros(2)
+    all_ties = {}
+    for s in range(1, 9):
+        net = netgen.make_network(netgen.small_net(seed_offset=s))
+        print(f"1-s pooled rates: seed {s}", flush=True)
+        g = _gpu(dtb, net, record_steps=T)
+        g.step(T)
+        ras = g.raster(0, T)
+        o = oracle.OracleNet(net)
+        ls = lockstep(o, ras)
+        er, eb = g.step_events(0, T)
+        np.testing.assert_array_equal(er, ls["ev_rec"])
+        np.testing.assert_array_equal(eb, ls["ev_bg"])
+        cg = g.region_counts(0, T)
+        np.testing.assert_array_equal(cg, ls["counts"])
+        jmax = max(np.abs(o.get(f)).max() for f in FIELDS[1:])
+        for f in FIELDS:
+            x, r = g.state(f), o.get(f)
+            assert rel_mse(x, r) < 1e-4, f
+            if f == "V":
+                assert np.max(np.abs(x - r)) < DELTA
+            else:
+                assert state_close(x, r, 1e-3 * jmax).all(), f
+        g.close()
+        free = oracle.OracleNet(net).run(T)
+        if not ls["ties"]:
+            np.testing.assert_array_equal(ras, free["raster"])
+        alt = netgen.make_network(netgen.small_net(seed_offset=s))
+        alt.V0 = (alt.V0.astype(np.float64) + 1e-4).astype(np.float32)
+        G += cg.sum(axis=0)
+        A += free["counts"].sum(axis=0)
+        P += oracle.OracleNet(alt).run(T)["counts"].sum(axis=0)
+        all_ties[s] = len(ls["ties"])
+    rel = np.abs(G - A) / A
+    floor = np.abs(P - A) / A
+    report("rates_1s_pooled_8_seeds", gpu_hz=(G / (8 * 500)).tolist(), ref_hz=(A / (8 * 500)).tolist(),
+           rel_error=rel.tolist(), ref_spread_1e4mV=floor.tolist(), ties_per_seed=all_ties)
+    assert np.all(rel < 0.02), rel
+
+
+def _forced_state_errors(o, gs, raster, steps):
+    """Teacher-force the handles `gs` and the reference with `raster` for
+    `steps` steps.  Per handle: the largest relative state error per field
+    over the neurons that stayed inside the forward-Euler stability bound
+    dt G / C <= 2 (G = g_L + sum_u g_u j_u, from the reference's gates before
+    each step) and over all neurons, and the relative MSE at the end.  A
+    neuron past the bound has a membrane map that multiplies any difference
+    by |1 - dt G / C| > 1 per step, so FP32 and FP64 drift apart there by
+    construction of the explicit scheme.  Also returns how many neurons
+    left the bound."""
+    net = o.net
+    pt = net.ptypes[net.ptype].astype(np.float64)  # per neuron: C gL EL Vth Vreset tref Iext g[4]
+    unstable = np.zeros(net.n, dtype=bool)
+    worst = [{f: 0.0 for f in FIELDS} for _ in gs]
+    worst_all = [{f: 0.0 for f in FIELDS} for _ in gs]
+    for g in gs:
+        g.force(raster[:steps])
+    for t in range(steps):
+        G = pt[:, 1] + sum(pt[:, 7 + u] * o.get(f) for u, f in enumerate(FIELDS[1:]))
+        unstable |= net.dt_ms * G / pt[:, 0] > 2.0
+        o.step(forced=raster[t])
+        for g in gs:
+            g.step(1)
+        ref = {f: o.get(f) for f in FIELDS}
+        for q, g in enumerate(gs):
+            for f in FIELDS:
+                x = g.state(f).astype(np.float64)
+                den = np.maximum(np.abs(ref[f]), max(1e-3 * np.abs(ref[f]).max(), 1e-30) if f != "V" else 1e-30)
+                e = np.abs(x - ref[f]) / den
+                worst_all[q][f] = max(worst_all[q][f], float(np.max(e)))
+                if not unstable.all():
+                    worst[q][f] = max(worst[q][f], float(np.max(e[~unstable])))
+    mse = [{f: rel_mse(g.state(f), o.get(f)) for f in FIELDS} for g in gs]
+    return worst, worst_all, mse, int(unstable.sum())
+
+
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("rate", [7, 15, 30])
-def test_bf16_rates_within_2_percent_on_the_slice(dtb, rate):
-    """Precision form on the 200k-neuron slice: the network-wide rate of the
-    BF16-weight run over steps [200, 1000) is within 2 % of the FP32 run, and
-    its per-population differences are no larger than twice those between
-    two FP32 realizations (V0 shifted by 1 uV), the noise floor of a 0.8 s
-    population rate."""
+def test_slice_fp32_and_bf16_against_fp64(dtb, rate):
+    """The 200,000-neuron slice (config 2) at the 7 / 15 / 30 Hz drives, FP32
+    and BF16 weights against the FP64 reference on the FP32 weights:
+      * 1 s free runs: network rate within 2 % of the reference's, for both
+        forms; per-population rates (size-weighted mean relative difference)
+        within twice the reference's own spread under a 1e-4 mV shift of V0
+        plus 0.5 % (this net is chaotic: the shifted reference run leaves the
+        original within tens of steps, and its small populations then differ
+        by up to tens of percent);
+      * 40 teacher-forced steps: per-step state error of each form (FP32 within
+        the 1e-5 bar at every neuron inside the forward-Euler stability bound
+        - at the 30 Hz drive about a tenth of the neurons leave it; BF16
+        reported: it carries the weights' quantisation) and the paper's
+        relative-MSE criterion (< 1e-4) over all neurons for both."""
+    T = 1000
     lam = netgen.PARTITION_LAMBDA[rate]
     net = netgen.make_network(netgen.slice_spec(rate_hz=rate, bg_lambda=lam))
-    alt = netgen.make_network(netgen.slice_spec(rate_hz=rate, bg_lambda=lam))
-    alt.V0 = (alt.V0 + np.float32(1e-3)).astype(np.float32)
+    sizes = net.region_sizes().astype(np.float64)
+    wgt = sizes / sizes.sum()
+    print(f"slice {rate} Hz: free runs", flush=True)
     counts = {}
-    for tag, nw, wt in (("f32", net, "f32"), ("bf16", net, "bf16"), ("f32b", alt, "f32")):
-        g = _gpu(dtb, nw, wtype=wt, record_steps=1000)
-        g.step(1000)
-        counts[tag] = g.region_counts(200, 1000).sum(axis=0).astype(np.float64)
+    for wt in ("f32", "bf16"):
+        g = _gpu(dtb, net, wtype=wt, record_steps=T)
+        g.step(T)
+        counts[wt] = g.region_counts(0, T).sum(axis=0).astype(np.float64)
         g.close()
-    a, b, c = counts["f32"], counts["bf16"], counts["f32b"]
-    assert abs(b.sum() - a.sum()) / a.sum() < 0.02
-    sizes = net.region_sizes()
-    w = sizes / sizes.sum()
-    d16 = (np.abs(b - a) / np.maximum(a, 1) * w).sum()
-    d32 = (np.abs(c - a) / np.maximum(a, 1) * w).sum()
-    assert d16 <= 2.0 * d32 + 0.005, (d16, d32)
+    A = oracle.OracleNet(net).run(T)["counts"].sum(axis=0).astype(np.float64)
+    alt = netgen.make_network(netgen.slice_spec(rate_hz=rate, bg_lambda=lam))
+    alt.V0 = (alt.V0.astype(np.float64) + 1e-4).astype(np.float32)
+    P = oracle.OracleNet(alt).run(T)["counts"].sum(axis=0).astype(np.float64)
+
+    def werr(x):
+        return float((np.abs(x - A) / np.maximum(A, 1.0) * wgt).sum())
+
+    mean_err = {wt: abs(c.sum() - A.sum()) / A.sum() for wt, c in counts.items()}
+    floor_mean, floor_w = abs(P.sum() - A.sum()) / A.sum(), werr(P)
+    # teacher forcing with the reference's own raster
+    print(f"slice {rate} Hz: teacher forcing", flush=True)
+    steps = 40
+    ras = oracle.OracleNet(net).run(steps)["raster"]
+    gs = [_gpu(dtb, net, wtype=wt, record_steps=steps) for wt in ("f32", "bf16")]
+    worst, worst_all, mse, n_unstable = _forced_state_errors(oracle.OracleNet(net), gs, ras, steps)
+    report("slice_precision", rate_hz=rate, ref_rate_hz=A.sum() / (net.n * T * 1e-3),
+           rate_error={"f32": mean_err["f32"], "bf16": mean_err["bf16"], "ref_spread_1e4mV": floor_mean},
+           region_weighted_error={"f32": werr(counts["f32"]), "bf16": werr(counts["bf16"]),
+                                  "ref_spread_1e4mV": floor_w},
+           forced_max_rel_error={"f32": worst[0], "bf16": worst[1]},
+           forced_max_rel_error_all={"f32": worst_all[0], "bf16": worst_all[1]},
+           neurons_past_euler_bound=n_unstable, forced_rel_mse={"f32": mse[0], "bf16": mse[1]})
+    for wt in ("f32", "bf16"):
+        assert mean_err[wt] < 0.02, (wt, mean_err)
+        assert werr(counts[wt]) <= 2.0 * floor_w + 0.005, (wt, werr(counts[wt]), floor_w)
+    for f in FIELDS:
+        assert worst[0][f] <= 1e-5, (f, worst[0][f])
+        assert mse[0][f] < 1e-4 and mse[1][f] < 1e-4, (f, mse)
 
 
-@pytest.mark.timeout(600)
-def test_full_size_partition_sampled_rows_and_event_totals(dtb):
-    """The 20,000,000-neuron / 2e9-synapse partition in the launch setup the
-    benchmark times, teacher-forced with a seeded 20 Hz raster.  Exact check
-    of every step's delivered-event total against the push-side count
-    sum_d sum_m s^{t-d+1}_m * outdeg_d(m) (out-degree per delay, counted
-    with numpy from the CSR), and state of 2,000 sampled rows against the
-    reference's row-subset mode (it computes those rows one by one)."""
-    net = netgen.make_network(netgen.partition_spec(rate_hz=15))
-    n, D = net.n, net.max_delay
-    outdeg = np.zeros(n * D, dtype=np.int64)
-    chunk = 200_000_000
-    for k0 in range(0, net.nnz, chunk):
-        key = net.col[k0:k0 + chunk].astype(np.int64) * D + (net.delay[k0:k0 + chunk].astype(np.int64) - 1)
-        outdeg += np.bincount(key, minlength=n * D)
-        del key
-    outdeg = outdeg.reshape(n, D)
-    T = 24
-    rng = np.random.default_rng(2024)
-    forced = (rng.random((T, n), dtype=np.float32) < 0.02).astype(np.uint8)
-    rows = np.sort(rng.choice(n, 2000, replace=False)).astype(np.int64)
-    o = oracle.OracleNet(net)
-    g = _gpu(dtb, net, record_steps=T)
-    g.force(forced)
-    for t in range(T):
-        o.step(forced=forced[t], rows=rows)
-        g.step(1)
-        er, _ = g.step_events(t, t + 1)
-        expect = 0
-        for d in range(1, D + 1):
-            if t - d + 1 >= 0:
-                expect += int(forced[t - d + 1].astype(np.int64) @ outdeg[:, d - 1])
-        assert int(er[0]) == expect, f"step {t}: {int(er[0])} != {expect}"
-        if t in (7, 15, T - 1):
-            jmax = max(np.abs(o.get(f)[rows]).max() for f in FIELDS[1:])
-            for f in FIELDS:
-                floor = 0.0 if f == "V" else 1e-3 * jmax
-                ok = _state_close(g.state(f)[rows], o.get(f)[rows], floor)
-                assert ok.all(), f"step {t} {f}: {np.count_nonzero(~ok)} sampled rows off"
+def test_rejected_background_change_leaves_the_drive(dtb):
+    """An invalid dtb_set_background (negative or huge lambda, negative or
+    non-finite weight) returns DTB_ERR_INVALID and changes nothing: the run
+    continues exactly as an untouched handle's, with the Poisson drive or
+    with the OU current selected before the call."""
+    net = netgen.make_network(netgen.small_net(seed_offset=4))
+    for ou in (False, True):
+        a, b = _gpu(dtb, net), _gpu(dtb, net)
+        for h in (a, b):
+            if ou:
+                h.set_background_ou(0.6, 0.4, 8.0)
+            h.step(20)
+        for lam, w in ((-1.0, 0.4), (1e6, 0.4), (1.0, -0.5), (1.0, float("inf")), (float("nan"), 0.4)):
+            with pytest.raises(dtb.DtbError):
+                a.set_background(lam, w)
+        a.step(60)
+        b.step(60)
+        np.testing.assert_array_equal(a.raster(0, 80), b.raster(0, 80))
+        np.testing.assert_array_equal(a.state("I_ou"), b.state("I_ou"))
+        assert a.counters() == b.counters()

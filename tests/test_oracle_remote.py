@@ -131,7 +131,7 @@ def test_split_network_replaying_its_own_raster_is_the_unsplit_run():
     T = 70
     full = oracle.OracleNet(net)
     rf = full.run(T, want_state=False)
-    local, blk = netgen.split_remote(net, 70)
+    local, blk = netgen.split_remote(net)
     assert blk.row_ptr[-1] == 30 * net.n
     part = oracle.OracleNet(local)
     part.set_remote(blk)
@@ -141,3 +141,46 @@ def test_split_network_replaying_its_own_raster_is_the_unsplit_run():
     np.testing.assert_array_equal(rp["ev_rec"], rf["ev_rec"])
     for f in ("V", "j_AMPA", "j_NMDA", "j_GABAa", "j_GABAb"):
         np.testing.assert_array_equal(part.get(f), full.get(f))
+
+
+def test_split_is_the_region_split_and_keeps_row_order():
+    """split_remote on a partition net: every local in-edge comes from the
+    row's own region and every remote one from another region (the J_intra /
+    J_inter split of Sec. V-B for a partition holding whole regions); the
+    local part followed by the remote part is each row's original order."""
+    net = netgen.make_network(netgen.partition_spec(n=50_000))
+    local, blk = netgen.split_remote(net)
+    n = net.n
+    rl = np.repeat(np.arange(n), np.diff(local.row_ptr))
+    rr = np.repeat(np.arange(n), np.diff(blk.row_ptr))
+    assert np.all(net.region[local.col] == net.region[rl])
+    assert np.all(net.region[blk.col] != net.region[rr])
+    assert local.nnz + int(blk.row_ptr[-1]) == net.nnz
+    assert local.nnz == 70 * n
+    for i in (0, 1, n // 2, n - 1):
+        a, b = local.row_ptr[i], local.row_ptr[i + 1]
+        c, d = blk.row_ptr[i], blk.row_ptr[i + 1]
+        k0, k1 = net.row_ptr[i], net.row_ptr[i + 1]
+        np.testing.assert_array_equal(np.concatenate([local.col[a:b], blk.col[c:d]]), net.col[k0:k1])
+        np.testing.assert_array_equal(np.concatenate([local.w[a:b], blk.w[c:d]]), net.w[k0:k1])
+        np.testing.assert_array_equal(np.concatenate([local.delay[a:b], blk.delay[c:d]]), net.delay[k0:k1])
+        # each part ascending by source
+        assert np.all(np.diff(local.col[a:b]) >= 0) and np.all(np.diff(blk.col[c:d]) >= 0)
+
+
+def test_embedded_independent_subgraph_runs_as_alone():
+    """The network of the accuracy check of Sec. VII-B: a subgraph embedded
+    with no synapse into or out of it evolves exactly as the subgraph alone
+    (same ids, same background draws), and no edge crosses the boundary."""
+    sub = netgen.make_network(netgen.slice_spec(rate_hz=7, n=3000))
+    rest = netgen.make_network(netgen.partition_spec(n=12_000))
+    e = netgen.embed_independent(sub, rest)
+    assert e.n == sub.n + rest.n and e.nnz == sub.nnz + rest.nnz and e.n_regions == sub.n_regions + rest.n_regions
+    k = int(e.row_ptr[sub.n])
+    assert np.all(e.col[:k] < sub.n) and np.all(e.col[k:] >= sub.n)
+    np.testing.assert_array_equal(e.region[:sub.n], sub.region)
+    a = oracle.OracleNet(sub).run(60)
+    b = oracle.OracleNet(e).run(60)
+    assert a["raster"].sum() > 0
+    np.testing.assert_array_equal(b["raster"][:, :sub.n], a["raster"])
+    np.testing.assert_array_equal(b["counts"][:, :sub.n_regions], a["counts"])
