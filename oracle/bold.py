@@ -18,8 +18,12 @@ rest (0, 1, 1, 1).  The paper prints no constants; the published ones are
 used (kappa 0.65 /s, gamma 0.41 /s, tau0 0.98 s, alpha 0.32, E0 0.34,
 V0 0.02); eps = 0.5 and the input scale RATE_SCALE = 100 Hz are choices.
 
-Pinned by: the closed-form fixed point under constant input, and exact rest
-(y = 0) under zero input (tests/test_bold_oracle.py).
+Pinned by: the closed-form fixed point under constant input, exact rest
+(y = 0) under zero input, the transient of a weak step input against the
+Euler map of the model's Jacobian at rest (derived by hand, with the
+published constants typed independently: decay rates, the (s, f)
+oscillation, tau0, alpha, E0 and the signal weights), and the exactly
+linear (s, f) subsystem under strong drive (tests/test_bold_oracle.py).
 """
 from __future__ import annotations
 
