@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 9
+#define DTB_ABI_VERSION 10
 
 typedef enum {
   DTB_OK = 0,
@@ -358,6 +358,20 @@ void dtb_mlp_destroy(dtb_mlp* mlp);
  * last), 1 <= k <= n <= 4096, in ascending order of score. */
 dtb_status dtb_topk(const float* score, int32_t n, int32_t k, int32_t* idx, void* hip_stream,
                     int on_device);
+
+/* dtb_topk for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same selection as dtb_topk with on_device = 0: score [n] and idx [k] are
+ * host arrays, 1 <= k <= n <= 4096 (DTB_ERR_INVALID otherwise, naming the
+ * limit).  The scores and indices are staged through a static device array
+ * of 32 KB (4096 scores + 4096 indices), one per GPU the library runs on,
+ * held until the process ends; its address is looked up once per device.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); it copies the scores in, sorts, copies the indices out and
+ * synchronizes hip_stream (NULL: the current device's null stream).  All
+ * calls on one GPU share that array, so calls that overlap on one GPU
+ * race: serialize them (one stream, or wait for the previous call). */
+dtb_status dtb_topk_noalloc(const float* score, int32_t n, int32_t k, int32_t* idx, void* hip_stream);
 
 /* ------------------------------------------------- assimilation */
 

@@ -96,6 +96,7 @@ SIGNATURES = {
     "dtb_mlp_train_step": ([_P, _P, _P, _I32, ctypes.c_float, _P, ctypes.c_int], ctypes.c_int),
     "dtb_mlp_destroy": ([_P], None),
     "dtb_topk": ([_P, _I32, _I32, _P, _P, ctypes.c_int], ctypes.c_int),
+    "dtb_topk_noalloc": ([_P, _I32, _I32, _P, _P], ctypes.c_int),
     "dtb_sync": ([_P], ctypes.c_int),
     "dtb_destroy": ([_P], None),
 }
@@ -121,7 +122,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 9:
+    if lib.dtb_abi_version() != 10:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -207,6 +208,14 @@ __global__ __launch_bounds__(1024) void k_topk(int n, int k, const float* __rest
   }
   for (int q = threadIdx.x; q < k; q += 1024) idx[q] = si[q];
 }
+
+constexpr int kTopkMax = 4096;  // scores one selection sorts in LDS
+
+// Staging area of dtb_topk_noalloc: the n scores of a call, then the k
+// selected indices.  One copy per GPU the library runs on, held until the
+// process ends.  Host code never uses this name as an address: it takes the
+// device address from hipGetSymbolAddress (scratch_on) instead.
+static __device__ __align__(256) uint32_t scratch[2 * kTopkMax];
 
 }  // namespace
 
@@ -492,29 +501,89 @@ dtb_status dtb_mlp_train_step(dtb_mlp* h, const float* X, const float* T, int32_
 }
 
 dtb_status dtb_topk(const float* score, int32_t n, int32_t k, int32_t* idx, void* hip_stream, int on_device) {
-  if (!score || !idx || n < 1 || n > 4096 || k < 1 || k > n)
+  if (!score || !idx || n < 1 || n > kTopkMax || k < 1 || k > n)
     return mfail(DTB_ERR_INVALID, "top-k needs 1 <= k <= n <= 4096");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (on_device) {
+    hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, s, n, k, score, idx);
+    MLP_HIP(hipGetLastError());
+    return DTB_OK;
+  }
   float* ds = nullptr;
   int32_t* di = nullptr;
-  const float* sp = score;
-  int32_t* ip = idx;
-  if (!on_device) {
-    MLP_HIP(hipMalloc(&ds, size_t(n) * 4));
-    MLP_HIP(hipMalloc(&di, size_t(k) * 4));
-    MLP_HIP(hipMemcpyAsync(ds, score, size_t(n) * 4, hipMemcpyHostToDevice, s));
-    sp = ds;
-    ip = di;
+  hipError_t e = hipMalloc(&ds, size_t(n) * 4);
+  if (e == hipSuccess) e = hipMalloc(&di, size_t(k) * 4);
+  if (e == hipSuccess) e = hipMemcpyAsync(ds, score, size_t(n) * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, s, n, k, ds, di);
+    e = hipGetLastError();
   }
-  hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, s, n, k, sp, ip);
-  hipError_t e = hipGetLastError();
-  if (!on_device) {
-    if (e == hipSuccess) e = hipMemcpyAsync(idx, di, size_t(k) * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(ds);
-    (void)hipFree(di);
-  }
+  if (e == hipSuccess) e = hipMemcpyAsync(idx, di, size_t(k) * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (ds) (void)hipFree(ds);
+  if (di) (void)hipFree(di);
   if (e != hipSuccess) return mfail(DTB_ERR_HIP, std::string("top-k: ") + hipGetErrorString(e));
+  return DTB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices] = {};
+
+// The device address of `scratch` on `dev`, looked up once per device with
+// that device current (each GPU holds its own copy at its own address).
+hipError_t scratch_on(int dev, uint32_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_at[dev] = p;
+  }
+  *out = static_cast<uint32_t*>(g_scratch_at[dev]);
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+dtb_status dtb_topk_noalloc(const float* score, int32_t n, int32_t k, int32_t* idx, void* hip_stream) {
+  if (!score || !idx) return mfail(DTB_ERR_INVALID, "top-k (no allocation): score and idx must not be NULL");
+  if (n < 1 || k < 1 || k > n) return mfail(DTB_ERR_INVALID, "top-k (no allocation) needs 1 <= k <= n");
+  if (n > kTopkMax)
+    return mfail(DTB_ERR_INVALID, "top-k (no allocation): n = " + std::to_string(n) +
+                                      " exceeds the 4096 scores its static staging area holds");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int dev = -1;
+  hipError_t e = s ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+  uint32_t* base = nullptr;
+  if (e == hipSuccess) e = scratch_on(dev, &base);
+  if (e != hipSuccess) return mfail(DTB_ERR_HIP, std::string("top-k (no allocation): ") + hipGetErrorString(e));
+  float* ds = reinterpret_cast<float*>(base);            // [n] scores
+  int32_t* di = reinterpret_cast<int32_t*>(base + kTopkMax);  // [k] indices
+  e = hipMemcpyAsync(ds, score, size_t(n) * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_topk, dim3(1), dim3(1024), 0, s, n, k, ds, di);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(idx, di, size_t(k) * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return mfail(DTB_ERR_HIP, std::string("top-k (no allocation): ") + hipGetErrorString(e));
   return DTB_OK;
 }
 

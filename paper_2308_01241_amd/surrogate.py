@@ -77,3 +77,14 @@ def topk(scores, k: int) -> np.ndarray:
     idx = np.zeros(k, dtype=np.int32)
     check(lib.dtb_topk(_ptr(s), s.size, int(k), _ptr(idx), None, 0))
     return idx
+
+
+def topk_noalloc(scores, k: int, stream=None) -> np.ndarray:
+    """topk through the entry point that allocates no device memory (its
+    scores and indices pass through the library's static staging area)."""
+    lib = load()
+    s = _f32(scores).ravel()
+    idx = np.zeros(k, dtype=np.int32)
+    h = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    check(lib.dtb_topk_noalloc(_ptr(s), s.size, int(k), _ptr(idx), h))
+    return idx

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_bitmap_words(lib):
-    assert lib.dtb_abi_version() == 9
+    assert lib.dtb_abi_version() == 10
     assert [lib.dtb_bitmap_words(n) for n in (0, 1, 32, 33, 64)] == [0, 1, 1, 2, 2]
     assert isinstance(lib.dtb_last_error(), bytes)
 
@@ -175,3 +175,13 @@ def test_autotune_rejects_bad_arguments_before_any_device_call(lib):
     assert lib.dtb_autotune(d, 1, None, None, None, 0, -1, 10, ctypes.byref(res)) == -1   # negative burn-in
     assert lib.dtb_autotune(d, 1, None, None, None, 0, 0, 10, None) == -1
     assert b"candidate" in lib.dtb_last_error() or b"burnin" in lib.dtb_last_error() or lib.dtb_last_error()
+
+
+def test_topk_noalloc_validates_before_any_device_call(lib):
+    s = np.zeros(4097, np.float32)
+    idx = np.zeros(8, np.int32)
+    assert lib.dtb_topk_noalloc(s.ctypes.data, 4097, 1, idx.ctypes.data, None) == -1
+    assert b"4096" in lib.dtb_last_error()
+    assert lib.dtb_topk_noalloc(None, 4, 1, idx.ctypes.data, None) == -1
+    assert lib.dtb_topk_noalloc(s.ctypes.data, 4, 5, idx.ctypes.data, None) == -1
+    assert lib.dtb_topk_noalloc(s.ctypes.data, 0, 0, idx.ctypes.data, None) == -1
