@@ -63,16 +63,16 @@ def log(*a):
 
 
 def gather_bytes(nnz: int, n: int, max_delay: int) -> float:
-    """Algorithmic bytes of one launch of the delivery-test kernel: 5 B of
-    index + delay per synapse and the D+1 delayed spike bits per neuron."""
+    """Algorithmic bytes of the delivery tests: 5 B of index + delay per
+    synapse and the D+1 delayed spike bits per neuron."""
     return 5.0 * nnz + n * (max_delay + 1) / 8.0
 
 
-def sums_bytes(nnz: int, n: int, events: float, w_bytes: int) -> float:
-    """Algorithmic bytes of one launch of the sums kernel: row pointers
-    (8 B per row), the one delivery bit per synapse it reads, the weight of
-    each delivered event and the four gates read and written."""
-    return 8.0 * n + nnz / 8.0 + w_bytes * events + 32.0 * n
+def rows_bytes(n: int, events: float, w_bytes: int) -> float:
+    """Algorithmic bytes of the row sums that follow the delivery tests:
+    row pointers (8 B per row), the weight of each delivered event and the
+    four gates read and written."""
+    return 8.0 * n + w_bytes * events + 32.0 * n
 
 
 def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) -> float:
@@ -87,7 +87,7 @@ def _spread(xs):
     return {"median": float(np.median(xs)), "min": float(xs[0]), "max": float(xs[-1]), "n": len(xs)}
 
 
-def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0), ou=None, keep_bits=False):
+def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0), ou=None, keep_bits=False):
     """One rate point: burn in to the stationary rate, save, then `reps`
     timed repetitions of `steps` steps from that same state."""
     import torch
@@ -98,7 +98,7 @@ def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0), o
     pre = burnin + warmup
     rec = pre + steps if keep_bits else max(steps, 16)
     g = dtb.Net(net, wtype=wtype, record_steps=rec, stream=torch.cuda.current_stream(),
-                bundle_syn=shape[0], unroll=shape[1])
+                bundle_syn=shape[0], unroll=shape[1], fuse=shape[2])
     torch.cuda.synchronize()
     log(f"[bench] {rate} Hz {wtype}: created in {time.time() - t0:.1f}s; burn-in {burnin} + warmup {warmup}")
     if ou is not None:
@@ -214,7 +214,7 @@ def ensemble_members(n_members: int = 64):
     return members, gains
 
 
-def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: int = 200):
+def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: int = 200, members_too: bool = True):
     """The batched ensemble: n_members independent networks of 50k-400k
     neurons (20 regions each, per-(member, region, channel) gains), advanced
     together by replays of one captured HIP graph, against the same members
@@ -231,7 +231,8 @@ def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: 
         f"{time.time() - t0:.1f}s")
     shape = autotune.lookup(n_tot, s_tot, n_members, "f32", max(m.max_delay for m in members))
     stream = torch.cuda.current_stream()
-    g = dtb.Net.batch(members, record_steps=64, stream=stream, bundle_syn=shape[0], unroll=shape[1])
+    g = dtb.Net.batch(members, record_steps=64, stream=stream, bundle_syn=shape[0], unroll=shape[1],
+                      fuse=shape[2])
     g.set_gains(gains.reshape(-1, 4))
     g.run(warmup)
     g.sync()
@@ -250,6 +251,8 @@ def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: 
                "rtf": ms * 1e-3 / (steps * 1e-3),
                "mean_rate_hz": (c1["spikes"] - c0["spikes"]) / (n_tot * steps * 1e-3),
                "bold_finite": bool(np.isfinite(bold).all())}
+    if not members_too:
+        return {"workload": f"ensemble: {n_members} members, {n_tot} neurons, {s_tot} synapses", "batched": batched}
     # the plain path, one member at a time, same gains, graph replays too
     ev_m, ms_m = 0, 0.0
     for m, nw in enumerate(members):
@@ -267,7 +270,7 @@ def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: 
         h.close()
     single = {"events_per_s": ev_m / (ms_m * 1e-3), "ms_per_step_all_members": ms_m / per_member_steps,
               "steps_per_member": per_member_steps}
-    return {"gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None},
+    return {"gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None, "fuse": shape[2] or None},
             "workload": f"ensemble: {n_members} members of 50k-400k neurons (20 regions each), "
                         f"{n_tot} neurons, {s_tot} synapses, per-region channel gains, 7 Hz drive, "
                         f"{steps} steps under one captured HIP graph",
@@ -374,6 +377,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="search the gather launch shape, store it")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16, OU, split and batched runs")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the batched ensemble (no member-by-member comparison), e.g. under a kernel trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's partition; --gpus {args.gpus} is not supported "
@@ -390,6 +395,9 @@ def main():
     if args.calibrate_copy:
         print(json.dumps(calibrate_copy()), flush=True)
         return
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": run_batched(args.batch_steps, 200, members_too=False)}), flush=True)
+        return
     rates = [int(x) for x in args.rates.split(",")]
     t0 = time.time()
     net = netgen.make_network(netgen.partition_spec(n=args.n, rate_hz=rates[0]))
@@ -404,19 +412,19 @@ def main():
             r = autotune.tune([net], wtype=wt, record_steps=64, cache_path=autotune.CACHE, burnin=args.burnin,
                               steps=40, stream=torch.cuda.current_stream())
             log(f"[autotune] partition {wt}: {r}")
-            out[f"partition/{wt}"] = {**r, "tried": {f"{b}/{u}": v for (b, u), v in r["tried"].items()}}
+            out[f"partition/{wt}"] = {**r, "tried": {f"{b}/{u}/{f}": v for (b, u, f), v in r["tried"].items()}}
         del net
         members, gains = ensemble_members(64)
         for wt in ("f32", "bf16"):
             r = autotune.tune(members, wtype=wt, record_steps=64, cache_path=autotune.CACHE, burnin=200, steps=40,
                               stream=torch.cuda.current_stream())
             log(f"[autotune] ensemble {wt}: {r}")
-            out[f"ensemble/{wt}"] = {**r, "tried": {f"{b}/{u}": v for (b, u), v in r["tried"].items()}}
+            out[f"ensemble/{wt}"] = {**r, "tried": {f"{b}/{u}/{f}": v for (b, u, f), v in r["tried"].items()}}
         print(json.dumps({"autotune": out}), flush=True)
         return
     n_neu, n_syn, n_del = net.n, net.nnz, net.max_delay
     shape = autotune.lookup(n_neu, n_syn, 1, args.wtype, n_del)
-    log(f"[bench] gather shape (bundle_syn, unroll): {shape} (0 = library default)")
+    log(f"[bench] gather shape (bundle_syn, unroll, fuse): {shape} (0 = library default)")
     res = {}
     want_split = not args.no_forms and args.wtype == "f32"
     for r in rates:
@@ -428,20 +436,30 @@ def main():
     wb = 2 if args.wtype == "bf16" else 4
     per = {k: v["ms"] / max(1, v["launches"]) for k, v in head["kernels"].items()}
     ev_step = head["events"] / args.steps
-    B = gather_bytes(n_syn, n_neu, n_del)
+    # the dominant kernel: the gather - its delivery tests, plus the row sums
+    # when they run in its workgroups (fuse 1); with separate sums (fuse 2)
+    # k_sums gets its own line (it reads the hit bits the gather wrote)
+    fused = per.get("sums", 0.0) == 0.0
+    Bg = gather_bytes(n_syn, n_neu, n_del)
+    Br = rows_bytes(n_neu, ev_step, wb)
+    B = Bg + Br if fused else Bg
     achieved = B / (per["gather"] * 1e-3) / 1e9
-    Bs = sums_bytes(n_syn, n_neu, ev_step, wb)
     Bt = step_bytes(n_syn, n_neu, n_del, ev_step, wb)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_gather",
+            "row_sums_in_gather": fused,
             "algorithmic_bytes_per_launch": B,
-            "hit_bits_written_per_launch": n_syn / 8.0,
             "avg_launch_ms": per["gather"],
-            "sums": {"algorithmic_bytes_per_launch": Bs, "avg_launch_ms": per["sums"],
-                     "achieved": round(Bs / (per["sums"] * 1e-3) / 1e9, 1)},
             "step": {"algorithmic_bytes": Bt, "ms": head["ms_per_step"],
                      "achieved": round(Bt / (head["ms_per_step"] * 1e-3) / 1e9, 1),
                      "frac": round(Bt / (head["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    if fused:
+        roof["parts"] = {"delivery_tests": Bg, "row_sums": Br}
+    else:
+        Bs = Br + n_syn / 8.0  # the sums also read one hit bit per synapse
+        roof["hit_bits_written_per_launch"] = n_syn / 8.0
+        roof["sums"] = {"kernel": "k_sums", "algorithmic_bytes_per_launch": Bs, "avg_launch_ms": per["sums"],
+                        "achieved": round(Bs / (per["sums"] * 1e-3) / 1e9, 1)}
     forms = {}
     if not args.no_forms and args.wtype == "f32":
         bf = {}
@@ -453,7 +471,6 @@ def main():
                           "mean_rate_hz": x["mean_rate_hz"],
                           "speedup_events_per_s": x["events_per_s"] / res[r]["events_per_s"],
                           "gather_ms": kx["gather"]["ms"] / max(1, kx["gather"]["launches"]),
-                          "sums_ms": kx["sums"]["ms"] / max(1, kx["sums"]["launches"]),
                           "rate_error_vs_f32": rate_error(x["region_rates"], res[r]["region_rates"])}
             log(f"[bench] bf16 {r} Hz: {json.dumps(bf[str(r)])}")
         forms["bf16"] = bf
@@ -462,7 +479,7 @@ def main():
         forms["ou_background"] = {"mu_sigma_tau_ms": list(OU_BACKGROUND), "events_per_s": ou["events_per_s"],
                                   "ms_per_step": ou["ms_per_step"], "rtf": ou["rtf"],
                                   "mean_rate_hz": ou["mean_rate_hz"],
-                                  "sums_ms": ou["kernels"]["sums"]["ms"] / max(1, ou["kernels"]["sums"]["launches"])}
+                                  "gather_ms": ou["kernels"]["gather"]["ms"] / max(1, ou["kernels"]["gather"]["launches"])}
         log(f"[bench] ou background: {json.dumps(forms['ou_background'])}")
         bits = head.pop("bits")
         net.bg_lambda = netgen.PARTITION_LAMBDA[r0]
@@ -492,7 +509,7 @@ def main():
                                   f"{args.burnin} burn-in steps)",
                       "global_batch": 1, "seq_len": args.steps, "parallelism": "single-gpu"},
            "rtf": head["rtf"], "ms_per_step_reps": head["ms_per_step_reps"], "roofline": roof, "cpu_baseline": cpu,
-           "gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None},
+           "gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None, "fuse": shape[2] or None},
            "rates": {str(r): point_summary(res[r]) for r in rates},
            "forms": forms or None,
            "kernels_ms_per_step": per}

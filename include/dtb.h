@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 10
+#define DTB_ABI_VERSION 12
 
 typedef enum {
   DTB_OK = 0,
@@ -108,6 +108,11 @@ typedef struct dtb_desc {
   int32_t gather_unroll;     /* launch shape of the gather: lookup tiles per wavefront per
                                 round, 1 .. 3 (0 = library default, 3).  A tuning knob:
                                 results do not depend on it */
+  int32_t gather_fuse;       /* where the row sums run: 1 = in the gather's workgroups, from
+                                the bundle's hit bitmap still in LDS; 2 = in a separate
+                                kernel over the hit buffer (always so while a remote in-edge
+                                block is set); 0 = library default, 1.  A tuning knob: both
+                                add the same terms in the same order */
 } dtb_desc;
 
 /* ------------------------------------------------------------ library */
@@ -294,13 +299,15 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps);
  * or n_cands = 0 for the library's list: the largest bundle and the sizes
  * whose bundle count fills whole rounds of the GPU's compute units), times
  * `steps` steps with hipEvents for each lookup-tiles-per-round value 1..3
- * (gather_unroll), and reports the fastest.  Every timing starts from the
+ * (gather_unroll) and each placement of the row sums 1..2 (gather_fuse),
+ * and reports the fastest.  Every timing starts from the
  * same state - the first candidate's state after `burnin` steps, saved once
  * and loaded before each timing - so all candidates time the same steps
  * (the shapes change only the schedule, never a result).  The members'
- * own gather_bundle_syn / gather_unroll are ignored.
+ * own gather_bundle_syn / gather_unroll / gather_fuse are ignored.
  * cache_path (may be NULL): a JSON file of tuned shapes keyed by
- * "<gfx arch>|n=..,nnz=..,members=..,w=<f32|bf16>,D=..", one entry per line;
+ * "<gfx arch>|n=..,nnz=..,members=..,w=<f32|bf16>,D=..", one entry per line
+ * ({"bundle_syn": b, "unroll": u, "fuse": f, "ms_per_step": ms});
  * a key already present is returned without timing (from_cache = 1),
  * otherwise the winner is added (the file is rewritten through a temporary
  * file; DTB_ERR_INVALID if it cannot be written).  Work runs on hip_stream
@@ -309,13 +316,14 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps);
  * stepping the candidate networks returns. */
 #define DTB_TUNE_MAX_BUNDLES 8
 typedef struct dtb_tune_result {
-  int32_t bundle_syn, unroll;   /* the fastest shape */
+  int32_t bundle_syn, unroll, fuse; /* the fastest shape */
   float ms_per_step;            /* its time per step (from the cache when from_cache) */
   int32_t from_cache;           /* 1: taken from cache_path without timing */
-  int32_t n_tried;              /* shapes timed: candidates x 3 */
-  int32_t tried_bundle[3 * DTB_TUNE_MAX_BUNDLES];
-  int32_t tried_unroll[3 * DTB_TUNE_MAX_BUNDLES];
-  float tried_ms[3 * DTB_TUNE_MAX_BUNDLES];
+  int32_t n_tried;              /* shapes timed: candidates x 3 x 2 */
+  int32_t tried_bundle[6 * DTB_TUNE_MAX_BUNDLES];
+  int32_t tried_unroll[6 * DTB_TUNE_MAX_BUNDLES];
+  int32_t tried_fuse[6 * DTB_TUNE_MAX_BUNDLES];
+  float tried_ms[6 * DTB_TUNE_MAX_BUNDLES];
 } dtb_tune_result;
 dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_stream, const char* cache_path,
                         const int32_t* bundle_cands, int32_t n_cands, int32_t burnin, int32_t steps,
@@ -343,6 +351,11 @@ dtb_status dtb_mlp_create(int32_t n_in, int32_t hidden, int32_t n_hidden, int32_
 int64_t dtb_mlp_num_params(const dtb_mlp* mlp);
 /* get = 1 copies the parameters out; get = 0 sets them (and resets Adam). */
 dtb_status dtb_mlp_params(dtb_mlp* mlp, float* buf, int get, int on_device);
+/* fp32 = 1: every matrix operand stays FP32 (MFMA 16x16x4 f32; same tiles,
+ * epilogues and accumulation order) - the check of the kernels' logic
+ * against an unrounded reference; fp32 = 0 (the default): bfloat16
+ * operands.  Parameters and Adam state are unaffected. */
+dtb_status dtb_mlp_set_operands(dtb_mlp* mlp, int fp32);
 /* Y [batch][n_out] = f(X [batch][n_in]); on_device tells where X and Y live. */
 dtb_status dtb_mlp_forward(dtb_mlp* mlp, const float* X, int32_t batch, float* Y, int on_device);
 /* loss = mean over all entries of (f(X) - T)^2; grads [num_params] its

@@ -37,18 +37,21 @@ class Desc(ctypes.Structure):
                 ("bg_w", ctypes.c_float), ("bg_lambda", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("wtype", ctypes.c_int32), ("record_steps", ctypes.c_int32),
                 ("gather_bundle_syn", ctypes.c_int32),
-                ("gather_unroll", ctypes.c_int32)]
+                ("gather_unroll", ctypes.c_int32),
+                ("gather_fuse", ctypes.c_int32)]
 
 
 TUNE_MAX_BUNDLES = 8
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("bundle_syn", ctypes.c_int32), ("unroll", ctypes.c_int32), ("ms_per_step", ctypes.c_float),
+    _fields_ = [("bundle_syn", ctypes.c_int32), ("unroll", ctypes.c_int32), ("fuse", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_float),
                 ("from_cache", ctypes.c_int32), ("n_tried", ctypes.c_int32),
-                ("tried_bundle", ctypes.c_int32 * (3 * TUNE_MAX_BUNDLES)),
-                ("tried_unroll", ctypes.c_int32 * (3 * TUNE_MAX_BUNDLES)),
-                ("tried_ms", ctypes.c_float * (3 * TUNE_MAX_BUNDLES))]
+                ("tried_bundle", ctypes.c_int32 * (6 * TUNE_MAX_BUNDLES)),
+                ("tried_unroll", ctypes.c_int32 * (6 * TUNE_MAX_BUNDLES)),
+                ("tried_fuse", ctypes.c_int32 * (6 * TUNE_MAX_BUNDLES)),
+                ("tried_ms", ctypes.c_float * (6 * TUNE_MAX_BUNDLES))]
 
 
 # every symbol include/dtb.h declares, with its ctypes signature
@@ -91,6 +94,7 @@ SIGNATURES = {
     "dtb_mlp_create": ([_I32, _I32, _I32, _I32, ctypes.c_uint64, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "dtb_mlp_num_params": ([_P], _I64),
     "dtb_mlp_params": ([_P, _P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "dtb_mlp_set_operands": ([_P, ctypes.c_int], ctypes.c_int),
     "dtb_mlp_forward": ([_P, _P, _I32, _P, ctypes.c_int], ctypes.c_int),
     "dtb_mlp_grad": ([_P, _P, _P, _I32, _P, _P, ctypes.c_int], ctypes.c_int),
     "dtb_mlp_train_step": ([_P, _P, _P, _I32, ctypes.c_float, _P, ctypes.c_int], ctypes.c_int),
@@ -122,7 +126,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 10:
+    if lib.dtb_abi_version() != 12:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

@@ -3,10 +3,12 @@ mesoscopic data assimilation idea of Sec. V-E, on one GPU).
 
 Pipeline, all on the GPU through the C ABI:
   1. data   - the batched ensemble runs from rest one window of `window`
-              steps at unit gains, then one at fresh per-population channel
-              gains ~ N(1, 0.2^2) (clipped at 0); a sample maps (gains,
-              population rates of the first window) -> (population rates of
-              the second window, BOLD at its end);
+              steps at unit gains, then `segments` chained windows, each at
+              fresh per-population channel gains ~ N(1, 0.2^2) (clipped at
+              0); a sample maps (gains, population rates of the window
+              before) -> (population rates of the window, BOLD at its end);
+              the default run (157 runs x 10 windows x 64 members) gives
+              100,480 training samples;
   2. train  - the MFMA surrogate MLP learns that map (z-scored, Adam, MSE);
   3. screen - against a synthetic twin target (a member network whose gains
               are hidden: one window at unit gains, then one at the hidden
@@ -46,7 +48,7 @@ class Setup:
     lo: int = 50_000           # member sizes ~ U[lo, hi]
     hi: int = 400_000
     regions: int = 20          # populations per member
-    window: int = 400          # steps per window (dt = 1 ms)
+    window: int = 200          # steps per window (dt = 1 ms)
     rate_hz: int = 7           # background drive of the members (about 10 Hz)
     target_n: int = 200_000    # size of the twin target
 
@@ -63,11 +65,15 @@ def window_rates(net, S: Setup):
     return net.region_rates(net.t - S.window, net.t).reshape(-1, S.regions)
 
 
-def generate(net, S: Setup, n_runs: int, rng):
-    """n_runs x members samples, each run the way the re-simulation check runs a
-    proposal: from rest, one window at unit gains, then one window at fresh
-    gains.  Returns X [samples, 5 R] (gains, rates of the first window) and
-    Y [samples, 2 R] (rates of the second window, BOLD at its end)."""
+def generate(net, S: Setup, n_runs: int, rng, segments: int = 1):
+    """n_runs x segments x members samples.  Each run starts from rest with
+    one window at unit gains, then `segments` chained windows, each at fresh
+    per-member gains ~ N(1, 0.2^2) clipped at 0 (network and hemodynamic
+    state carry over from window to window).  A sample maps (a member's
+    gains in the window, its population rates over the window before) to
+    (its rates over the window, BOLD at the window's end).  The first
+    window of a run is exactly how the re-simulation check runs a proposal.
+    Returns X [samples, 5 R] and Y [samples, 2 R]."""
     M, R = net.n_members, S.regions
     X, Y = [], []
     for run in range(n_runs):
@@ -75,13 +81,15 @@ def generate(net, S: Setup, n_runs: int, rng):
         net.set_gains(np.ones((M * R, 4), dtype=np.float32))
         net.run(S.window)
         prev = window_rates(net, S)
-        g = np.clip(rng.normal(1.0, GAIN_SD, (M, R, 4)), 0.0, None).astype(np.float32)
-        net.set_gains(g.reshape(-1, 4))
-        net.run(S.window)
-        rates = window_rates(net, S)
-        bold = net.bold().reshape(M, R)
-        X.append(np.concatenate([g.reshape(M, -1), prev], axis=1))
-        Y.append(np.concatenate([rates, 1e3 * bold], axis=1))  # BOLD in 1e-3 units
+        for _ in range(segments):
+            g = np.clip(rng.normal(1.0, GAIN_SD, (M, R, 4)), 0.0, None).astype(np.float32)
+            net.set_gains(g.reshape(-1, 4))
+            net.run(S.window)
+            rates = window_rates(net, S)
+            bold = net.bold().reshape(M, R)
+            X.append(np.concatenate([g.reshape(M, -1), prev], axis=1))
+            Y.append(np.concatenate([rates, 1e3 * bold], axis=1))  # BOLD in 1e-3 units
+            prev = rates
         if (run + 1) % 16 == 0 or run + 1 == n_runs:
             log(f"[data] run {run + 1}/{n_runs}: {len(X) * M} samples")
     return np.concatenate(X).astype(np.float32), np.concatenate(Y).astype(np.float32)
@@ -235,9 +243,10 @@ def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096,
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--members", type=int, default=64)
-    ap.add_argument("--window", type=int, default=400)
-    ap.add_argument("--runs", type=int, default=192)
-    ap.add_argument("--test-runs", type=int, default=32)
+    ap.add_argument("--window", type=int, default=200)
+    ap.add_argument("--runs", type=int, default=157)
+    ap.add_argument("--test-runs", type=int, default=16)
+    ap.add_argument("--segments", type=int, default=10, help="chained gain windows per run")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--iters", type=int, default=8)
     ap.add_argument("--seeds", type=str, default="0,1,2")
@@ -255,16 +264,17 @@ def main(argv=None):
     del members
     log(f"[data] ensemble: {net.n} neurons, {net.n_members} members, built in {time.time() - t0:.1f}s")
     tic = time.perf_counter()
-    X, Y = generate(net, S, a.runs, np.random.default_rng(32))
+    X, Y = generate(net, S, a.runs, np.random.default_rng(32), segments=a.segments)
     gen_s = time.perf_counter() - tic
-    Xt, Yt = generate(net, S, a.test_runs, np.random.default_rng(33))
+    Xt, Yt = generate(net, S, a.test_runs, np.random.default_rng(33), segments=a.segments)
     net.close()
     tic = time.perf_counter()
     m, sx, sy = train(X, Y, epochs=a.epochs)
     train_s = time.perf_counter() - tic
     err = evaluate(m, sx, sy, Xt, Yt, S.regions)
     log(f"[train] held-out error: {json.dumps(err)}")
-    rep = {"setup": dataclasses.asdict(S), "samples": int(len(X)), "test_samples": int(len(Xt)),
+    rep = {"setup": dataclasses.asdict(S), "segments_per_run": a.segments, "runs": a.runs,
+           "test_runs": a.test_runs, "samples": int(len(X)), "test_samples": int(len(Xt)),
            "mean_rate_hz": float(Y[:, :S.regions].mean()),
            "generate_s": gen_s, "train_s": train_s, "held_out": err, "screen": {}}
     target = netgen.make_network(netgen.ensemble_member_spec(41, S.target_n, rate_hz=S.rate_hz,

@@ -1,6 +1,6 @@
 """Launch-shape autotuner of the gather (binding of dtb_autotune).
 
-Two knobs, neither of which changes any result (the summation order is each
+Three knobs, none of which changes any result (the summation order is each
 row's CSR order either way):
 
 * the bundle size (most synapses per workgroup): it sets the LDS hit bitmap
@@ -9,7 +9,11 @@ row's CSR order either way):
   once per delay); sizes that make the bundle count a whole number of
   rounds over the CUs avoid a partly idle last round;
 * the lookup tiles per wavefront per round (1, 2 or 3): bytes in flight per
-  wavefront against registers.
+  wavefront against registers;
+* where the row sums run (1: in the gather's workgroups from the LDS hit
+  bitmap, 2: in a separate kernel over the hit buffer): one launch and no
+  hit-buffer traffic against a phase per bundle in which its CU issues
+  only the rows' random weight loads.
 
 The library times each candidate on the real network with HIP events, all
 from one burned-in state, and caches the winner in a JSON file keyed by GPU
@@ -43,21 +47,22 @@ def _arch() -> str:
 
 
 def lookup(n, nnz, n_members=1, wtype="f32", max_delay=20, path=CACHE, arch=None):
-    """Cached (bundle_syn, unroll) for this shape, or (0, 0) (library defaults)."""
+    """Cached (bundle_syn, unroll, fuse) for this shape, or (0, 0, 0) (the
+    library defaults)."""
     try:
         with open(path) as f:
             db = json.load(f)
     except (OSError, ValueError):
-        return 0, 0
+        return 0, 0, 0
     ent = db.get(shape_key(arch or _arch(), n, nnz, n_members, wtype, max_delay))
-    return (int(ent["bundle_syn"]), int(ent["unroll"])) if ent else (0, 0)
+    return (int(ent["bundle_syn"]), int(ent["unroll"]), int(ent.get("fuse", 0))) if ent else (0, 0, 0)
 
 
 def tune(members, wtype: str = "f32", record_steps: int = 64, cache_path=CACHE, bundles=(), burnin: int = 0,
          steps: int = 20, stream=None) -> dict:
     """dtb_autotune over the network(s) `members` (one: a plain partition,
     several: a batch).  Returns the winning shape, its ms per step, whether
-    it came from the cache, and every timed (bundle_syn, unroll) -> ms."""
+    it came from the cache, and every timed (bundle_syn, unroll, fuse) -> ms."""
     lib = load()
     members = list(members)
     descs = (Desc * len(members))()
@@ -75,6 +80,8 @@ def tune(members, wtype: str = "f32", record_steps: int = 64, cache_path=CACHE, 
                            _ptr(cands) if cands.size else None, int(cands.size), int(burnin), int(steps),
                            ctypes.byref(res)))
     del keep
-    tried = {(int(res.tried_bundle[q]), int(res.tried_unroll[q])): float(res.tried_ms[q]) for q in range(res.n_tried)}
-    return {"bundle_syn": int(res.bundle_syn), "unroll": int(res.unroll), "ms_per_step": float(res.ms_per_step),
+    tried = {(int(res.tried_bundle[q]), int(res.tried_unroll[q]), int(res.tried_fuse[q])): float(res.tried_ms[q])
+             for q in range(res.n_tried)}
+    return {"bundle_syn": int(res.bundle_syn), "unroll": int(res.unroll), "fuse": int(res.fuse),
+            "ms_per_step": float(res.ms_per_step),
             "from_cache": bool(res.from_cache), "tried": tried}

@@ -184,6 +184,7 @@ dtb_status validate(const dtb_desc* s) {
   if (s->gather_bundle_syn != 0 && (s->gather_bundle_syn < 4096 || s->gather_bundle_syn > kBundleMaxSyn))
     return fail(DTB_ERR_INVALID, "gather_bundle_syn must be 0 or in [4096, 2^20-1]");
   if (s->gather_unroll < 0 || s->gather_unroll > 3) return fail(DTB_ERR_INVALID, "gather_unroll must be 0 .. 3");
+  if (s->gather_fuse < 0 || s->gather_fuse > 2) return fail(DTB_ERR_INVALID, "gather_fuse must be 0 .. 2");
   if (!(s->dt_ms > 0.f) || !finite_f(s->dt_ms)) return fail(DTB_ERR_INVALID, "dt_ms must be finite and > 0");
   for (int u = 0; u < 4; ++u) {
     if (!(s->tau_ms[u] > 0.f) || !finite_f(s->tau_ms[u]))
@@ -555,6 +556,7 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
   d.member = desc->member;
   d.wtype = desc->wtype;
   d.unroll = desc->gather_unroll ? desc->gather_unroll : kGatherUnroll;
+  d.fuse = desc->gather_fuse ? desc->gather_fuse : 1;
   d.rec = desc->record_steps;
   d.slots = std::max(d.rec, d.max_delay) + 1;
   d.bg_w = desc->bg_w;
@@ -851,17 +853,21 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
     }
     if (e == hipSuccess) e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
     if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
+    // the gather workgroups also sum their rows (fuse == 1) unless a remote
+    // block is set: then both blocks' hit bits go to k_sums (local, then
+    // remote)
+    const bool fuse = !net->remote && d.fuse == 1;
     if (e == hipSuccess)
-      e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, net->stream); });
+      e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, fuse, net->stream); });
     if (e == hipSuccess && net->remote) {
       // J_inter after J_intra, once the remote spikes are in (the paper's
       // computing-thread order); its delivery tests OR into their own hit
       // buffer
       e = hipStreamWaitEvent(net->stream, net->join_ev, 0);
       if (e == hipSuccess)
-        e = timed(net, 5, [&] { return launch_gather(d, d.rem, d.rraster, d.rwords_pad, net->stream); });
+        e = timed(net, 5, [&] { return launch_gather(d, d.rem, d.rraster, d.rwords_pad, false, net->stream); });
     }
-    if (e == hipSuccess) e = timed(net, 3, [&] { return launch_sums(d, net->stream); });
+    if (e == hipSuccess && !fuse) e = timed(net, 3, [&] { return launch_sums(d, net->stream); });
     if (e == hipSuccess) e = timed(net, 4, [&] { return launch_finalize(d, net->stream); });
     if (e != hipSuccess) return hip_fail(net, e, "kernel launch");
     net->t = t + 1;
@@ -888,8 +894,8 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
     for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
       e = launch_neuron_update(d, nullptr, net->stream);
       if (e == hipSuccess) e = launch_compact(d, net->stream);
-      if (e == hipSuccess) e = launch_gather(d, d.loc, d.raster, d.words_pad, net->stream);
-      if (e == hipSuccess) e = launch_sums(d, net->stream);
+      if (e == hipSuccess) e = launch_gather(d, d.loc, d.raster, d.words_pad, d.fuse == 1, net->stream);
+      if (e == hipSuccess && d.fuse != 1) e = launch_sums(d, net->stream);
       if (e == hipSuccess) e = launch_finalize(d, net->stream);
     }
     hipGraph_t g = nullptr;
@@ -1397,12 +1403,13 @@ dtb_status dtb_load(dtb_net* net, const void* host_buf, size_t len) {
 namespace {
 
 struct TuneEntry {
-  int32_t bundle_syn = 0, unroll = 0;
+  int32_t bundle_syn = 0, unroll = 0, fuse = 0;
   double ms = 0.0;
 };
 
 // Cache file: one JSON object, one entry per line,
-//   "<arch>|n=<n>,nnz=<nnz>,members=<m>,w=<f32|bf16>,D=<D>": {"bundle_syn": b, "unroll": u, "ms_per_step": ms}
+//   "<arch>|n=<n>,nnz=<nnz>,members=<m>,w=<f32|bf16>,D=<D>":
+//       {"bundle_syn": b, "unroll": u, "fuse": f, "ms_per_step": ms}
 // Lines that do not parse are dropped when the file is rewritten.
 std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
   std::map<std::string, TuneEntry> db;
@@ -1415,8 +1422,8 @@ std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
     if (b == std::string::npos) continue;
     TuneEntry e;
     const char* rest = line.c_str() + b + 1;
-    if (std::sscanf(rest, " : {\"bundle_syn\": %d, \"unroll\": %d, \"ms_per_step\": %lf", &e.bundle_syn, &e.unroll,
-                    &e.ms) == 3)
+    if (std::sscanf(rest, " : {\"bundle_syn\": %d, \"unroll\": %d, \"fuse\": %d, \"ms_per_step\": %lf",
+                    &e.bundle_syn, &e.unroll, &e.fuse, &e.ms) == 4)
       db[line.substr(a + 1, b - a - 1)] = e;
   }
   return db;
@@ -1430,9 +1437,9 @@ bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& 
     f << "{\n";
     size_t q = 0;
     for (const auto& kv : db) {
-      char buf[160];
-      std::snprintf(buf, sizeof(buf), ": {\"bundle_syn\": %d, \"unroll\": %d, \"ms_per_step\": %.6f}",
-                    kv.second.bundle_syn, kv.second.unroll, kv.second.ms);
+      char buf[192];
+      std::snprintf(buf, sizeof(buf), ": {\"bundle_syn\": %d, \"unroll\": %d, \"fuse\": %d, \"ms_per_step\": %.6f}",
+                    kv.second.bundle_syn, kv.second.unroll, kv.second.fuse, kv.second.ms);
       f << "\"" << kv.first << "\"" << buf << (++q < db.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -1480,6 +1487,7 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
     if (it != db.end()) {
       out->bundle_syn = it->second.bundle_syn;
       out->unroll = it->second.unroll;
+      out->fuse = it->second.fuse;
       out->ms_per_step = float(it->second.ms);
       out->from_cache = 1;
       return DTB_OK;
@@ -1514,6 +1522,7 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
     for (auto& x : ds) {
       x.gather_bundle_syn = cands[c];
       x.gather_unroll = 0;
+      x.gather_fuse = 0;
     }
     dtb_net* net = nullptr;
     st = n_members == 1 ? dtb_create(ds.data(), hip_stream, &net) : dtb_create_batch(ds.data(), n_members, hip_stream, &net);
@@ -1526,8 +1535,10 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
         st = dtb_save(net, saved.data(), saved.size(), &used);
       }
     }
-    for (int32_t u = 1; u <= 3 && st == DTB_OK; ++u) {
+    for (int32_t v = 0; v < 6 && st == DTB_OK; ++v) {
+      const int32_t u = 1 + v % 3, fz = 1 + v / 3;
       net->d.unroll = u;
+      net->d.fuse = fz;
       drop_graph(net);
       if ((st = dtb_load(net, saved.data(), saved.size()))) break;
       e = hipEventRecord(ea, net->stream);
@@ -1543,10 +1554,12 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
       const int q = out->n_tried++;
       out->tried_bundle[q] = cands[c];
       out->tried_unroll[q] = u;
+      out->tried_fuse[q] = fz;
       out->tried_ms[q] = ms / float(steps);
       if (q == 0 || out->tried_ms[q] < out->ms_per_step) {
         out->bundle_syn = cands[c];
         out->unroll = u;
+        out->fuse = fz;
         out->ms_per_step = out->tried_ms[q];
       }
     }
@@ -1557,7 +1570,7 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
   if (st) return st;
   if (cache_path) {
     auto db = read_tune_cache(cache_path);
-    db[key] = TuneEntry{out->bundle_syn, out->unroll, double(out->ms_per_step)};
+    db[key] = TuneEntry{out->bundle_syn, out->unroll, out->fuse, double(out->ms_per_step)};
     if (!write_tune_cache(cache_path, db))
       return fail(DTB_ERR_INVALID, std::string("cannot write the tuning cache ") + cache_path);
   }

@@ -134,6 +134,7 @@ struct DeviceNet {
   int32_t n_regions = 0, max_delay = 0, n_ptypes = 0, member = 0;
   int32_t wtype = 0, rec = 0;       // rec = record_steps
   int32_t unroll = 3;               // gather lookup tiles per wavefront per round (1 .. 3)
+  int32_t fuse = 1;                 // row sums in the gather's workgroups (1) or in k_sums (2)
   int32_t slots = 0;                // spike-bitmap ring slots: max(rec, D) + 1
   int32_t poisson_K = 0, poisson_cap = 1;
   int64_t compact_blocks = 0;
@@ -195,8 +196,12 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
 hipError_t launch_compact_read(const DeviceNet& d, const int64_t* at, int32_t* ids, int32_t* count,
                                uint64_t* status, uint32_t* ticket, int64_t* total, hipStream_t s);
 hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
+// delivery tests of one in-edge block; with fuse_sums the same workgroups
+// then sum their bundles' rows and update background and gates (no k_sums
+// needed: the partition has no other block), otherwise the hit bits go to
+// the block's hit buffer for launch_sums
 hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
-                         hipStream_t s);
+                         bool fuse_sums, hipStream_t s);
 // observation-error variances of one EnKF analysis, passed by value
 constexpr int kEnkfMaxObs = 64;
 struct EnkfVar {

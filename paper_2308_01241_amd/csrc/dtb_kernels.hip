@@ -9,11 +9,13 @@
 //                    popcounts, block scan, decoupled look-back);
 //   k_gather         delivery tests of the pull over each row's in-edges
 //                    through the delay ring (J_intra), in (delay, source)
-//                    order, into a hit bitmap per bundle;
-//   k_sums           per row: delivered weights in CSR order, the Poisson
-//                    count that stands in for the spikes of other
-//                    partitions (J_inter), the gate update (jump + exact
-//                    decay);
+//                    order, into a hit bitmap per bundle; then, in the same
+//                    workgroup, per row: delivered weights in CSR order,
+//                    the Poisson count that stands in for the spikes of
+//                    other partitions (J_inter), the gate update (jump +
+//                    exact decay);
+//   k_sums           the per-row part alone, when a remote in-edge block
+//                    is gathered too (local, then remote, then background);
 //   k_finalize       per-step event totals, BOLD, ring slot, step counter.
 //
 // Everything is FP32 except the integer work (ids, delays, ballots, counts,
@@ -291,19 +293,26 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(
 }
 
 // ------------------------------------------------------------------ gather
-// The pull over each row's in-edges (J_intra) in two kernels.
-//  k_gather - delivery tests, one workgroup (16 wavefronts) per bundle of
-//    rows.  The bundle's lookup stream is sorted by (delay, source); a
-//    wavefront takes 256-entry tiles, rebuilds the sources by prefix sums of
-//    the 12-bit deltas, reads the spike bit of step t - d + 1 from that
-//    step's slot of the delay ring (monotone addresses, so the cache lines
-//    of the bitmaps are swept rather than hit at random) and sets the
-//    synapse's bit in the LDS hit bitmap (integer OR: order-free).  The
-//    finished bitmap goes to the hit buffer in one coalesced pass.
-//  k_sums - one thread per row visits the row's set hit bits in ascending
-//    position, which is its CSR order, loads only those weights and
-//    accumulates E and I in FP32 - the fixed per-neuron summation order -
-//    then adds the background count and updates the four gates.
+// The pull over each row's in-edges (J_intra).
+//  k_gather - one workgroup (16 wavefronts) per bundle of rows.  Phase 1,
+//    the delivery tests: the bundle's lookup stream is sorted by (delay,
+//    source); a wavefront takes 256-entry tiles (four planes of 64
+//    consecutive entries, one entry per lane), rebuilds the sources by
+//    prefix sums of the 12-bit deltas,
+//    reads the spike bit of step t - d + 1 from that step's slot of the
+//    delay ring (monotone addresses, so the cache lines of the bitmaps are
+//    swept rather than hit at random) and sets the synapse's bit in the LDS
+//    hit bitmap (integer OR: order-free).  Phase 2, when the partition has
+//    no other in-edge block: the same workgroup sums its rows from that
+//    bitmap, adds their background and updates their gates (fused_rows).
+//    With a remote block, the bitmap goes to the hit buffer in one
+//    coalesced pass instead, for
+//  k_sums - one thread per row visits the row's set hit bits (local block,
+//    then remote block) in ascending position, which is its CSR order,
+//    loads only those weights and accumulates E and I in FP32 - the fixed
+//    per-neuron summation order - then adds the background count and
+//    updates the four gates.  Both paths add the same terms in the same
+//    order, so their results are identical.
 // Gather workgroups are mapped XCD-aware: the blocks an XCD receives
 // (blockIdx congruent mod 8) take a contiguous range of bundles, so bundles
 // of the same population (same source set) share that XCD's L2; the eight
@@ -344,7 +353,10 @@ __device__ inline void stream_store(T* p, T v) {
 // One round of delivery tests over kU tiles already in registers: rebuild
 // the sources (a wavefront prefix sum of the deltas per plane of 64 entries,
 // on top of the tile's first source) and issue the kU x 4 bitmap loads, each
-// over 64 consecutive sources.
+// over 64 consecutive sources.  (Four consecutive entries per lane instead
+// - one prefix sum per tile - was measured slower: each load then spans a
+// whole tile's sources, so its lanes touch about four times as many cache
+// lines.)
 template <int kU>
 __device__ inline void gather_lookups(const u32x4 (&tv)[kU], const uint32_t (&h)[kU], const uint32_t* bitmaps,
                                       int64_t words_pad, int32_t t_mod, int32_t slots, uint32_t wmax,
@@ -393,13 +405,203 @@ __device__ inline void gather_hits(const u32x4 (&tv)[kU], const uint32_t (&src)[
   }
 }
 
-template <int kU>
-__global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kU == 1 ? 8 : 4)))
+// ------------------------------------------------------------ row sums
+// A row's delivered weights are added in ascending CSR position - the row's
+// fixed summation order - kWalkHits hits at a time, their weights loaded
+// together; then its background input and its gates are updated.  The same
+// code serves the gather with fused sums (hits read from the bundle's LDS
+// hit bitmap) and k_sums (hits read from the hit buffers).
+constexpr int kWalkHits = 4;
+
+// gather modes: hit bits out to the hit buffer (k_sums follows), or the
+// rows summed in the same workgroup from LDS, with FP32 or BF16 weights
+constexpr int kHitsOut = 0, kSumF32 = 1, kSumBF16 = 2;
+
+// what a row's tail reads and writes besides its sums
+struct RowTail {
+  float* j;                 // [4][n_pad] gates
+  int64_t n_pad;
+  float a0, a1, a2, a3;     // exp(-dt / tau_u)
+  float bg_w;               // background weight
+  const uint32_t* poisson;  // inversion table of the background count
+  int K;                    // its entries
+  float* ou;                // I_ou [n_pad], or null for the Poisson background
+  float ou_mu, ou_a, ou_s;  // OU mean, exp(-dt / tau), sigma sqrt(1 - a^2)
+  int32_t* bad;             // non-finite flag
+};
+
+// the CSR side of an in-edge block: row pointers and signed weights
+struct RowsCsr {
+  const int64_t* row_ptr;
+  const void* wts;
+};
+
+// weights of nh hits at CSR positions base + hp[q], as FP32 bit patterns
+// (a BF16 weight is the high half of its FP32 value; sign = inhibitory)
+template <bool kBF16>
+__device__ inline void load_weights(const void* wts, int64_t base, const int (&hp)[kWalkHits], int nh,
+                                    uint32_t (&x)[kWalkHits]) {
+  const float* wf = reinterpret_cast<const float*>(wts) + base;
+  const uint16_t* wb = reinterpret_cast<const uint16_t*>(wts) + base;
+#pragma unroll
+  for (int q = 0; q < kWalkHits; ++q)
+    if (q < nh) x[q] = kBF16 ? uint32_t(stream_load(wb + hp[q])) << 16 : __float_as_uint(stream_load(wf + hp[q]));
+}
+
+__device__ inline void walk_add(const uint32_t (&x)[kWalkHits], int nh, float& dE, float& dI) {
+#pragma unroll
+  for (int q = 0; q < kWalkHits; ++q) {
+    if (q < nh) {
+      const float wv = __uint_as_float(x[q] & 0x7FFFFFFFu);
+      if (x[q] >> 31) dI += wv;
+      else dE += wv;
+    }
+  }
+}
+
+// Row rr's tail at step t after its delivered sums dE / dI: the background
+// count (Philox4x64-10, counter (t, row within its member network, member, 0),
+// key the member's seed) joins the excitatory sum - or, with the OU
+// background, I_ou takes one exact OU step instead - then the four gates
+// decay and jump.  Returns the row's background events.
+__device__ inline uint32_t row_finish(const RowTail& A, int64_t t, int64_t rr, int64_t mrow0, int32_t member,
+                                      uint64_t seed, float dE, float dI, const float (&jv)[4]) {
+  const uint32_t u = A.ou ? 0u
+                          : uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(rr - mrow0), uint64_t(member), 0ull,
+                                                       seed, 0ull));
+  const int c = poisson_count(u, A.poisson, A.K);
+  const float de = __fmaf_rn(float(c), A.bg_w, dE);
+  const float ja = __fmaf_rn(A.a0, jv[0], de);
+  const float jb = __fmaf_rn(A.a1, jv[1], de);
+  const float jc = __fmaf_rn(A.a2, jv[2], dI);
+  const float jd = __fmaf_rn(A.a3, jv[3], dI);
+  A.j[rr] = ja;
+  A.j[A.n_pad + rr] = jb;
+  A.j[2 * A.n_pad + rr] = jc;
+  A.j[3 * A.n_pad + rr] = jd;
+  if (!(isfinite(ja) && isfinite(jb) && isfinite(jc) && isfinite(jd))) atomicOr(A.bad, 1);
+  if (A.ou) {
+    // I_ou <- mu + a (I_ou - mu) + s xi, xi by Box-Muller on Philox stream 1
+    uint64_t w1 = 0;
+    const uint32_t h0 = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(rr - mrow0), uint64_t(member), 1ull,
+                                                   seed, 0ull, &w1));
+    const uint32_t h1 = uint32_t(w1 >> 32);
+    // the draw in FP64 (u1, u2 exact), rounded once: a float u1 cannot
+    // resolve ln u1 near 1
+    const double u1 = (double(h0) + 1.0) * 2.3283064365386962890625e-10;  // (0, 1]
+    const double u2 = double(h1) * 2.3283064365386962890625e-10;          // [0, 1)
+    const float xi = float(sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2));
+    const float xo = A.ou[rr];
+    const float y = __fmaf_rn(A.ou_s, xi, __fmaf_rn(A.ou_a, xo - A.ou_mu, A.ou_mu));
+    A.ou[rr] = y;
+    if (!isfinite(y)) atomicOr(A.bad, 1);
+  }
+  return uint32_t(c);
+}
+
+// A row's walk over bits [p0, p0 + len) of a bundle's LDS hit bitmap, in
+// ascending position.
+struct LdsWalk {
+  int w, w1;
+  uint32_t bits, last;
+};
+
+__device__ inline void lds_walk_init(const uint32_t* s_hits, int p0, int len, LdsWalk& R) {
+  if (len <= 0) {
+    R.w = 0;
+    R.w1 = -1;
+    R.bits = R.last = 0u;
+    return;
+  }
+  R.w = p0 >> 5;
+  R.w1 = (p0 + len - 1) >> 5;
+  R.bits = s_hits[R.w] & (~0u << (p0 & 31));
+  R.last = ~0u >> (31 - ((p0 + len - 1) & 31));
+}
+
+// the next up to kWalkHits hit positions of the row (fewer: the row is done)
+__device__ inline int lds_walk_collect(const uint32_t* s_hits, LdsWalk& R, int (&hp)[kWalkHits]) {
+  int nh = 0;
+  while (nh < kWalkHits) {
+    if (R.w == R.w1) R.bits &= R.last;
+    if (R.bits) {
+      hp[nh++] = (R.w << 5) + (__ffs(R.bits) - 1);
+      R.bits &= R.bits - 1u;
+    } else if (R.w < R.w1) {
+      R.bits = s_hits[++R.w];
+    } else {
+      break;
+    }
+  }
+  return nh;
+}
+
+// Rows of a bundle summed from its LDS hit bitmap by one workgroup: each
+// thread takes kFuseRows rows at a time (rows tid, tid + T, ... of the
+// bundle, T = threads), walks their bits, requests all their first
+// kWalkHits weights together and adds each row's weights in its CSR order;
+// a row with more hits continues alone.  Then each row's background and
+// gates.  One row at a time measured fastest (2 and 4 rows in flight per
+// thread: 0.2 % and 3 % slower at 7 Hz, 2 % and 6 % at 30 Hz): the phase
+// is bound by the weight lines it fetches, not by load latency.
+constexpr int kFuseRows = 1;
+
+template <bool kBF16>
+__device__ inline void fused_rows(const uint32_t* s_hits, const Bundle& B, const RowsCsr& rows, const RowTail& A,
+                                  int64_t t, int tid, uint32_t& ev, uint32_t& evb) {
+  for (int64_t rb = B.row0 + tid; rb < B.row1; rb += int64_t(kFuseRows) * kGatherThreads) {
+    int64_t r[kFuseRows];
+    bool valid[kFuseRows];
+    float jv[kFuseRows][4], dE[kFuseRows], dI[kFuseRows];
+    LdsWalk W[kFuseRows];
+#pragma unroll
+    for (int h = 0; h < kFuseRows; ++h) {
+      r[h] = rb + int64_t(h) * kGatherThreads;
+      valid[h] = r[h] < B.row1;
+      dE[h] = dI[h] = 0.f;
+      int64_t k0 = 0, k1 = 0;
+      jv[h][0] = jv[h][1] = jv[h][2] = jv[h][3] = 0.f;
+      if (valid[h]) {
+        k0 = rows.row_ptr[r[h]];
+        k1 = rows.row_ptr[r[h] + 1];
+        jv[h][0] = A.j[r[h]];
+        jv[h][1] = A.j[A.n_pad + r[h]];
+        jv[h][2] = A.j[2 * A.n_pad + r[h]];
+        jv[h][3] = A.j[3 * A.n_pad + r[h]];
+      }
+      lds_walk_init(s_hits, int(k0 - B.syn0), int(k1 - k0), W[h]);
+    }
+    int hp[kFuseRows][kWalkHits], nh[kFuseRows];
+    uint32_t x[kFuseRows][kWalkHits];
+#pragma unroll
+    for (int h = 0; h < kFuseRows; ++h) nh[h] = lds_walk_collect(s_hits, W[h], hp[h]);
+#pragma unroll
+    for (int h = 0; h < kFuseRows; ++h) load_weights<kBF16>(rows.wts, B.syn0, hp[h], nh[h], x[h]);
+#pragma unroll
+    for (int h = 0; h < kFuseRows; ++h) {
+      walk_add(x[h], nh[h], dE[h], dI[h]);
+      ev += uint32_t(nh[h]);
+      while (nh[h] == kWalkHits) {
+        nh[h] = lds_walk_collect(s_hits, W[h], hp[h]);
+        load_weights<kBF16>(rows.wts, B.syn0, hp[h], nh[h], x[h]);
+        walk_add(x[h], nh[h], dE[h], dI[h]);
+        ev += uint32_t(nh[h]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < kFuseRows; ++h)
+      if (valid[h]) evb += row_finish(A, t, r[h], B.member_row0, B.member, B.seed, dE[h], dI[h], jv[h]);
+  }
+}
+
+template <int kU, int kMode>
+__global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kU == 1 && kMode == kHitsOut ? 8 : 4)))
 void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
               const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
               const uint32_t* __restrict__ bitmaps, int64_t words_pad, int32_t slots,
-              uint32_t* __restrict__ hitbuf, int64_t* __restrict__ ev_ring) {
+              uint32_t* __restrict__ hitbuf, int64_t* __restrict__ ev_ring, RowsCsr rows, RowTail A) {
   extern __shared__ uint32_t s_hits[];
+  __shared__ uint32_t s_red[2][kGatherThreads / 64];
   const int32_t t_mod = int32_t(step[1]);
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(t_mod) * kStripes * 2;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -480,25 +682,42 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
   }
   __syncthreads();
 
-  // ---- hand the delivery tests to the sums: the bundle's hit words, and
-  // the delivered events (set bits below the padding bit at nsyn)
-  uint32_t ev = 0;
-  uint32_t* __restrict__ dst = hitbuf + (B.hbit0 >> 5);
-  for (int q = tid; q < hw; q += kGatherThreads) {
-    const uint32_t w = s_hits[q];
-    stream_store(dst + q, w);
-    ev += uint32_t(__popc(q == hw - 1 ? w & ((1u << (B.nsyn & 31)) - 1u) : w));
+  uint32_t ev = 0, evb = 0;
+  if constexpr (kMode == kHitsOut) {
+    // ---- hand the delivery tests to the sums: the bundle's hit words, and
+    // the delivered events (set bits below the padding bit at nsyn)
+    uint32_t* __restrict__ dst = hitbuf + (B.hbit0 >> 5);
+    for (int q = tid; q < hw; q += kGatherThreads) {
+      const uint32_t w = s_hits[q];
+      stream_store(dst + q, w);
+      ev += uint32_t(__popc(q == hw - 1 ? w & ((1u << (B.nsyn & 31)) - 1u) : w));
+    }
+  } else {
+    // ---- phase 2: the sums of the bundle's rows from the hit bitmap still
+    // in LDS (row r's CSR positions [row_ptr[r] - syn0, row_ptr[r+1] -
+    // syn0)), then their background and gates.  The delivered events are
+    // the hits the rows visit.
+    fused_rows<kMode == kSumBF16>(s_hits, B, rows, A, step[0], tid, ev, evb);
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) ev += __shfl_down(ev, off);
-  __syncthreads();  // every hit word is read
-  if (lane == 0) s_hits[tid >> 6] = ev;
+  for (int off = 32; off > 0; off >>= 1) {
+    ev += __shfl_down(ev, off);
+    evb += __shfl_down(evb, off);
+  }
+  if (lane == 0) {
+    s_red[0][tid >> 6] = ev;
+    s_red[1][tid >> 6] = evb;
+  }
   __syncthreads();
   if (tid == 0) {
-    int64_t r = 0;
-    for (int w = 0; w < kGatherThreads / 64; ++w) r += s_hits[w];
+    int64_t r = 0, rb = 0;
+    for (int w = 0; w < kGatherThreads / 64; ++w) {
+      r += s_red[0][w];
+      rb += s_red[1][w];
+    }
     int64_t* dsts = ev_slot + 2 * (blockIdx.x & (kStripes - 1));
     if (r) atomicAdd(reinterpret_cast<unsigned long long*>(dsts), (unsigned long long)r);
+    if (rb) atomicAdd(reinterpret_cast<unsigned long long*>(dsts + 1), (unsigned long long)rb);
   }
 }
 
@@ -527,7 +746,6 @@ struct SumBlock {
 // time; hits are taken kWalkHits at a time and their weights loaded
 // together.
 constexpr int kWalkWords = 5;
-constexpr int kWalkHits = 4;
 
 struct RowWalk {
   int64_t k0, bit0, w, w1;
@@ -579,23 +797,7 @@ __device__ inline int walk_collect(const SumBlock& S, RowWalk& R, int (&hp)[kWal
 template <bool kBF16>
 __device__ inline void walk_load(const SumBlock& S, const RowWalk& R, const int (&hp)[kWalkHits], int nh,
                                  uint32_t (&x)[kWalkHits]) {
-  const float* wf = reinterpret_cast<const float*>(S.wts);
-  const uint16_t* wb = reinterpret_cast<const uint16_t*>(S.wts);
-#pragma unroll
-  for (int q = 0; q < kWalkHits; ++q)
-    if (q < nh)
-      x[q] = kBF16 ? uint32_t(stream_load(wb + R.k0 + hp[q])) << 16 : __float_as_uint(stream_load(wf + R.k0 + hp[q]));
-}
-
-__device__ inline void walk_add(const uint32_t (&x)[kWalkHits], int nh, float& dE, float& dI) {
-#pragma unroll
-  for (int q = 0; q < kWalkHits; ++q) {
-    if (q < nh) {
-      const float wv = __uint_as_float(x[q] & 0x7FFFFFFFu);
-      if (x[q] >> 31) dI += wv;
-      else dE += wv;
-    }
-  }
+  load_weights<kBF16>(S.wts, R.k0, hp, nh, x);
 }
 
 // adds the delivered weights of one block to the kRows rows of a thread,
@@ -630,10 +832,8 @@ __device__ inline void block_rows_sum(const SumBlock& S, const int64_t (&r)[kRow
 
 template <bool kBF16, int kRows>
 __global__ __launch_bounds__(kSumsRowsPerBlock / kRows) void k_sums(
-    int64_t n, int64_t n_pad, const int64_t* __restrict__ step, SumBlock loc, SumBlock rem, int has_rem,
-    float* __restrict__ j, float a0, float a1, float a2, float a3, float bg_w,
-    const uint32_t* __restrict__ poisson, int K, float* __restrict__ ou, float ou_mu, float ou_a, float ou_s,
-    int64_t* __restrict__ ev_ring, int32_t* __restrict__ bad) {
+    int64_t n, const int64_t* __restrict__ step, SumBlock loc, SumBlock rem, int has_rem, RowTail A,
+    int64_t* __restrict__ ev_ring) {
   constexpr int kT = kSumsRowsPerBlock / kRows;  // threads per block
   __shared__ uint32_t s_bg[kT / 64];
   const int64_t t = step[0];
@@ -650,10 +850,10 @@ __global__ __launch_bounds__(kSumsRowsPerBlock / kRows) void k_sums(
     dE[h] = dI[h] = 0.f;
     B[h] = nullptr;
     if (valid[h]) {
-      jv[h][0] = j[r[h]];
-      jv[h][1] = j[n_pad + r[h]];
-      jv[h][2] = j[2 * n_pad + r[h]];
-      jv[h][3] = j[3 * n_pad + r[h]];
+      jv[h][0] = A.j[r[h]];
+      jv[h][1] = A.j[A.n_pad + r[h]];
+      jv[h][2] = A.j[2 * A.n_pad + r[h]];
+      jv[h][3] = A.j[3 * A.n_pad + r[h]];
     }
   }
   block_rows_sum<kBF16, kRows>(loc, r, valid, dE, dI, B);
@@ -665,41 +865,7 @@ __global__ __launch_bounds__(kSumsRowsPerBlock / kRows) void k_sums(
 #pragma unroll
   for (int h = 0; h < kRows; ++h) {
     if (!valid[h]) continue;
-    const int64_t rr = r[h];
-    const uint64_t seed = B[h]->seed;
-    const int64_t mrow0 = B[h]->member_row0;
-    const int32_t member = B[h]->member;
-    const uint32_t u = ou ? 0u
-                          : uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(rr - mrow0), uint64_t(member), 0ull,
-                                                       seed, 0ull));
-    const int c = poisson_count(u, poisson, K);
-    evb += uint32_t(c);
-    const float de = __fmaf_rn(float(c), bg_w, dE[h]);
-    const float ja = __fmaf_rn(a0, jv[h][0], de);
-    const float jb = __fmaf_rn(a1, jv[h][1], de);
-    const float jc = __fmaf_rn(a2, jv[h][2], dI[h]);
-    const float jd = __fmaf_rn(a3, jv[h][3], dI[h]);
-    j[rr] = ja;
-    j[n_pad + rr] = jb;
-    j[2 * n_pad + rr] = jc;
-    j[3 * n_pad + rr] = jd;
-    if (!(isfinite(ja) && isfinite(jb) && isfinite(jc) && isfinite(jd))) atomicOr(bad, 1);
-    if (ou) {
-      // I_ou <- mu + a (I_ou - mu) + s xi, xi by Box-Muller on Philox stream 1
-      uint64_t w1 = 0;
-      const uint32_t h0 = uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(rr - mrow0), uint64_t(member), 1ull,
-                                                     seed, 0ull, &w1));
-      const uint32_t h1 = uint32_t(w1 >> 32);
-      // the draw in FP64 (u1, u2 exact), rounded once: a float u1 cannot
-      // resolve ln u1 near 1
-      const double u1 = (double(h0) + 1.0) * 2.3283064365386962890625e-10;  // (0, 1]
-      const double u2 = double(h1) * 2.3283064365386962890625e-10;          // [0, 1)
-      const float xi = float(sqrt(-2.0 * log(u1)) * cos(6.283185307179586477 * u2));
-      const float xo = ou[rr];
-      const float y = __fmaf_rn(ou_s, xi, __fmaf_rn(ou_a, xo - ou_mu, ou_mu));
-      ou[rr] = y;
-      if (!isfinite(y)) atomicOr(bad, 1);
-    }
+    evb += row_finish(A, t, r[h], B[h]->member_row0, B[h]->member, B[h]->seed, dE[h], dI[h], jv[h]);
   }
   // block total of background events, one striped atomic per block
 #pragma unroll
@@ -820,38 +986,57 @@ hipError_t launch_compact_read(const DeviceNet& d, const int64_t* at, int32_t* i
 
 namespace {
 
-template <int kU>
-void launch_gather_as(const ConnBlock& cb, const int64_t* step, const uint32_t* bitmaps, int64_t words_pad,
-                      int32_t slots, int64_t* ev, hipStream_t s) {
+RowTail row_tail(const DeviceNet& d) {
+  return RowTail{d.j, d.n_pad, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
+                 d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.bad};
+}
+
+template <int kU, int kMode>
+void launch_gather_as(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
+                      hipStream_t s) {
   const unsigned grid = unsigned(cb.xcd_max * 8);
   const size_t lds = size_t(cb.hit_words) * 4;
-  hipLaunchKernelGGL((k_gather<kU>), dim3(grid), dim3(kGatherThreads), lds, s, cb.xcd_first, step, cb.bundles,
-                     cb.tiles, cb.theads, bitmaps, words_pad, slots, cb.hitbuf, ev);
+  hipLaunchKernelGGL((k_gather<kU, kMode>), dim3(grid), dim3(kGatherThreads), lds, s, cb.xcd_first, d.step,
+                     cb.bundles, cb.tiles, cb.theads, bitmaps, words_pad, d.slots, cb.hitbuf, d.ev,
+                     RowsCsr{cb.row_ptr, cb.wts}, row_tail(d));
+}
+
+template <int kMode>
+void launch_gather_mode(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
+                        hipStream_t s) {
+  switch (d.unroll) {
+    case 1: launch_gather_as<1, kMode>(d, cb, bitmaps, words_pad, s); break;
+    case 2: launch_gather_as<2, kMode>(d, cb, bitmaps, words_pad, s); break;
+    default: launch_gather_as<3, kMode>(d, cb, bitmaps, words_pad, s); break;
+  }
+}
+
+template <int kU, int kMode>
+hipError_t set_lds_limit_one(int bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kU, kMode>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 }  // namespace
 
 hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
-                         hipStream_t s) {
+                         bool fuse_sums, hipStream_t s) {
   if (cb.n_bundles == 0) return hipSuccess;
-  switch (d.unroll) {
-    case 1: launch_gather_as<1>(cb, d.step, bitmaps, words_pad, d.slots, d.ev, s); break;
-    case 2: launch_gather_as<2>(cb, d.step, bitmaps, words_pad, d.slots, d.ev, s); break;
-    default: launch_gather_as<3>(cb, d.step, bitmaps, words_pad, d.slots, d.ev, s); break;
-  }
+  if (!fuse_sums) launch_gather_mode<kHitsOut>(d, cb, bitmaps, words_pad, s);
+  else if (d.wtype == DTB_W_BF16) launch_gather_mode<kSumBF16>(d, cb, bitmaps, words_pad, s);
+  else launch_gather_mode<kSumF32>(d, cb, bitmaps, words_pad, s);
   return hipGetLastError();
 }
 
 hipError_t gather_set_lds_limit() {
   const int bytes = kHitWords * 4;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<1>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<2>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<3>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
+  hipError_t e = hipSuccess;
+  for (hipError_t x : {set_lds_limit_one<1, kHitsOut>(bytes), set_lds_limit_one<2, kHitsOut>(bytes),
+                       set_lds_limit_one<3, kHitsOut>(bytes), set_lds_limit_one<1, kSumF32>(bytes),
+                       set_lds_limit_one<2, kSumF32>(bytes), set_lds_limit_one<3, kSumF32>(bytes),
+                       set_lds_limit_one<1, kSumBF16>(bytes), set_lds_limit_one<2, kSumBF16>(bytes),
+                       set_lds_limit_one<3, kSumBF16>(bytes)})
+    if (e == hipSuccess) e = x;
   return e;
 }
 
@@ -862,13 +1047,11 @@ hipError_t launch_sums(const DeviceNet& d, hipStream_t s) {
   const SumBlock rem{d.rem.bundles, d.rem.block_bundle, d.rem.row_ptr, d.rem.wts, d.rem.hitbuf};
   const int has_rem = d.rem.n_bundles > 0 ? 1 : 0;
   if (d.wtype == DTB_W_BF16)
-    hipLaunchKernelGGL((k_sums<true, kSumsRows>), dim3(grid), dim3(kT), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
-                       d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
-                       d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
+    hipLaunchKernelGGL((k_sums<true, kSumsRows>), dim3(grid), dim3(kT), 0, s, d.n, d.step, loc, rem, has_rem,
+                       row_tail(d), d.ev);
   else
-    hipLaunchKernelGGL((k_sums<false, kSumsRows>), dim3(grid), dim3(kT), 0, s, d.n, d.n_pad, d.step, loc, rem, has_rem,
-                       d.j, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
-                       d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.ev, d.bad);
+    hipLaunchKernelGGL((k_sums<false, kSumsRows>), dim3(grid), dim3(kT), 0, s, d.n, d.step, loc, rem, has_rem,
+                       row_tail(d), d.ev);
   return hipGetLastError();
 }
 

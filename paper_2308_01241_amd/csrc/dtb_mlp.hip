@@ -6,7 +6,9 @@
 // bfloat16, accumulation in FP32.  Master weights, Adam moments, biases,
 // pre-activations and gradients are FP32.  Rounding points: layer inputs and
 // weights (forward); the upstream gradient, saved activations and weights
-// (backward).
+// (backward).  A handle can instead keep every operand in FP32
+// (v_mfma_f32_16x16x4_f32, same tiles and epilogues): the check of the
+// kernels' index logic against an unrounded FP64 reference.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,6 +40,11 @@ __host__ __device__ inline uint16_t f2bf(float f) {
   return uint16_t(u >> 16);
 }
 
+// an FP32 value as a matrix operand: bfloat16 bits (round to nearest even)
+// or the float itself
+__device__ inline uint16_t to_op(float x, uint16_t*) { return f2bf(x); }
+__device__ inline float to_op(float x, float*) { return x; }
+
 __device__ inline float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
 __device__ inline float gelu_grad(float z) {
   return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
@@ -46,18 +53,21 @@ __device__ inline float gelu_grad(float z) {
 enum Epi { kHidden = 0, kOut = 1, kDGelu = 2, kStore = 3 };
 
 // C(m, n) = sum_k A(m, k) B(k, n) over 64x64 output tiles, K in steps of 32.
-//   A(m, k) = TA ? A[k lda + m] : A[m lda + k]      (bfloat16 bits)
+//   A(m, k) = TA ? A[k lda + m] : A[m lda + k]      (Op: bfloat16 bits or float)
 //   B(k, n) = TB ? B[n ldb + k] : B[k ldb + n]
 // Four wavefronts per tile, each a 32x32 quarter = 2x2 MFMA 16x16 blocks.
 // MFMA operand layout (16x16x32 bf16): lane l supplies A[l % 16][8 (l / 16) + e]
-// and B[8 (l / 16) + e][l % 16], e = 0..7; it receives D[4 (l / 16) + r][l % 16].
-template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
-                                              const uint16_t* __restrict__ B, int ldb,
+// and B[8 (l / 16) + e][l % 16], e = 0..7; (16x16x4 f32): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; both return D[4 (l / 16) + r][l % 16].
+template <bool TA, bool TB, int EPI, typename Op>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const Op* __restrict__ A, int lda,
+                                              const Op* __restrict__ B, int ldb,
                                               const float* __restrict__ bias, float* __restrict__ Cf,
-                                              uint16_t* __restrict__ Cb, int ldc, const float* __restrict__ Zprev) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[64][40];  // [m][k], rows padded to 80 B
-  __shared__ __attribute__((aligned(16))) uint16_t sB[64][40];  // [n][k]
+                                              Op* __restrict__ Cb, int ldc, const float* __restrict__ Zprev) {
+  constexpr bool kF32 = sizeof(Op) == 4;
+  constexpr int kRow = kF32 ? 33 : 40;  // LDS row pitch in elements (80 B for bf16)
+  __shared__ __attribute__((aligned(16))) Op sA[64][kRow];  // [m][k]
+  __shared__ __attribute__((aligned(16))) Op sB[64][kRow];  // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -70,23 +80,38 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     for (int q = tid; q < 64 * 32; q += 256) {
       const int r = q >> 5, c = q & 31;
       const int m = m0 + r, k = k0 + c;
-      uint16_t v = 0;
+      Op v = Op(0);
       if (m < M && k < K) v = TA ? A[int64_t(k) * lda + m] : A[int64_t(m) * lda + k];
       sA[r][c] = v;
       const int nn = n0 + r;
-      uint16_t w = 0;
+      Op w = Op(0);
       if (nn < N && k < K) w = TB ? B[int64_t(nn) * ldb + k] : B[int64_t(k) * ldb + nn];
       sB[r][c] = w;
     }
     __syncthreads();
-    const int kk = 8 * (lane >> 4);
+    if constexpr (kF32) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sA[wm + 16 * i + (lane & 15)][kk]);
+      for (int kk = 0; kk < 32; kk += 4) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sB[wn + 16 * j + (lane & 15)][kk]);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 2; ++i) {
+          const float a = sA[wm + 16 * i + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const float b = sB[wn + 16 * j + (lane & 15)][kk + (lane >> 4)];
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      const int kk = 8 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sA[wm + 16 * i + (lane & 15)][kk]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sB[wn + 16 * j + (lane & 15)][kk]);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -105,17 +130,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
         if (EPI == kHidden) {
           const float z = x + bias[col];
           Cf[o] = z;
-          Cb[o] = f2bf(gelu(z));
+          Cb[o] = to_op(gelu(z), Cb);
         } else if (EPI == kOut) {
           Cf[o] = x + bias[col];
         } else if (EPI == kDGelu) {
           const float dz = x * gelu_grad(Zprev[o]);
           Cf[o] = dz;
-          Cb[o] = f2bf(dz);
+          Cb[o] = to_op(dz, Cb);
         } else {
           Cf[o] = x;
         }
       }
+}
+
+// FP32 values as matrix operands
+template <typename Op>
+__global__ void k_to_op(int64_t n, const float* __restrict__ x, Op* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = to_op(x[i], y);
 }
 
 __global__ void k_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
@@ -125,8 +157,9 @@ __global__ void k_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __re
 
 // d(loss)/dY for loss = mean((Y - T)^2) and the loss itself (one block, fixed
 // summation order: strided partial sums then a tree).
+template <typename Op>
 __global__ __launch_bounds__(1024) void k_mse(int64_t n, const float* __restrict__ Y, const float* __restrict__ T,
-                                              float* __restrict__ dY, uint16_t* __restrict__ dYb,
+                                              float* __restrict__ dY, Op* __restrict__ dYb,
                                               double* __restrict__ loss) {
   __shared__ double s[1024];
   double acc = 0.0;
@@ -136,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_mse(int64_t n, const float* __restrict
     acc += double(d) * double(d);
     const float g = scale * d;
     dY[i] = g;
-    dYb[i] = f2bf(g);
+    dYb[i] = to_op(g, dYb);
   }
   s[threadIdx.x] = acc;
   __syncthreads();
@@ -232,10 +265,11 @@ struct dtb_mlp {
   float *m = nullptr, *v = nullptr, *g = nullptr;
   // activations for up to cap rows
   int cap = 0;
+  bool f32_ops = false;              // operands in FP32 instead of bfloat16
   std::vector<float*> Z;            // pre-activations per layer (output layer: Y)
-  std::vector<uint16_t*> Act;       // bf16 layer inputs: Act[0] = X, Act[l] = gelu(Z[l-1])
+  std::vector<void*> Act;           // operand-typed layer inputs: Act[0] = X, Act[l] = gelu(Z[l-1])
   float *dZf[2] = {nullptr, nullptr};
-  uint16_t* dZb[2] = {nullptr, nullptr};
+  void* dZb[2] = {nullptr, nullptr}; // operand-typed copies of dZf
   float *Xf = nullptr, *Tf = nullptr;
   double* loss = nullptr;
   std::vector<void*> buf;           // activation allocations (freed on regrow)
@@ -273,11 +307,11 @@ dtb_status ensure_cap(dtb_mlp* h, int rows) {
   h->Act.assign(L, nullptr);
   for (int l = 0; l < L; ++l) {
     MLP_HIP(al(size_t(rows) * h->dims[l + 1] * 4, reinterpret_cast<void**>(&h->Z[l])));
-    MLP_HIP(al(size_t(rows) * h->dims[l] * 2, reinterpret_cast<void**>(&h->Act[l])));
+    MLP_HIP(al(size_t(rows) * h->dims[l] * 4, &h->Act[l]));  // 4 B: room for either operand type
   }
   for (int q = 0; q < 2; ++q) {
     MLP_HIP(al(size_t(rows) * wmax * 4, reinterpret_cast<void**>(&h->dZf[q])));
-    MLP_HIP(al(size_t(rows) * wmax * 2, reinterpret_cast<void**>(&h->dZb[q])));
+    MLP_HIP(al(size_t(rows) * wmax * 4, &h->dZb[q]));
   }
   MLP_HIP(al(size_t(rows) * h->dims[0] * 4, reinterpret_cast<void**>(&h->Xf)));
   MLP_HIP(al(size_t(rows) * h->dims[L] * 4, reinterpret_cast<void**>(&h->Tf)));
@@ -285,58 +319,78 @@ dtb_status ensure_cap(dtb_mlp* h, int rows) {
   return DTB_OK;
 }
 
-template <bool TA, bool TB, int EPI>
-hipError_t gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
-                const float* bias, float* Cf, uint16_t* Cb, int ldc, const float* Zprev) {
+template <bool TA, bool TB, int EPI, typename Op>
+hipError_t gemm(hipStream_t s, int M, int N, int K, const Op* A, int lda, const Op* B, int ldb, const float* bias,
+                float* Cf, Op* Cb, int ldc, const float* Zprev) {
   dim3 grid(unsigned((N + 63) / 64), unsigned((M + 63) / 64));
-  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, bias, Cf, Cb, ldc,
+  hipLaunchKernelGGL((k_gemm<TA, TB, EPI, Op>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, bias, Cf, Cb, ldc,
                      Zprev);
   return hipGetLastError();
 }
 
+// the weights as operands: the bfloat16 copies, or the FP32 master weights
+const uint16_t* op_weights(const dtb_mlp* h, uint16_t*) { return h->wb; }
+const float* op_weights(const dtb_mlp* h, float*) { return h->w; }
+
 // forward pass of `rows` rows whose FP32 inputs are in h->Xf; output in h->Z[L-1]
-hipError_t forward(dtb_mlp* h, int rows) {
+template <typename Op>
+hipError_t forward_as(dtb_mlp* h, int rows) {
   const int L = layers_of(h);
   const int64_t nin = int64_t(rows) * h->dims[0];
-  hipLaunchKernelGGL(k_to_bf16, dim3(unsigned((nin + 255) / 256)), dim3(256), 0, h->stream, nin, h->Xf, h->Act[0]);
+  Op* const tag = nullptr;
+  hipLaunchKernelGGL((k_to_op<Op>), dim3(unsigned((nin + 255) / 256)), dim3(256), 0, h->stream, nin, h->Xf,
+                     static_cast<Op*>(h->Act[0]));
   hipError_t e = hipGetLastError();
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     const int in = h->dims[l], out = h->dims[l + 1];
-    const uint16_t* W = h->wb + h->woff[l];
+    const Op* W = op_weights(h, tag) + h->woff[l];
     const float* b = h->w + h->boff[l];
+    const Op* a = static_cast<const Op*>(h->Act[l]);
     if (l < L - 1)
-      e = gemm<false, true, kHidden>(h->stream, rows, out, in, h->Act[l], in, W, in, b, h->Z[l], h->Act[l + 1], out,
-                                     nullptr);
+      e = gemm<false, true, kHidden, Op>(h->stream, rows, out, in, a, in, W, in, b, h->Z[l],
+                                         static_cast<Op*>(h->Act[l + 1]), out, nullptr);
     else
-      e = gemm<false, true, kOut>(h->stream, rows, out, in, h->Act[l], in, W, in, b, h->Z[l], nullptr, out, nullptr);
+      e = gemm<false, true, kOut, Op>(h->stream, rows, out, in, a, in, W, in, b, h->Z[l], nullptr, out, nullptr);
   }
   return e;
 }
 
 // gradient of mean((Y - T)^2) into h->g (T in h->Tf); needs forward() first
-hipError_t backward(dtb_mlp* h, int rows) {
+template <typename Op>
+hipError_t backward_as(dtb_mlp* h, int rows) {
   const int L = layers_of(h);
   const int64_t nout = int64_t(rows) * h->dims[L];
-  hipLaunchKernelGGL(k_mse, dim3(1), dim3(1024), 0, h->stream, nout, h->Z[L - 1], h->Tf, h->dZf[0], h->dZb[0],
-                     h->loss);
+  Op* const tag = nullptr;
+  hipLaunchKernelGGL((k_mse<Op>), dim3(1), dim3(1024), 0, h->stream, nout, h->Z[L - 1], h->Tf, h->dZf[0],
+                     static_cast<Op*>(h->dZb[0]), h->loss);
   hipError_t e = hipGetLastError();
   int cur = 0;
   for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
     const int in = h->dims[l], out = h->dims[l + 1];
     // dW_l = dZ_l^T A_l    (out x in)
-    e = gemm<true, false, kStore>(h->stream, out, in, rows, h->dZb[cur], out, h->Act[l], in, nullptr,
-                                  h->g + h->woff[l], nullptr, in, nullptr);
+    e = gemm<true, false, kStore, Op>(h->stream, out, in, rows, static_cast<const Op*>(h->dZb[cur]), out,
+                                      static_cast<const Op*>(h->Act[l]), in, nullptr, h->g + h->woff[l], nullptr,
+                                      in, nullptr);
     if (e != hipSuccess) break;
     hipLaunchKernelGGL(k_colsum, dim3(unsigned((out + 255) / 256)), dim3(256), 0, h->stream, rows, out, h->dZf[cur],
                        h->g + h->boff[l]);
     e = hipGetLastError();
     if (e != hipSuccess || l == 0) break;
     // dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})   (rows x in)
-    e = gemm<false, false, kDGelu>(h->stream, rows, in, out, h->dZb[cur], out, h->wb + h->woff[l], in, nullptr,
-                                   h->dZf[1 - cur], h->dZb[1 - cur], in, h->Z[l - 1]);
+    e = gemm<false, false, kDGelu, Op>(h->stream, rows, in, out, static_cast<const Op*>(h->dZb[cur]), out,
+                                       op_weights(h, tag) + h->woff[l], in, nullptr, h->dZf[1 - cur],
+                                       static_cast<Op*>(h->dZb[1 - cur]), in, h->Z[l - 1]);
     cur = 1 - cur;
   }
   return e;
+}
+
+hipError_t forward(dtb_mlp* h, int rows) {
+  return h->f32_ops ? forward_as<float>(h, rows) : forward_as<uint16_t>(h, rows);
+}
+
+hipError_t backward(dtb_mlp* h, int rows) {
+  return h->f32_ops ? backward_as<float>(h, rows) : backward_as<uint16_t>(h, rows);
 }
 
 dtb_status copy_in(dtb_mlp* h, float* dst, const float* src, size_t bytes, int on_device) {
@@ -436,6 +490,13 @@ dtb_status dtb_mlp_params(dtb_mlp* h, float* buf, int get, int on_device) {
   MLP_HIP(hipMemsetAsync(h->v, 0, P * 4, h->stream));
   MLP_HIP(hipStreamSynchronize(h->stream));
   h->step = 0;
+  return DTB_OK;
+}
+
+dtb_status dtb_mlp_set_operands(dtb_mlp* h, int fp32) {
+  if (!h || (fp32 != 0 && fp32 != 1)) return mfail(DTB_ERR_INVALID, "set_operands needs a handle and fp32 in {0, 1}");
+  MLP_HIP(hipStreamSynchronize(h->stream));
+  h->f32_ops = fp32 == 1;
   return DTB_OK;
 }
 

@@ -55,18 +55,18 @@ class Net:
     """
 
     def __init__(self, network, wtype: str = "f32", record_steps: int = 1024, stream=None, _members=None,
-                 bundle_syn: int = 0, unroll: int = 0):
+                 bundle_syn: int = 0, unroll: int = 0, fuse: int = 0):
         lib = load()
         self._lib = lib
         h = ctypes.c_void_p()
         if _members is None:
-            d, keep = _make_desc(network, wtype, record_steps, bundle_syn, unroll)
+            d, keep = _make_desc(network, wtype, record_steps, bundle_syn, unroll, fuse)
             check(lib.dtb_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)))
         else:
             descs = (Desc * len(_members))()
             keep = []
             for m, nw in enumerate(_members):
-                d, k = _make_desc(nw, wtype, record_steps, bundle_syn, unroll)
+                d, k = _make_desc(nw, wtype, record_steps, bundle_syn, unroll, fuse)
                 descs[m] = d
                 keep.append(k)
             check(lib.dtb_create_batch(descs, len(_members), _stream_handle(stream), ctypes.byref(h)))
@@ -89,10 +89,10 @@ class Net:
 
     @classmethod
     def batch(cls, members, wtype: str = "f32", record_steps: int = 1024, stream=None, bundle_syn: int = 0,
-              unroll: int = 0) -> "Net":
+              unroll: int = 0, fuse: int = 0) -> "Net":
         """One handle advancing several independent networks together."""
         return cls(None, wtype=wtype, record_steps=record_steps, stream=stream, _members=list(members),
-                   bundle_syn=bundle_syn, unroll=unroll)
+                   bundle_syn=bundle_syn, unroll=unroll, fuse=fuse)
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -262,7 +262,7 @@ class Net:
         return {"steps": v[0].value, "spikes": v[1].value, "ev_rec": v[2].value, "ev_bg": v[3].value}
 
 
-def _make_desc(nw, wtype, record_steps, bundle_syn=0, unroll=0):
+def _make_desc(nw, wtype, record_steps, bundle_syn=0, unroll=0, fuse=0):
     keep = []
 
     def arr(a, dt):
@@ -303,6 +303,7 @@ def _make_desc(nw, wtype, record_steps, bundle_syn=0, unroll=0):
     d.record_steps = int(record_steps)
     d.gather_bundle_syn = int(bundle_syn)
     d.gather_unroll = int(unroll)
+    d.gather_fuse = int(fuse)
     return d, keep
 
 

@@ -48,6 +48,10 @@ class MLP:
         assert t.size == self.num_params
         check(self._lib.dtb_mlp_params(self._h, _ptr(t), 0, 0))
 
+    def set_operands(self, fp32: bool) -> None:
+        """FP32 matrix operands (True) or bfloat16 (False, the default)."""
+        check(self._lib.dtb_mlp_set_operands(self._h, 1 if fp32 else 0))
+
     def forward(self, X) -> np.ndarray:
         X = _f32(X).reshape(-1, self.n_in)
         Y = np.zeros((X.shape[0], self.n_out), dtype=np.float32)

@@ -118,3 +118,39 @@ def test_topk_is_exact_with_ties_and_nan(dtb):
         key = np.where(np.isnan(s), np.inf, s)
         order = np.lexsort((np.arange(n), key))[:k]
         np.testing.assert_array_equal(idx, order)
+
+
+def _close_per_tensor(a, b, tol):
+    """max over entries of |a - b| / (|b| + mean |b|) <= tol."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    r = float((np.abs(a - b) / (np.abs(b) + np.mean(np.abs(b)))).max())
+    assert r <= tol, r
+    return r
+
+
+@pytest.mark.parametrize("B", [256, 77])
+def test_fp32_operands_match_unrounded_reference_elementwise(dtb, B):
+    """The kernels' logic (tiling, transposes, tails, epilogues, MSE, bias
+    sums) with every matrix operand in FP32: the output and every gradient
+    entry within 1e-5 of the unrounded FP64 reference, per entry relative
+    to |ref| + mean |ref| of its tensor (FP32 arithmetic of the same
+    products gives about 2e-6 on this measure).  Switching back to bfloat16
+    operands restores the rounded path."""
+    shp, theta, X, T = _rand(2, B)
+    m = dtb.MLP(*DIMS)
+    m.set_params(theta)
+    Yb = m.forward(X)
+    m.set_operands(True)
+    theta64 = theta.astype(np.float64)
+    Y64, _ = ref.forward(theta64, X, shp, bf16=False)
+    _close_per_tensor(m.forward(X), Y64, 1e-5)
+    loss, g = m.grad(X, T)
+    l64, g64 = ref.loss_and_grad(theta64, X, T, shp, bf16=False)
+    assert abs(loss - l64) <= 1e-5 * abs(l64)
+    o = 0
+    for (r, c) in shp:
+        for size in (r * c, r):
+            _close_per_tensor(g[o:o + size], g64[o:o + size], 1e-5)
+            o += size
+    m.set_operands(False)
+    np.testing.assert_array_equal(m.forward(X), Yb)

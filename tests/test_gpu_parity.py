@@ -265,16 +265,21 @@ def test_many_bundles_teacher_forced(dtb):
 
 
 def test_launch_shapes_give_identical_results(dtb):
-    """Bundle size and tiles per round change only the schedule: every
-    shape produces the same raster, state and counters bit for bit (and the
-    raster matches the reference)."""
+    """Bundle size, tiles per round and where the row sums run change only
+    the schedule: every shape produces the same raster, state and counters
+    bit for bit (and the raster matches the reference), also under graph
+    replay."""
     net = netgen.make_network(netgen.small_net(seed_offset=5))
     T = 80
     ref = oracle.OracleNet(net).run(T, want_margin=True)
     runs = []
-    for bs, u in [(0, 0), (4096, 1), (4096, 2), (4096, 3), (20000, 1), (65536, 3)]:
-        g = _gpu(dtb, net, bundle_syn=bs, unroll=u)
-        g.step(T)
+    for bs, u, f in [(0, 0, 0), (4096, 1, 2), (4096, 2, 1), (4096, 3, 2), (20000, 1, 1), (65536, 3, 2)]:
+        g = _gpu(dtb, net, bundle_syn=bs, unroll=u, fuse=f)
+        if f == 2:
+            g.run(T // 2)  # graph replay of the separate-sums launch sequence
+            g.step(T - T // 2)
+        else:
+            g.step(T)
         runs.append((g.raster(0, T), g.state("V"), g.state("j_AMPA"), g.counters()))
         g.close()
     _check_raster(runs[0][0], net, ref)
