@@ -82,12 +82,17 @@ def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) ->
     return 5.0 * nnz + w_bytes * events + n * (2 * 21 + 2) + n * (max_delay + 1) / 8.0
 
 
+def _shape_dict(shape):
+    """The gather's launch shape as reported (None = library default)."""
+    return {k: (v or None) for k, v in zip(("bundle_syn", "unroll", "fuse", "events"), shape)}
+
+
 def _spread(xs):
     xs = sorted(xs)
     return {"median": float(np.median(xs)), "min": float(xs[0]), "max": float(xs[-1]), "n": len(xs)}
 
 
-def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0), ou=None, keep_bits=False):
+def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0, 0), ou=None, keep_bits=False):
     """One rate point: burn in to the stationary rate, save, then `reps`
     timed repetitions of `steps` steps from that same state."""
     import torch
@@ -98,7 +103,7 @@ def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0)
     pre = burnin + warmup
     rec = pre + steps if keep_bits else max(steps, 16)
     g = dtb.Net(net, wtype=wtype, record_steps=rec, stream=torch.cuda.current_stream(),
-                bundle_syn=shape[0], unroll=shape[1], fuse=shape[2])
+                bundle_syn=shape[0], unroll=shape[1], fuse=shape[2], events=shape[3])
     torch.cuda.synchronize()
     log(f"[bench] {rate} Hz {wtype}: created in {time.time() - t0:.1f}s; burn-in {burnin} + warmup {warmup}")
     if ou is not None:
@@ -232,7 +237,7 @@ def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: 
     shape = autotune.lookup(n_tot, s_tot, n_members, "f32", max(m.max_delay for m in members))
     stream = torch.cuda.current_stream()
     g = dtb.Net.batch(members, record_steps=64, stream=stream, bundle_syn=shape[0], unroll=shape[1],
-                      fuse=shape[2])
+                      fuse=shape[2], events=shape[3])
     g.set_gains(gains.reshape(-1, 4))
     g.run(warmup)
     g.sync()
@@ -270,7 +275,7 @@ def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: 
         h.close()
     single = {"events_per_s": ev_m / (ms_m * 1e-3), "ms_per_step_all_members": ms_m / per_member_steps,
               "steps_per_member": per_member_steps}
-    return {"gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None, "fuse": shape[2] or None},
+    return {"gather_shape": _shape_dict(shape),
             "workload": f"ensemble: {n_members} members of 50k-400k neurons (20 regions each), "
                         f"{n_tot} neurons, {s_tot} synapses, per-region channel gains, 7 Hz drive, "
                         f"{steps} steps under one captured HIP graph",
@@ -412,19 +417,19 @@ def main():
             r = autotune.tune([net], wtype=wt, record_steps=64, cache_path=autotune.CACHE, burnin=args.burnin,
                               steps=40, stream=torch.cuda.current_stream())
             log(f"[autotune] partition {wt}: {r}")
-            out[f"partition/{wt}"] = {**r, "tried": {f"{b}/{u}/{f}": v for (b, u, f), v in r["tried"].items()}}
+            out[f"partition/{wt}"] = {**r, "tried": {"/".join(map(str, k)): v for k, v in r["tried"].items()}}
         del net
         members, gains = ensemble_members(64)
         for wt in ("f32", "bf16"):
             r = autotune.tune(members, wtype=wt, record_steps=64, cache_path=autotune.CACHE, burnin=200, steps=40,
                               stream=torch.cuda.current_stream())
             log(f"[autotune] ensemble {wt}: {r}")
-            out[f"ensemble/{wt}"] = {**r, "tried": {f"{b}/{u}/{f}": v for (b, u, f), v in r["tried"].items()}}
+            out[f"ensemble/{wt}"] = {**r, "tried": {"/".join(map(str, k)): v for k, v in r["tried"].items()}}
         print(json.dumps({"autotune": out}), flush=True)
         return
     n_neu, n_syn, n_del = net.n, net.nnz, net.max_delay
     shape = autotune.lookup(n_neu, n_syn, 1, args.wtype, n_del)
-    log(f"[bench] gather shape (bundle_syn, unroll, fuse): {shape} (0 = library default)")
+    log(f"[bench] gather shape (bundle_syn, unroll, fuse, events): {shape} (0 = library default)")
     res = {}
     want_split = not args.no_forms and args.wtype == "f32"
     for r in rates:
@@ -509,7 +514,7 @@ def main():
                                   f"{args.burnin} burn-in steps)",
                       "global_batch": 1, "seq_len": args.steps, "parallelism": "single-gpu"},
            "rtf": head["rtf"], "ms_per_step_reps": head["ms_per_step_reps"], "roofline": roof, "cpu_baseline": cpu,
-           "gather_shape": {"bundle_syn": shape[0] or None, "unroll": shape[1] or None, "fuse": shape[2] or None},
+           "gather_shape": _shape_dict(shape),
            "rates": {str(r): point_summary(res[r]) for r in rates},
            "forms": forms or None,
            "kernels_ms_per_step": per}

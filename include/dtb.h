@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 12
+#define DTB_ABI_VERSION 13
 
 typedef enum {
   DTB_OK = 0,
@@ -113,6 +113,15 @@ typedef struct dtb_desc {
                                 kernel over the hit buffer (always so while a remote in-edge
                                 block is set); 0 = library default, 1.  A tuning knob: both
                                 add the same terms in the same order */
+  int32_t gather_events;     /* how the local block's delivery tests are found: 1 = the pull
+                                sweep of each bundle's (delay, source)-sorted synapses over the
+                                delayed spike bitmaps; 2 = spike-driven: the step's spikes of
+                                the last D steps (their id lists) each deliver through their
+                                out-synapses of the matching delay, bucketed per bundle, which
+                                then sets the same hit bits (needs at most 4096 bundles;
+                                DTB_ERR_UNSUPPORTED otherwise); 0 = library default, 1.  A
+                                tuning knob: both find the same hits, so the results are
+                                identical */
 } dtb_desc;
 
 /* ------------------------------------------------------------ library */
@@ -252,9 +261,11 @@ dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int6
  * a pair of hipEvents recorded on the handle's stream.  dtb_read_timing
  * synchronizes, returns the summed durations in ms and the number of timed
  * launches per kernel, in the order neuron update, compaction, gather
- * (delivery tests), sums (per-row sums, background, gates), finalize,
- * remote gather (the remote block's delivery tests, timed on the second
- * stream) (double [6], int64 [6]; either may be NULL), and clears them. */
+ * (delivery tests, with the row sums when they run there), sums (per-row
+ * sums, background, gates), finalize, remote gather (the remote block's
+ * delivery tests, timed on the second stream), events (the bucketing of
+ * spike-driven deliveries) (double [7], int64 [7]; either may be NULL), and
+ * clears them. */
 dtb_status dtb_set_timing(dtb_net* net, int enable);
 dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches);
 
@@ -299,15 +310,17 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps);
  * or n_cands = 0 for the library's list: the largest bundle and the sizes
  * whose bundle count fills whole rounds of the GPU's compute units), times
  * `steps` steps with hipEvents for each lookup-tiles-per-round value 1..3
- * (gather_unroll) and each placement of the row sums 1..2 (gather_fuse),
- * and reports the fastest.  Every timing starts from the
+ * (gather_unroll) and each placement of the row sums 1..2 (gather_fuse) of
+ * the sweep, and for each placement with spike-driven delivery
+ * (gather_events = 2, when the bundles fit it), and reports the fastest.  Every timing starts from the
  * same state - the first candidate's state after `burnin` steps, saved once
  * and loaded before each timing - so all candidates time the same steps
  * (the shapes change only the schedule, never a result).  The members'
- * own gather_bundle_syn / gather_unroll / gather_fuse are ignored.
+ * own gather_bundle_syn / gather_unroll / gather_fuse / gather_events are
+ * ignored.
  * cache_path (may be NULL): a JSON file of tuned shapes keyed by
  * "<gfx arch>|n=..,nnz=..,members=..,w=<f32|bf16>,D=..", one entry per line
- * ({"bundle_syn": b, "unroll": u, "fuse": f, "ms_per_step": ms});
+ * ({"bundle_syn": b, "unroll": u, "fuse": f, "events": v, "ms_per_step": ms});
  * a key already present is returned without timing (from_cache = 1),
  * otherwise the winner is added (the file is rewritten through a temporary
  * file; DTB_ERR_INVALID if it cannot be written).  Work runs on hip_stream
@@ -316,14 +329,15 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps);
  * stepping the candidate networks returns. */
 #define DTB_TUNE_MAX_BUNDLES 8
 typedef struct dtb_tune_result {
-  int32_t bundle_syn, unroll, fuse; /* the fastest shape */
+  int32_t bundle_syn, unroll, fuse, events; /* the fastest shape (unroll 0 with events 2) */
   float ms_per_step;            /* its time per step (from the cache when from_cache) */
   int32_t from_cache;           /* 1: taken from cache_path without timing */
-  int32_t n_tried;              /* shapes timed: candidates x 3 x 2 */
-  int32_t tried_bundle[6 * DTB_TUNE_MAX_BUNDLES];
-  int32_t tried_unroll[6 * DTB_TUNE_MAX_BUNDLES];
-  int32_t tried_fuse[6 * DTB_TUNE_MAX_BUNDLES];
-  float tried_ms[6 * DTB_TUNE_MAX_BUNDLES];
+  int32_t n_tried;              /* shapes timed: per candidate 3 x 2 sweeps + 2 spike-driven */
+  int32_t tried_bundle[8 * DTB_TUNE_MAX_BUNDLES];
+  int32_t tried_unroll[8 * DTB_TUNE_MAX_BUNDLES];
+  int32_t tried_fuse[8 * DTB_TUNE_MAX_BUNDLES];
+  int32_t tried_events[8 * DTB_TUNE_MAX_BUNDLES];
+  float tried_ms[8 * DTB_TUNE_MAX_BUNDLES];
 } dtb_tune_result;
 dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_stream, const char* cache_path,
                         const int32_t* bundle_cands, int32_t n_cands, int32_t burnin, int32_t steps,

@@ -38,7 +38,8 @@ class Desc(ctypes.Structure):
                 ("wtype", ctypes.c_int32), ("record_steps", ctypes.c_int32),
                 ("gather_bundle_syn", ctypes.c_int32),
                 ("gather_unroll", ctypes.c_int32),
-                ("gather_fuse", ctypes.c_int32)]
+                ("gather_fuse", ctypes.c_int32),
+                ("gather_events", ctypes.c_int32)]
 
 
 TUNE_MAX_BUNDLES = 8
@@ -46,12 +47,13 @@ TUNE_MAX_BUNDLES = 8
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("bundle_syn", ctypes.c_int32), ("unroll", ctypes.c_int32), ("fuse", ctypes.c_int32),
-                ("ms_per_step", ctypes.c_float),
+                ("events", ctypes.c_int32), ("ms_per_step", ctypes.c_float),
                 ("from_cache", ctypes.c_int32), ("n_tried", ctypes.c_int32),
-                ("tried_bundle", ctypes.c_int32 * (6 * TUNE_MAX_BUNDLES)),
-                ("tried_unroll", ctypes.c_int32 * (6 * TUNE_MAX_BUNDLES)),
-                ("tried_fuse", ctypes.c_int32 * (6 * TUNE_MAX_BUNDLES)),
-                ("tried_ms", ctypes.c_float * (6 * TUNE_MAX_BUNDLES))]
+                ("tried_bundle", ctypes.c_int32 * (8 * TUNE_MAX_BUNDLES)),
+                ("tried_unroll", ctypes.c_int32 * (8 * TUNE_MAX_BUNDLES)),
+                ("tried_fuse", ctypes.c_int32 * (8 * TUNE_MAX_BUNDLES)),
+                ("tried_events", ctypes.c_int32 * (8 * TUNE_MAX_BUNDLES)),
+                ("tried_ms", ctypes.c_float * (8 * TUNE_MAX_BUNDLES))]
 
 
 # every symbol include/dtb.h declares, with its ctypes signature
@@ -126,7 +128,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 12:
+    if lib.dtb_abi_version() != 13:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

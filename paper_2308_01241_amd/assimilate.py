@@ -6,7 +6,8 @@ Pipeline, all on the GPU through the C ABI:
               steps at unit gains, then `segments` chained windows, each at
               fresh per-population channel gains ~ N(1, 0.2^2) (clipped at
               0); a sample maps (gains, population rates of the window
-              before) -> (population rates of the window, BOLD at its end);
+              before, hemodynamic state at the window's start) ->
+              (population rates of the window, BOLD at its end);
               the default run (157 runs x 10 windows x 64 members) gives
               100,480 training samples;
   2. train  - the MFMA surrogate MLP learns that map (z-scored, Adam, MSE);
@@ -65,6 +66,14 @@ def window_rates(net, S: Setup):
     return net.region_rates(net.t - S.window, net.t).reshape(-1, S.regions)
 
 
+def hemo_state(net, S: Setup):
+    """[members, 4 regions] Balloon-Windkessel state (s, f - 1, v - 1, q - 1)
+    of every population now: where the BOLD of the next window starts from."""
+    _, st = net.bold(state=True)
+    st = st.astype(np.float64) - np.array([0.0, 1.0, 1.0, 1.0])
+    return st.reshape(-1, S.regions * 4).astype(np.float32)
+
+
 def generate(net, S: Setup, n_runs: int, rng, segments: int = 1):
     """n_runs x segments x members samples.  Each run starts from rest with
     one window at unit gains, then `segments` chained windows, each at fresh
@@ -73,7 +82,11 @@ def generate(net, S: Setup, n_runs: int, rng, segments: int = 1):
     gains in the window, its population rates over the window before) to
     (its rates over the window, BOLD at the window's end).  The first
     window of a run is exactly how the re-simulation check runs a proposal.
-    Returns X [samples, 5 R] and Y [samples, 2 R]."""
+    The hemodynamic state at the window's start is an input too: it carries
+    over from window to window, and the BOLD at the window's end depends on
+    it as much as on the window's rates.
+    Returns X [samples, 9 R] (gains 4 R, rates of the window before R,
+    hemodynamic state at the window's start 4 R) and Y [samples, 2 R]."""
     M, R = net.n_members, S.regions
     X, Y = [], []
     for run in range(n_runs):
@@ -83,11 +96,12 @@ def generate(net, S: Setup, n_runs: int, rng, segments: int = 1):
         prev = window_rates(net, S)
         for _ in range(segments):
             g = np.clip(rng.normal(1.0, GAIN_SD, (M, R, 4)), 0.0, None).astype(np.float32)
+            hemo = hemo_state(net, S)
             net.set_gains(g.reshape(-1, 4))
             net.run(S.window)
             rates = window_rates(net, S)
             bold = net.bold().reshape(M, R)
-            X.append(np.concatenate([g.reshape(M, -1), prev], axis=1))
+            X.append(np.concatenate([g.reshape(M, -1), prev, hemo], axis=1))
             Y.append(np.concatenate([rates, 1e3 * bold], axis=1))  # BOLD in 1e-3 units
             prev = rates
         if (run + 1) % 16 == 0 or run + 1 == n_runs:
@@ -171,9 +185,10 @@ class Resim:
         self.net.set_gains(np.ones(((k + 1) * S.regions, 4), dtype=np.float32))
         self.net.run(S.window)
         base = window_rates(self.net, S)
+        hemo = hemo_state(self.net, S)
         self.net.set_gains(full.reshape(-1, 4))
         self.net.run(S.window)
-        return window_rates(self.net, S), 1e3 * self.net.bold().reshape(k + 1, S.regions), base
+        return window_rates(self.net, S), 1e3 * self.net.bold().reshape(k + 1, S.regions), base, hemo
 
     def close(self):
         self.net.close()
@@ -191,8 +206,8 @@ def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096,
     own = resim is None
     resim = resim or Resim(target_net, k, S)
     # the twin: the re-simulation batch's last copy, run at the hidden gains
-    rs, bs, base = resim(np.ones((k, R, 4), dtype=np.float32), twin_gains=hidden_gains)
-    t_rates, t_bold, prev = rs[k].copy(), bs[k].copy(), base[k].copy()
+    rs, bs, base, hemo = resim(np.ones((k, R, 4), dtype=np.float32), twin_gains=hidden_gains)
+    t_rates, t_bold, prev, h0 = rs[k].copy(), bs[k].copy(), base[k].copy(), hemo[k].copy()
     sr, sb = sy.sd[:R], sy.sd[R:]
     mu = np.ones((R, 4), dtype=np.float32)
     best_fit = np.inf
@@ -200,7 +215,8 @@ def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096,
     for it in range(iters):
         sd = GAIN_SD * shrink ** it
         props = np.clip(mu[None] + rng.normal(0, sd, (n_prop, R, 4)), 0.0, None).astype(np.float32)
-        X = np.concatenate([props.reshape(n_prop, -1), np.repeat(prev[None], n_prop, 0)], axis=1)
+        X = np.concatenate([props.reshape(n_prop, -1), np.repeat(prev[None], n_prop, 0),
+                            np.repeat(h0[None], n_prop, 0)], axis=1)
         import torch
         torch.cuda.synchronize()
         tic = time.perf_counter()
@@ -209,12 +225,12 @@ def screen(m, sx, sy, target_net, hidden_gains, S: Setup, iters=10, n_prop=4096,
         best = topk(score, k)
         t_screen = time.perf_counter() - tic
         tic = time.perf_counter()
-        rs, bs, _ = resim(props[best])
+        rs, bs, _, _ = resim(props[best])
         rs, bs = rs[:k], bs[:k]
         t_sim = time.perf_counter() - tic
         fit_s = _fit(rs, bs, t_rates, t_bold, sr, sb)
         rnd = rng.choice(n_prop, k, replace=False)
-        rr, br, _ = resim(props[rnd])
+        rr, br, _, _ = resim(props[rnd])
         rr, br = rr[:k], br[:k]
         fit_r = _fit(rr, br, t_rates, t_bold, sr, sb)
         pb = P[best][:, R:]

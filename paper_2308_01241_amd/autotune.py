@@ -1,6 +1,6 @@
 """Launch-shape autotuner of the gather (binding of dtb_autotune).
 
-Three knobs, none of which changes any result (the summation order is each
+Four knobs, none of which changes any result (the summation order is each
 row's CSR order either way):
 
 * the bundle size (most synapses per workgroup): it sets the LDS hit bitmap
@@ -13,7 +13,11 @@ row's CSR order either way):
 * where the row sums run (1: in the gather's workgroups from the LDS hit
   bitmap, 2: in a separate kernel over the hit buffer): one launch and no
   hit-buffer traffic against a phase per bundle in which its CU issues
-  only the rows' random weight loads.
+  only the rows' random weight loads;
+* how the delivery tests are found (1: the pull sweep of every synapse over
+  the delayed spike bitmaps, 2: spike-driven, the last D steps' spikes each
+  delivering through their out-synapses of the matching delay): bytes per
+  synapse against bytes per delivered event.
 
 The library times each candidate on the real network with HIP events, all
 from one burned-in state, and caches the winner in a JSON file keyed by GPU
@@ -47,22 +51,24 @@ def _arch() -> str:
 
 
 def lookup(n, nnz, n_members=1, wtype="f32", max_delay=20, path=CACHE, arch=None):
-    """Cached (bundle_syn, unroll, fuse) for this shape, or (0, 0, 0) (the
-    library defaults)."""
+    """Cached (bundle_syn, unroll, fuse, events) for this shape, or
+    (0, 0, 0, 0) (the library defaults)."""
     try:
         with open(path) as f:
             db = json.load(f)
     except (OSError, ValueError):
-        return 0, 0, 0
+        return 0, 0, 0, 0
     ent = db.get(shape_key(arch or _arch(), n, nnz, n_members, wtype, max_delay))
-    return (int(ent["bundle_syn"]), int(ent["unroll"]), int(ent.get("fuse", 0))) if ent else (0, 0, 0)
+    if not ent:
+        return 0, 0, 0, 0
+    return int(ent["bundle_syn"]), int(ent["unroll"]), int(ent.get("fuse", 0)), int(ent.get("events", 0))
 
 
 def tune(members, wtype: str = "f32", record_steps: int = 64, cache_path=CACHE, bundles=(), burnin: int = 0,
          steps: int = 20, stream=None) -> dict:
     """dtb_autotune over the network(s) `members` (one: a plain partition,
     several: a batch).  Returns the winning shape, its ms per step, whether
-    it came from the cache, and every timed (bundle_syn, unroll, fuse) -> ms."""
+    it came from the cache, and every timed (bundle_syn, unroll, fuse, events) -> ms."""
     lib = load()
     members = list(members)
     descs = (Desc * len(members))()
@@ -80,8 +86,8 @@ def tune(members, wtype: str = "f32", record_steps: int = 64, cache_path=CACHE, 
                            _ptr(cands) if cands.size else None, int(cands.size), int(burnin), int(steps),
                            ctypes.byref(res)))
     del keep
-    tried = {(int(res.tried_bundle[q]), int(res.tried_unroll[q]), int(res.tried_fuse[q])): float(res.tried_ms[q])
-             for q in range(res.n_tried)}
+    tried = {(int(res.tried_bundle[q]), int(res.tried_unroll[q]), int(res.tried_fuse[q]),
+              int(res.tried_events[q])): float(res.tried_ms[q]) for q in range(res.n_tried)}
     return {"bundle_syn": int(res.bundle_syn), "unroll": int(res.unroll), "fuse": int(res.fuse),
-            "ms_per_step": float(res.ms_per_step),
+            "events": int(res.events), "ms_per_step": float(res.ms_per_step),
             "from_cache": bool(res.from_cache), "tried": tried}

@@ -185,6 +185,7 @@ dtb_status validate(const dtb_desc* s) {
     return fail(DTB_ERR_INVALID, "gather_bundle_syn must be 0 or in [4096, 2^20-1]");
   if (s->gather_unroll < 0 || s->gather_unroll > 3) return fail(DTB_ERR_INVALID, "gather_unroll must be 0 .. 3");
   if (s->gather_fuse < 0 || s->gather_fuse > 2) return fail(DTB_ERR_INVALID, "gather_fuse must be 0 .. 2");
+  if (s->gather_events < 0 || s->gather_events > 2) return fail(DTB_ERR_INVALID, "gather_events must be 0 .. 2");
   if (!(s->dt_ms > 0.f) || !finite_f(s->dt_ms)) return fail(DTB_ERR_INVALID, "dt_ms must be finite and > 0");
   for (int u = 0; u < 4; ++u) {
     if (!(s->tau_ms[u] > 0.f) || !finite_f(s->tau_ms[u]))
@@ -263,7 +264,108 @@ struct BlockInput {
   const uint8_t* delay;
   const uint8_t* src_inh;
   int32_t bundle_syn;
+  bool events;      // spike-driven delivery table instead of the sorted lookup tiles
+  int64_t n_src;    // sources (the event table's rows)
 };
+
+// The spike-driven delivery table of a block: every synapse as (bundle <<
+// kPosBits | position in its bundle), grouped by source and, inside a
+// source, by delay, otherwise in CSR order (a stable counting sort on host
+// threads): the deliveries of source m through delay d are entries
+// [soff[m (D+1) + d - 1], soff[m (D+1) + d]).  Plus the per-bundle buckets
+// the step's deliveries are sorted into.
+dtb_status build_events(dtb_net* net, ConnBlock& cb, const BlockInput* s, const std::vector<Bundle>& bl) {
+  const int D = net->d.max_delay;
+  const int64_t nb = int64_t(bl.size()), nnz = s->nnz, ns = s->n_src;
+  if (nb > kEventMaxBundles)
+    return fail(DTB_ERR_UNSUPPORTED, "spike-driven delivery takes at most " + std::to_string(kEventMaxBundles) +
+                                         " bundles (" + std::to_string(nb) + " here): raise gather_bundle_syn");
+  const unsigned T = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  // thread q takes bundles [cut[q], cut[q+1]) with about nnz / T synapses
+  std::vector<int64_t> cut(T + 1, nb);
+  cut[0] = 0;
+  {
+    int64_t b = 0, acc = 0;
+    for (unsigned q = 1; q < T; ++q) {
+      const int64_t goal = nnz * int64_t(q) / int64_t(T);
+      while (b < nb && acc + bl[b].nsyn <= goal) acc += bl[b++].nsyn;
+      cut[q] = b;
+    }
+  }
+  auto on_threads = [&](const std::function<void(unsigned)>& fn) {
+    std::vector<std::thread> th;
+    for (unsigned q = 0; q < T; ++q) th.emplace_back([&fn, q] { fn(q); });
+    for (auto& x : th) x.join();
+  };
+  std::vector<std::vector<uint32_t>> hist(T);
+  on_threads([&](unsigned q) {
+    hist[q].assign(size_t(ns), 0u);
+    for (int64_t b = cut[q]; b < cut[q + 1]; ++b)
+      for (int64_t k = bl[b].syn0; k < bl[b].syn0 + bl[b].nsyn; ++k) hist[q][s->col[k]]++;
+  });
+  // run starts per source, then each thread's place inside every run
+  std::vector<uint32_t> start(size_t(ns) + 1, 0u);
+  parallel_for(ns, [&](int64_t a, int64_t b) {
+    for (int64_t m = a; m < b; ++m) {
+      uint32_t c = 0;
+      for (unsigned q = 0; q < T; ++q) c += hist[q][m];
+      start[m + 1] = c;
+    }
+  });
+  for (int64_t m = 0; m < ns; ++m) start[m + 1] += start[m];
+  parallel_for(ns, [&](int64_t a, int64_t b) {
+    for (int64_t m = a; m < b; ++m) {
+      uint32_t o = start[m];
+      for (unsigned q = 0; q < T; ++q) {
+        const uint32_t c = hist[q][m];
+        hist[q][m] = o;
+        o += c;
+      }
+    }
+  });
+  std::vector<uint32_t> ent(size_t(std::max<int64_t>(1, nnz)));
+  std::vector<uint8_t> dl(size_t(std::max<int64_t>(1, nnz)));
+  on_threads([&](unsigned q) {
+    for (int64_t b = cut[q]; b < cut[q + 1]; ++b)
+      for (int64_t k = bl[b].syn0; k < bl[b].syn0 + bl[b].nsyn; ++k) {
+        const uint32_t o = hist[q][s->col[k]]++;
+        ent[o] = (uint32_t(b) << kPosBits) | uint32_t(k - bl[b].syn0);
+        dl[o] = s->delay[k];
+      }
+  });
+  std::vector<std::vector<uint32_t>>().swap(hist);
+  // inside each source's run: stable by delay, and the (source, delay) runs
+  std::vector<uint32_t> soff(size_t(ns) * (D + 1));
+  parallel_for(ns, [&](int64_t a, int64_t b) {
+    std::vector<uint32_t> tmp;
+    uint32_t c[kMaxDelay + 2];
+    for (int64_t m = a; m < b; ++m) {
+      const uint32_t r0 = start[m], r1 = start[m + 1];
+      std::fill(c, c + D + 2, 0u);
+      for (uint32_t o = r0; o < r1; ++o) c[dl[o]]++;
+      uint32_t* so = &soff[size_t(m) * (D + 1)];
+      so[0] = r0;
+      for (int d = 1; d <= D; ++d) so[d] = so[d - 1] + c[d];
+      tmp.assign(ent.begin() + r0, ent.begin() + r1);
+      uint32_t at[kMaxDelay + 1];
+      for (int d = 1; d <= D; ++d) at[d] = so[d - 1];
+      for (uint32_t o = r0; o < r1; ++o) ent[at[dl[o]]++] = tmp[o - r0];
+    }
+  });
+  std::vector<uint8_t>().swap(dl);
+  dtb_status st;
+  if ((st = dalloc(net, &cb.ev_ent, std::max<int64_t>(1, nnz))) ||
+      (st = dalloc(net, &cb.ev_soff, std::max<int64_t>(1, ns * (D + 1)))) ||
+      (st = dalloc(net, &cb.evbuf, std::max<int64_t>(1, nnz))) || (st = dalloc(net, &cb.ev_cursor, nb)))
+    return st;
+  if ((st = upload(net, cb.ev_ent, ent.data(), size_t(nnz) * 4)) ||
+      (st = upload(net, cb.ev_soff, soff.data(), soff.size() * 4)))
+    return st;
+  hipError_t e = hipMemsetAsync(cb.ev_cursor, 0, size_t(nb) * 4, net->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) return hip_fail(net, e, "event buckets");
+  return DTB_OK;
+}
 
 dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {
   const DeviceNet& d = net->d;
@@ -295,8 +397,9 @@ dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {
   }
   const int64_t nb = int64_t(bl.size());
   // 2. per bundle: sort by (delay, source, position) and cut into tiles
+  // (the sweep's lookup stream; the spike-driven delivery does without)
   std::vector<std::vector<uint32_t>> btiles(nb), bheads(nb);
-  parallel_items(nb, [&](int64_t q) {
+  if (!s->events) parallel_items(nb, [&](int64_t q) {
     const Bundle& b = bl[q];
     std::vector<uint64_t> key(size_t(b.nsyn));
     for (int32_t p = 0; p < b.nsyn; ++p) {
@@ -363,14 +466,18 @@ dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {
   cb.n_tiles = ntiles;
   cb.hit_words = hw;
   cb.hit_total_words = hwords;
-  // contiguous bundle ranges per XCD with about equal numbers of tiles
+  // contiguous bundle ranges per XCD with about equal work: tiles of the
+  // lookup stream (sweep) or synapses (spike-driven)
   int64_t xf[9];
   {
+    auto work = [&](int64_t q) { return s->events ? int64_t(bl[q].nsyn) : int64_t(bl[q].ntiles); };
+    int64_t tot = 0;
+    for (int64_t q = 0; q < nb; ++q) tot += work(q);
     xf[0] = 0;
     int64_t acc = 0, q = 0;
     for (int x = 1; x < 8; ++x) {
-      const int64_t goal = (ntiles * x + 7) / 8;
-      while (q < nb && acc + bl[q].ntiles <= goal) acc += bl[q++].ntiles;
+      const int64_t goal = (tot * x + 7) / 8;
+      while (q < nb && acc + work(q) <= goal) acc += work(q++);
       xf[x] = q;
     }
     xf[8] = nb;
@@ -417,6 +524,7 @@ dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {
     std::vector<uint32_t>().swap(btiles[q]);
     std::vector<uint32_t>().swap(bheads[q]);
   }
+  if (s->events && (st = build_events(net, cb, s, bl))) return st;
   // 3. weights in CSR order with the sign bit marking an inhibitory source
   const int64_t chunk = int64_t(1) << 26;
   std::vector<uint8_t> hwt;
@@ -445,7 +553,8 @@ dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {
 }
 
 dtb_status build_connections(dtb_net* net, const dtb_desc* s) {
-  BlockInput in{s->n, s->nnz, s->row_ptr, s->col, s->w, s->delay, s->is_inh, s->gather_bundle_syn};
+  BlockInput in{s->n, s->nnz, s->row_ptr, s->col, s->w, s->delay, s->is_inh, s->gather_bundle_syn,
+                net->d.events != 0, s->n};
   return build_block(net, net->d.loc, &in);
 }
 
@@ -557,6 +666,8 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
   d.wtype = desc->wtype;
   d.unroll = desc->gather_unroll ? desc->gather_unroll : kGatherUnroll;
   d.fuse = desc->gather_fuse ? desc->gather_fuse : 1;
+  d.events = desc->gather_events == 2 ? 1 : 0;
+  d.id_slots = d.events ? desc->max_delay + 1 : 1;
   d.rec = desc->record_steps;
   d.slots = std::max(d.rec, d.max_delay) + 1;
   d.bg_w = desc->bg_w;
@@ -582,8 +693,8 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
       (st = dalloc(net, &d.poisson, std::max(1, d.poisson_K))) ||
       (st = dalloc(net, &d.raster, slots * d.words_pad)) ||
       (st = dalloc(net, &d.counts, slots * d.n_regions)) || (st = dalloc(net, &d.ev, slots * kStripes * 2)) ||
-      (st = dalloc(net, &d.totals, 4)) || (st = dalloc(net, &d.ids, d.n_pad)) ||
-      (st = dalloc(net, &d.id_count, 1)) || (st = dalloc(net, &d.cstatus, d.compact_blocks)) ||
+      (st = dalloc(net, &d.totals, 4)) || (st = dalloc(net, &d.ids, int64_t(d.id_slots) * d.n_pad)) ||
+      (st = dalloc(net, &d.id_count, d.id_slots)) || (st = dalloc(net, &d.cstatus, d.compact_blocks)) ||
       (st = dalloc(net, &d.cticket, 1)) || (st = dalloc(net, &d.force, (d.rec + 1) * d.words_pad)) ||
       (st = dalloc(net, &d.bad, 1)) || (st = dalloc(net, &d.step, 2)) ||
       (st = dalloc(net, &d.inv_nr_dt, d.n_regions)) || (st = dalloc(net, &d.bold, 4 * d.n_regions)) ||
@@ -599,7 +710,7 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
   for (auto pr : std::vector<std::pair<void*, size_t>>{
            {d.j, 4 * d.n_pad * sizeof(float)}, {d.ref, size_t(d.n_pad)},
            {d.raster, slots * d.words_pad * 4}, {d.counts, slots * d.n_regions * 4},
-           {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32}, {d.id_count, 4},
+           {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32}, {d.id_count, size_t(d.id_slots) * 4},
            {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.ptype, d.n_pad * 2},
            {d.region, d.n_pad * 4}, {d.V, d.n_pad * 4}, {d.step, 16}, {d.bold, size_t(d.n_regions) * 16},
            {d.bold_y, size_t(d.n_regions) * 4}, {d.rd_status, d.compact_blocks * 8}, {d.rd_count, 4}}) {
@@ -857,8 +968,14 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
     // block is set: then both blocks' hit bits go to k_sums (local, then
     // remote)
     const bool fuse = !net->remote && d.fuse == 1;
-    if (e == hipSuccess)
+    if (d.events) {
+      // spike-driven delivery: the step's deliveries into per-bundle buckets,
+      // then each bundle's hit bitmap from its bucket
+      if (e == hipSuccess) e = timed(net, 6, [&] { return launch_events(d, net->stream); });
+      if (e == hipSuccess) e = timed(net, 2, [&] { return launch_gather_events(d, fuse, net->stream); });
+    } else if (e == hipSuccess) {
       e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, fuse, net->stream); });
+    }
     if (e == hipSuccess && net->remote) {
       // J_inter after J_intra, once the remote spikes are in (the paper's
       // computing-thread order); its delivery tests OR into their own hit
@@ -894,7 +1011,12 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
     for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
       e = launch_neuron_update(d, nullptr, net->stream);
       if (e == hipSuccess) e = launch_compact(d, net->stream);
-      if (e == hipSuccess) e = launch_gather(d, d.loc, d.raster, d.words_pad, d.fuse == 1, net->stream);
+      if (d.events) {
+        if (e == hipSuccess) e = launch_events(d, net->stream);
+        if (e == hipSuccess) e = launch_gather_events(d, d.fuse == 1, net->stream);
+      } else if (e == hipSuccess) {
+        e = launch_gather(d, d.loc, d.raster, d.words_pad, d.fuse == 1, net->stream);
+      }
       if (e == hipSuccess && d.fuse != 1) e = launch_sums(d, net->stream);
       if (e == hipSuccess) e = launch_finalize(d, net->stream);
     }
@@ -921,7 +1043,8 @@ dtb_status dtb_reset(dtb_net* net) {
   for (auto pr : std::vector<std::pair<void*, size_t>>{
            {d.j, 4 * d.n_pad * sizeof(float)}, {d.ref, size_t(d.n_pad)}, {d.raster, slots * d.words_pad * 4},
            {d.counts, slots * d.n_regions * 4}, {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32},
-           {d.id_count, 4}, {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.step, 16},
+           {d.id_count, size_t(d.id_slots) * 4}, {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4},
+           {d.step, 16},
            {d.bold, size_t(d.n_regions) * 16}, {d.bold_y, size_t(d.n_regions) * 4}}) {
     if (e == hipSuccess) e = hipMemsetAsync(pr.first, 0, pr.second, net->stream);
   }
@@ -1025,7 +1148,7 @@ dtb_status dtb_set_remote_block(dtb_net* net, int64_t n_remote, int64_t nnz, con
   if (bad >= 0) return fail(DTB_ERR_INVALID, "delay out of [1, max_delay] at synapse " + std::to_string(bad));
   bad = find_first(nnz, [&](int64_t k) { return !(finite_f(w[k]) && w[k] >= 0.f); });
   if (bad >= 0) return fail(DTB_ERR_INVALID, "weight not finite and >= 0 at synapse " + std::to_string(bad));
-  BlockInput in{d.n, nnz, row_ptr, col, w, delay, remote_is_inh, 0};
+  BlockInput in{d.n, nnz, row_ptr, col, w, delay, remote_is_inh, 0, false, n_remote};
   if ((st = build_block(net, d.rem, &in))) return st;
   d.n_remote = n_remote;
   d.rwords_pad = round_up(n_remote, kNeuronPad) / 32;
@@ -1143,8 +1266,9 @@ dtb_status dtb_read_spike_ids(dtb_net* net, int64_t t, int32_t* ids, int64_t cap
   if (!count || cap < 0 || (cap > 0 && !ids)) return fail(DTB_ERR_INVALID, "bad ids / cap / count");
   if ((st = window(net, t, t + 1))) return st;
   DeviceNet& d = net->d;
-  const int32_t* src_ids = d.ids;
-  const int32_t* src_count = d.id_count;
+  const int64_t islot = t % d.id_slots;  // step t's list, while it is the last step
+  const int32_t* src_ids = d.ids + islot * d.n_pad;
+  const int32_t* src_count = d.id_count + islot;
   if (t != net->t - 1) {
     // an earlier step: rebuild its list from the step's ring slot with the
     // same compaction kernel, on the read's own look-back words
@@ -1277,8 +1401,7 @@ std::vector<std::pair<void*, size_t>> state_sections(const dtb_net* net, int32_t
       {d.ref, np},             {d.gain, 4 * R * 4},
       {d.raster, slots * size_t(d.words_pad) * 4},
       {d.counts, slots * R * 4}, {d.ev, slots * kStripes * 2 * 8},
-      {d.totals, 4 * 8},       {d.ids, np * 4},
-      {d.id_count, 4},         {d.step, 2 * 8},
+      {d.totals, 4 * 8},       {d.step, 2 * 8},
       {d.bold, 4 * R * 4},     {d.bold_y, R * 4}};
   if (ou_on) v.emplace_back(d.ou, np * 4);
   if (net->remote) v.emplace_back(d.rraster, slots * size_t(d.rwords_pad) * 4);
@@ -1381,6 +1504,20 @@ dtb_status dtb_load(dtb_net* net, const void* host_buf, size_t len) {
   if (e == hipSuccess) e = hipMemsetAsync(d.cstatus, 0, size_t(d.compact_blocks) * 8, net->stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.cticket, 0, 4, net->stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.bad, 0, 4, net->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d.id_count, 0, size_t(d.id_slots) * 4, net->stream);
+  // the spike-id lists still needed (the last step's; with spike-driven
+  // delivery the last D steps') are rebuilt from the restored bitmaps
+  const int64_t keep = d.id_slots == 1 ? 1 : int64_t(d.max_delay);
+  for (int64_t q = std::max<int64_t>(0, h.t - keep); q < h.t && e == hipSuccess; ++q) {
+    const int64_t at[2] = {net->read_epoch++, q % d.slots};
+    const int64_t sl = q % d.id_slots;
+    e = hipMemcpyAsync(d.rd_at, at, sizeof(at), hipMemcpyHostToDevice, net->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d.rd_ticket, 0, 4, net->stream);
+    if (e == hipSuccess)
+      e = launch_compact_read(d, d.rd_at, d.ids + sl * d.n_pad, d.id_count + sl, d.rd_status, d.rd_ticket,
+                              d.rd_total, net->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);  // `at` lives until here
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
   if (e != hipSuccess) return hip_fail(net, e, "load");
   d.poisson_K = h.poisson_K;
@@ -1403,13 +1540,13 @@ dtb_status dtb_load(dtb_net* net, const void* host_buf, size_t len) {
 namespace {
 
 struct TuneEntry {
-  int32_t bundle_syn = 0, unroll = 0, fuse = 0;
+  int32_t bundle_syn = 0, unroll = 0, fuse = 0, events = 0;
   double ms = 0.0;
 };
 
 // Cache file: one JSON object, one entry per line,
 //   "<arch>|n=<n>,nnz=<nnz>,members=<m>,w=<f32|bf16>,D=<D>":
-//       {"bundle_syn": b, "unroll": u, "fuse": f, "ms_per_step": ms}
+//       {"bundle_syn": b, "unroll": u, "fuse": f, "events": v, "ms_per_step": ms}
 // Lines that do not parse are dropped when the file is rewritten.
 std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
   std::map<std::string, TuneEntry> db;
@@ -1422,8 +1559,8 @@ std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
     if (b == std::string::npos) continue;
     TuneEntry e;
     const char* rest = line.c_str() + b + 1;
-    if (std::sscanf(rest, " : {\"bundle_syn\": %d, \"unroll\": %d, \"fuse\": %d, \"ms_per_step\": %lf",
-                    &e.bundle_syn, &e.unroll, &e.fuse, &e.ms) == 4)
+    if (std::sscanf(rest, " : {\"bundle_syn\": %d, \"unroll\": %d, \"fuse\": %d, \"events\": %d, \"ms_per_step\": %lf",
+                    &e.bundle_syn, &e.unroll, &e.fuse, &e.events, &e.ms) == 5)
       db[line.substr(a + 1, b - a - 1)] = e;
   }
   return db;
@@ -1437,9 +1574,10 @@ bool write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& 
     f << "{\n";
     size_t q = 0;
     for (const auto& kv : db) {
-      char buf[192];
-      std::snprintf(buf, sizeof(buf), ": {\"bundle_syn\": %d, \"unroll\": %d, \"fuse\": %d, \"ms_per_step\": %.6f}",
-                    kv.second.bundle_syn, kv.second.unroll, kv.second.fuse, kv.second.ms);
+      char buf[224];
+      std::snprintf(buf, sizeof(buf),
+                    ": {\"bundle_syn\": %d, \"unroll\": %d, \"fuse\": %d, \"events\": %d, \"ms_per_step\": %.6f}",
+                    kv.second.bundle_syn, kv.second.unroll, kv.second.fuse, kv.second.events, kv.second.ms);
       f << "\"" << kv.first << "\"" << buf << (++q < db.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -1488,6 +1626,7 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
       out->bundle_syn = it->second.bundle_syn;
       out->unroll = it->second.unroll;
       out->fuse = it->second.fuse;
+      out->events = it->second.events;
       out->ms_per_step = float(it->second.ms);
       out->from_cache = 1;
       return DTB_OK;
@@ -1518,59 +1657,73 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
     return fail(DTB_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
   }
   dtb_status st = DTB_OK;
+  // per candidate bundle size: the sweep with 1..3 tiles per round and either
+  // placement of the row sums, then the spike-driven delivery with either
+  // placement (when the bundles fit its 4096 ids)
   for (size_t c = 0; c < cands.size() && st == DTB_OK; ++c) {
-    for (auto& x : ds) {
-      x.gather_bundle_syn = cands[c];
-      x.gather_unroll = 0;
-      x.gather_fuse = 0;
-    }
-    dtb_net* net = nullptr;
-    st = n_members == 1 ? dtb_create(ds.data(), hip_stream, &net) : dtb_create_batch(ds.data(), n_members, hip_stream, &net);
-    if (st) break;
-    if (saved.empty()) {
-      // one burned-in state shared by every candidate: each times the same steps
-      size_t used = 0;
-      if (!(st = dtb_step(net, burnin)) && !(st = dtb_save(net, nullptr, 0, &used))) {
-        saved.resize(used);
-        st = dtb_save(net, saved.data(), saved.size(), &used);
+    for (int32_t mode = 1; mode <= 2 && st == DTB_OK; ++mode) {
+      for (auto& x : ds) {
+        x.gather_bundle_syn = cands[c];
+        x.gather_unroll = 0;
+        x.gather_fuse = 0;
+        x.gather_events = mode;
       }
-    }
-    for (int32_t v = 0; v < 6 && st == DTB_OK; ++v) {
-      const int32_t u = 1 + v % 3, fz = 1 + v / 3;
-      net->d.unroll = u;
-      net->d.fuse = fz;
-      drop_graph(net);
-      if ((st = dtb_load(net, saved.data(), saved.size()))) break;
-      e = hipEventRecord(ea, net->stream);
-      if (e == hipSuccess && (st = dtb_step(net, steps))) break;
-      if (e == hipSuccess) e = hipEventRecord(eb, net->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(eb);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
-      if (e != hipSuccess) {
-        st = fail(DTB_ERR_HIP, std::string("autotune timing: ") + hipGetErrorString(e));
-        break;
+      dtb_net* net = nullptr;
+      st = n_members == 1 ? dtb_create(ds.data(), hip_stream, &net)
+                          : dtb_create_batch(ds.data(), n_members, hip_stream, &net);
+      if (st == DTB_ERR_UNSUPPORTED && mode == 2) {  // too many bundles for the event table
+        st = DTB_OK;
+        continue;
       }
-      const int q = out->n_tried++;
-      out->tried_bundle[q] = cands[c];
-      out->tried_unroll[q] = u;
-      out->tried_fuse[q] = fz;
-      out->tried_ms[q] = ms / float(steps);
-      if (q == 0 || out->tried_ms[q] < out->ms_per_step) {
-        out->bundle_syn = cands[c];
-        out->unroll = u;
-        out->fuse = fz;
-        out->ms_per_step = out->tried_ms[q];
+      if (st) break;
+      if (saved.empty()) {
+        // one burned-in state shared by every candidate: each times the same steps
+        size_t used = 0;
+        if (!(st = dtb_step(net, burnin)) && !(st = dtb_save(net, nullptr, 0, &used))) {
+          saved.resize(used);
+          st = dtb_save(net, saved.data(), saved.size(), &used);
+        }
       }
+      const int32_t nv = mode == 1 ? 6 : 2;
+      for (int32_t v = 0; v < nv && st == DTB_OK; ++v) {
+        const int32_t u = mode == 1 ? 1 + v % 3 : 0, fz = mode == 1 ? 1 + v / 3 : 1 + v;
+        net->d.unroll = u ? u : kGatherUnroll;
+        net->d.fuse = fz;
+        drop_graph(net);
+        if ((st = dtb_load(net, saved.data(), saved.size()))) break;
+        e = hipEventRecord(ea, net->stream);
+        if (e == hipSuccess && (st = dtb_step(net, steps))) break;
+        if (e == hipSuccess) e = hipEventRecord(eb, net->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(eb);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+        if (e != hipSuccess) {
+          st = fail(DTB_ERR_HIP, std::string("autotune timing: ") + hipGetErrorString(e));
+          break;
+        }
+        const int q = out->n_tried++;
+        out->tried_bundle[q] = cands[c];
+        out->tried_unroll[q] = u;
+        out->tried_fuse[q] = fz;
+        out->tried_events[q] = mode;
+        out->tried_ms[q] = ms / float(steps);
+        if (q == 0 || out->tried_ms[q] < out->ms_per_step) {
+          out->bundle_syn = cands[c];
+          out->unroll = u;
+          out->fuse = fz;
+          out->events = mode;
+          out->ms_per_step = out->tried_ms[q];
+        }
+      }
+      dtb_destroy(net);
     }
-    dtb_destroy(net);
   }
   (void)hipEventDestroy(ea);
   (void)hipEventDestroy(eb);
   if (st) return st;
   if (cache_path) {
     auto db = read_tune_cache(cache_path);
-    db[key] = TuneEntry{out->bundle_syn, out->unroll, out->fuse, double(out->ms_per_step)};
+    db[key] = TuneEntry{out->bundle_syn, out->unroll, out->fuse, out->events, double(out->ms_per_step)};
     if (!write_tune_cache(cache_path, db))
       return fail(DTB_ERR_INVALID, std::string("cannot write the tuning cache ") + cache_path);
   }

@@ -79,7 +79,7 @@ static_assert(kUpdateNpt == 1 || kUpdateNpt == 2 || kUpdateNpt == 4, "neurons pe
 #define DTB_GATHER_BUNDLE_SYN 1048575
 #endif
 constexpr int kGatherThreads = DTB_GATHER_THREADS;
-constexpr int kTimedKernels = 6;  // neuron update, compaction, gather, sums, finalize, remote gather
+constexpr int kTimedKernels = 7;  // neuron update, compaction, gather, sums, finalize, remote gather, events
 constexpr int kGatherUnroll = DTB_GATHER_UNROLL;
 constexpr int64_t kBundleDefaultSyn = DTB_GATHER_BUNDLE_SYN;
 static_assert(kBundleDefaultSyn <= kBundleMaxSyn, "bundle positions are 20 bits");
@@ -117,7 +117,20 @@ struct ConnBlock {
                                     // synapse in CSR order (from bit hbit0), rewritten every step
   int64_t* row_ptr = nullptr;       // [n + 1]
   void* wts = nullptr;              // [nnz] float or bf16, sign bit = inhibitory source
+  // spike-driven delivery (gather_events = 2; local block only): the
+  // synapses grouped by source and, within a source, by delay, each as
+  // (bundle << kPosBits | position in the bundle); a step's deliveries are
+  // bucketed per bundle into evbuf (bundle b's bucket at its syn0, room for
+  // all its synapses), ev_cursor[b] entries long
+  uint32_t* ev_ent = nullptr;       // [nnz]
+  uint32_t* ev_soff = nullptr;      // [n_src][D + 1]: (m, d) = [soff[m (D+1) + d - 1], soff[m (D+1) + d])
+  uint32_t* evbuf = nullptr;        // [nnz]
+  int32_t* ev_cursor = nullptr;     // [n_bundles]
 };
+
+constexpr int kEventMaxBundles = 1 << (32 - kPosBits);  // bundle ids fit the 12 high bits of an entry
+constexpr int kEventThreads = 1024;  // threads of the bucketing kernel
+constexpr int kEventGrid = 256;      // its workgroups (one per CU: its LDS staging takes most of a CU's)
 
 // Derived per-type constants in the order the neuron update reads them.
 struct PType {
@@ -135,6 +148,8 @@ struct DeviceNet {
   int32_t wtype = 0, rec = 0;       // rec = record_steps
   int32_t unroll = 3;               // gather lookup tiles per wavefront per round (1 .. 3)
   int32_t fuse = 1;                 // row sums in the gather's workgroups (1) or in k_sums (2)
+  int32_t events = 0;               // 1: the local block's deliveries are spike-driven (event table)
+  int32_t id_slots = 1;             // spike-id lists kept: D + 1 with events (one per delay), else 1
   int32_t slots = 0;                // spike-bitmap ring slots: max(rec, D) + 1
   int32_t poisson_K = 0, poisson_cap = 1;
   int64_t compact_blocks = 0;
@@ -166,8 +181,8 @@ struct DeviceNet {
   int32_t* counts = nullptr;        // [slots][n_regions]
   int64_t* ev = nullptr;            // [slots][kStripes][2] striped (rec, bg); [slot][0][*] final
   int64_t* totals = nullptr;        // [4]: spikes, ev_rec, ev_bg, steps
-  int32_t* ids = nullptr;           // [n_pad] ascending spike ids of the last step
-  int32_t* id_count = nullptr;      // [1]
+  int32_t* ids = nullptr;           // [id_slots][n_pad] ascending spike ids: step t's list in slot t mod id_slots
+  int32_t* id_count = nullptr;      // [id_slots]
   // spike list of an earlier recorded step, rebuilt on request from its
   // ring slot: [0] epoch - 1, [1] slot | ids | count | look-back status words,
   // ticket, spike-total sink
@@ -202,6 +217,12 @@ hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
 // the block's hit buffer for launch_sums
 hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
                          bool fuse_sums, hipStream_t s);
+// spike-driven delivery of the local block: the deliveries of the spikes of
+// steps t .. t-D+1 through their delays, bucketed per bundle (k_events),
+// then per bundle the hit bitmap from its bucket and, like launch_gather,
+// the row sums or the hit words (k_gather on the buckets)
+hipError_t launch_events(const DeviceNet& d, hipStream_t s);
+hipError_t launch_gather_events(const DeviceNet& d, bool fuse_sums, hipStream_t s);
 // observation-error variances of one EnKF analysis, passed by value
 constexpr int kEnkfMaxObs = 64;
 struct EnkfVar {

@@ -208,13 +208,17 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 
 __global__ __launch_bounds__(kCompactBlock) void k_compact(
     const int64_t* __restrict__ step, const uint32_t* __restrict__ raster, int64_t words, int64_t n_blocks,
-    int32_t* __restrict__ ids, int32_t* __restrict__ id_count, uint64_t* __restrict__ status,
-    uint32_t* __restrict__ ticket, int64_t* __restrict__ spike_total) {
+    int32_t* __restrict__ ids, int32_t* __restrict__ id_count, int32_t id_slots, int64_t id_stride,
+    uint64_t* __restrict__ status, uint32_t* __restrict__ ticket, int64_t* __restrict__ spike_total) {
   __shared__ uint32_t s_bid;
   __shared__ int s_wave[kCompactBlock / 64];
   __shared__ int s_excl;
   const uint32_t epoch = uint32_t(uint64_t(step[0]) + 1u);  // never 0 for a live step
   const uint32_t* __restrict__ bits = raster + step[1] * words;
+  // the list of step t goes to slot t mod id_slots (one slot, or one per delay)
+  const int64_t islot = step[0] % id_slots;
+  ids += islot * id_stride;
+  id_count += islot;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_bid = atomicAdd(ticket, 1u);
   __syncthreads();
@@ -327,6 +331,177 @@ __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
   x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x142, 0xA, 0xF, false));  // row_bcast:15
   x += uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x143, 0xC, 0xF, false));  // row_bcast:31
   return x;
+}
+
+// ------------------------------------------------------- spike-driven delivery
+// The deliveries of step t through every delay d = 1..D: each spike m of
+// step t - d + 1 (that step's id list) delivers through its synapses of
+// delay d, entries [soff[m (D+1) + d - 1], soff[m (D+1) + d]) of the event
+// table, each naming (bundle, position in the bundle).  The (delay, spike)
+// pairs are cut into equal shares, one per workgroup.  A workgroup works in
+// rounds: its threads take the next pairs, a block prefix sum of their run
+// lengths places the runs' entries one after another, and up to kEvStage
+// of them are staged in LDS (entry k read by thread k mod T, so the loads
+// of a run are adjacent); they are counted per bundle, sorted by bundle in
+// LDS, each bundle's share reserved in its bucket with one global atomic,
+// and written out bundle by bundle, so a bucket receives contiguous pieces.
+// A run that does not fit continues in the next round.  The order inside a
+// bucket is free: a bucket only sets bits, and every synapse delivers at
+// most once per step, so a bundle's bucket (room for all its synapses)
+// never overflows.
+constexpr int kEvStage = 10240;
+
+__device__ inline uint32_t block_incl_scan(uint32_t x, uint32_t* s_w, uint32_t& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t v = wave_incl_scan_dpp(x);
+  if (lane == 63) s_w[w] = v;
+  __syncthreads();
+  uint32_t add = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < kEventThreads / 64; ++q) {
+    const uint32_t y = s_w[q];
+    if (q < w) add += y;
+    all += y;
+  }
+  __syncthreads();  // s_w is reused by the next scan
+  total = all;
+  return v + add;
+}
+
+__global__ __launch_bounds__(kEventThreads) void k_events(
+    const int64_t* __restrict__ step, const int32_t* __restrict__ ids, const int32_t* __restrict__ id_count,
+    int32_t id_slots, int64_t id_stride, int32_t D, const uint32_t* __restrict__ soff,
+    const uint32_t* __restrict__ ent, const Bundle* __restrict__ bundles, int32_t n_bundles,
+    int32_t* __restrict__ cursor, uint32_t* __restrict__ evbuf) {
+  extern __shared__ uint32_t s_dyn[];
+  uint32_t* s_stage = s_dyn;                    // [kEvStage] the round's entries, in run order
+  uint32_t* s_sorted = s_stage + kEvStage;      // [kEvStage] the same, by bundle
+  uint32_t* s_cnt = s_sorted + kEvStage;        // [n_bundles] entries per bundle this round
+  uint32_t* s_off = s_cnt + n_bundles;          // [n_bundles] their places in s_sorted
+  uint32_t* s_gb = s_off + n_bundles;           // [n_bundles] their first place in the bucket
+  __shared__ int64_t s_pre[kMaxDelay + 1];      // first pair of each delay
+  __shared__ int64_t s_base[kMaxDelay];         // its id list
+  __shared__ uint32_t s_ex[kEventThreads];      // staged entries before each thread's run
+  __shared__ uint32_t s_a[kEventThreads];       // table index of each thread's next entry
+  __shared__ uint32_t s_w[kEventThreads / 64];
+  __shared__ int64_t s_cur;                     // next pair of the share
+  __shared__ uint32_t s_coff;                   // entries of that pair already done
+  const int tid = threadIdx.x;
+  const int64_t t = step[0];
+  if (tid == 0) {
+    int64_t acc = 0;
+    for (int d = 1; d <= D; ++d) {
+      const int64_t e = t - d + 1;  // spikes of step e arrive now through delay d
+      const int64_t sl = e >= 0 ? e % id_slots : 0;
+      s_pre[d - 1] = acc;
+      s_base[d - 1] = sl * id_stride;
+      acc += e >= 0 ? int64_t(id_count[sl]) : 0;
+    }
+    s_pre[D] = acc;
+  }
+  for (int b = tid; b < n_bundles; b += kEventThreads) s_cnt[b] = 0u;
+  __syncthreads();
+  const int64_t R = s_pre[D];
+  const int64_t per = (R + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = min(R, int64_t(blockIdx.x) * per), r1 = min(R, r0 + per);
+  if (tid == 0) {
+    s_cur = r0;
+    s_coff = 0u;
+  }
+  __syncthreads();
+  while (true) {
+    const int64_t cur = s_cur;
+    const uint32_t coff = s_coff;
+    if (cur >= r1) break;  // the same for every thread
+    // this thread's pair and its run of entries
+    const int64_t i = cur + tid;
+    uint32_t a = 0, len = 0;
+    if (i < r1) {
+      int lo = 0, hi = D - 1;  // the delay: the last d with s_pre[d] <= i
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      const int64_t m = ids[s_base[lo] + (i - s_pre[lo])];
+      a = soff[m * (D + 1) + lo];
+      len = soff[m * (D + 1) + lo + 1] - a;
+      if (tid == 0) {
+        a += coff;
+        len -= coff;
+      }
+    }
+    uint32_t total = 0;
+    const uint32_t incl = block_incl_scan(len, s_w, total);
+    s_ex[tid] = incl - len;
+    s_a[tid] = a;
+    const uint32_t K = min(total, uint32_t(kEvStage));
+    __syncthreads();
+    // stage entries [0, K): entry k belongs to the last run starting at or before k
+    for (uint32_t k = tid; k < K; k += kEventThreads) {
+      int lo = 0, hi = kEventThreads - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_ex[mid] <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint32_t e = ent[s_a[lo] + (k - s_ex[lo])];
+      s_stage[k] = e;
+      atomicAdd(&s_cnt[e >> kPosBits], 1u);
+    }
+    if (tid == 0) {
+      if (total <= uint32_t(kEvStage)) {
+        s_cur = cur + min(int64_t(kEventThreads), r1 - cur);
+        s_coff = 0u;
+      } else {  // the run holding entry K - 1 continues in the next round
+        int lo = 0, hi = kEventThreads - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_ex[mid] <= K - 1) lo = mid;
+          else hi = mid - 1;
+        }
+        const uint32_t run_len = (lo + 1 < kEventThreads ? s_ex[lo + 1] : total) - s_ex[lo];
+        const uint32_t done = K - s_ex[lo];
+        if (done == run_len) {
+          s_cur = cur + lo + 1;
+          s_coff = 0u;
+        } else {
+          s_cur = cur + lo;
+          s_coff = (lo == 0 ? coff : 0u) + done;
+        }
+      }
+    }
+    __syncthreads();
+    // places by bundle: exclusive prefix of the counts (each thread sums a
+    // stripe of consecutive bundles), and each bundle's piece of its bucket
+    const int per_t = (n_bundles + kEventThreads - 1) / kEventThreads;
+    const int b0 = min(n_bundles, tid * per_t), b1 = min(n_bundles, b0 + per_t);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += s_cnt[b];
+    uint32_t all = 0;
+    uint32_t run = block_incl_scan(sum, s_w, all) - sum;
+    for (int b = b0; b < b1; ++b) {
+      const uint32_t c = s_cnt[b];
+      s_off[b] = run;
+      run += c;
+      if (c) s_gb[b] = uint32_t(bundles[b].syn0) + uint32_t(atomicAdd(&cursor[b], int32_t(c)));
+    }
+    __syncthreads();
+    for (uint32_t k = tid; k < K; k += kEventThreads) {
+      const uint32_t e = s_stage[k];
+      s_sorted[atomicAdd(&s_off[e >> kPosBits], 1u)] = e;
+    }
+    __syncthreads();
+    // written bundle by bundle: consecutive places of a bundle are adjacent in its bucket
+    for (uint32_t k = tid; k < K; k += kEventThreads) {
+      const uint32_t e = s_sorted[k];
+      const uint32_t b = e >> kPosBits;
+      evbuf[s_gb[b] + (k - (s_off[b] - s_cnt[b]))] = e & kPosMask;
+    }
+    __syncthreads();
+    for (int b = b0; b < b1; ++b) s_cnt[b] = 0u;
+    __syncthreads();
+  }
 }
 
 // Data touched once per step (lookup tiles, row pointers, gates, weights)
@@ -594,14 +769,26 @@ __device__ inline void fused_rows(const uint32_t* s_hits, const Bundle& B, const
   }
 }
 
-template <int kU, int kMode>
+// where a bundle's delivery tests come from: the sweep of its (delay,
+// source)-sorted lookup stream over the delayed spike bitmaps, or its
+// bucket of the step's spike-driven deliveries (k_events)
+constexpr int kFromSweep = 0, kFromEvents = 1;
+
+// a bundle's bucket of deliveries: bundle b's at evbuf + syn0, cursor[b] long
+struct EventSrc {
+  const uint32_t* evbuf;
+  int32_t* cursor;
+};
+
+template <int kU, int kMode, int kSrc>
 __global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kU == 1 && kMode == kHitsOut ? 8 : 4)))
 void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__ step, const Bundle* __restrict__ bundles,
               const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ theads,
               const uint32_t* __restrict__ bitmaps, int64_t words_pad, int32_t slots,
-              uint32_t* __restrict__ hitbuf, int64_t* __restrict__ ev_ring, RowsCsr rows, RowTail A) {
+              uint32_t* __restrict__ hitbuf, int64_t* __restrict__ ev_ring, RowsCsr rows, RowTail A, EventSrc E) {
   extern __shared__ uint32_t s_hits[];
   __shared__ uint32_t s_red[2][kGatherThreads / 64];
+  __shared__ int32_t s_count;
   const int32_t t_mod = int32_t(step[1]);
   int64_t* __restrict__ ev_slot = ev_ring + int64_t(t_mod) * kStripes * 2;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -612,8 +799,21 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
   const Bundle B = bundles[bi];
   const int hw = (B.nsyn >> 5) + 1;  // includes the padding bit at position nsyn
   for (int q = tid; q < hw; q += kGatherThreads) s_hits[q] = 0u;
+  if (kSrc == kFromEvents && tid == 0) s_count = E.cursor[bi];
   __syncthreads();
 
+  if constexpr (kSrc == kFromEvents) {
+    // ---- phase 1 from the bucket: each delivery sets its synapse's bit
+    // (positions < nsyn, each at most once per step); the bucket is emptied
+    // for the next step once every thread has read its count
+    const int cnt = s_count;
+    const uint32_t* __restrict__ bk = E.evbuf + B.syn0;
+    for (int q = tid; q < cnt; q += kGatherThreads) {
+      const uint32_t p = stream_load(bk + q);
+      atomicOr(&s_hits[p >> 5], 1u << (p & 31u));
+    }
+    if (tid == 0) E.cursor[bi] = 0;
+  } else {
   // ---- phase 1: delivery tests in (delay, source) order
   // Software pipeline over rounds of kU tiles per wavefront.  In the stage
   // that takes the hits of round r, the bitmap words of round r+1 are
@@ -680,6 +880,7 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
       }
     }
   }
+  }  // sweep
   __syncthreads();
 
   uint32_t ev = 0, evb = 0;
@@ -970,7 +1171,8 @@ hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipS
 
 hipError_t launch_compact(const DeviceNet& d, hipStream_t s) {
   hipLaunchKernelGGL(k_compact, dim3(unsigned(d.compact_blocks)), dim3(kCompactBlock), 0, s, d.step, d.raster,
-                     d.words_pad, d.compact_blocks, d.ids, d.id_count, d.cstatus, d.cticket, d.totals);
+                     d.words_pad, d.compact_blocks, d.ids, d.id_count, d.id_slots, d.n_pad, d.cstatus, d.cticket,
+                     d.totals);
   return hipGetLastError();
 }
 
@@ -980,7 +1182,7 @@ hipError_t launch_compact(const DeviceNet& d, hipStream_t s) {
 hipError_t launch_compact_read(const DeviceNet& d, const int64_t* at, int32_t* ids, int32_t* count,
                                uint64_t* status, uint32_t* ticket, int64_t* total, hipStream_t s) {
   hipLaunchKernelGGL(k_compact, dim3(unsigned(d.compact_blocks)), dim3(kCompactBlock), 0, s, at, d.raster,
-                     d.words_pad, d.compact_blocks, ids, count, status, ticket, total);
+                     d.words_pad, d.compact_blocks, ids, count, 1, 0, status, ticket, total);
   return hipGetLastError();
 }
 
@@ -991,29 +1193,29 @@ RowTail row_tail(const DeviceNet& d) {
                  d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.bad};
 }
 
-template <int kU, int kMode>
+template <int kU, int kMode, int kSrc>
 void launch_gather_as(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
                       hipStream_t s) {
   const unsigned grid = unsigned(cb.xcd_max * 8);
   const size_t lds = size_t(cb.hit_words) * 4;
-  hipLaunchKernelGGL((k_gather<kU, kMode>), dim3(grid), dim3(kGatherThreads), lds, s, cb.xcd_first, d.step,
+  hipLaunchKernelGGL((k_gather<kU, kMode, kSrc>), dim3(grid), dim3(kGatherThreads), lds, s, cb.xcd_first, d.step,
                      cb.bundles, cb.tiles, cb.theads, bitmaps, words_pad, d.slots, cb.hitbuf, d.ev,
-                     RowsCsr{cb.row_ptr, cb.wts}, row_tail(d));
+                     RowsCsr{cb.row_ptr, cb.wts}, row_tail(d), EventSrc{cb.evbuf, cb.ev_cursor});
 }
 
 template <int kMode>
 void launch_gather_mode(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
                         hipStream_t s) {
   switch (d.unroll) {
-    case 1: launch_gather_as<1, kMode>(d, cb, bitmaps, words_pad, s); break;
-    case 2: launch_gather_as<2, kMode>(d, cb, bitmaps, words_pad, s); break;
-    default: launch_gather_as<3, kMode>(d, cb, bitmaps, words_pad, s); break;
+    case 1: launch_gather_as<1, kMode, kFromSweep>(d, cb, bitmaps, words_pad, s); break;
+    case 2: launch_gather_as<2, kMode, kFromSweep>(d, cb, bitmaps, words_pad, s); break;
+    default: launch_gather_as<3, kMode, kFromSweep>(d, cb, bitmaps, words_pad, s); break;
   }
 }
 
-template <int kU, int kMode>
+template <int kU, int kMode, int kSrc>
 hipError_t set_lds_limit_one(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kU, kMode>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<kU, kMode, kSrc>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -1028,14 +1230,36 @@ hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t
   return hipGetLastError();
 }
 
+hipError_t launch_events(const DeviceNet& d, hipStream_t s) {
+  const ConnBlock& cb = d.loc;
+  if (cb.n_bundles == 0) return hipSuccess;
+  const size_t lds = (2 * size_t(kEvStage) + 3 * size_t(cb.n_bundles)) * 4;
+  hipLaunchKernelGGL(k_events, dim3(kEventGrid), dim3(kEventThreads), lds, s, d.step, d.ids,
+                     d.id_count, d.id_slots, d.n_pad, d.max_delay, cb.ev_soff, cb.ev_ent, cb.bundles,
+                     int32_t(cb.n_bundles), cb.ev_cursor, cb.evbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_events(const DeviceNet& d, bool fuse_sums, hipStream_t s) {
+  const ConnBlock& cb = d.loc;
+  if (cb.n_bundles == 0) return hipSuccess;
+  if (!fuse_sums) launch_gather_as<1, kHitsOut, kFromEvents>(d, cb, nullptr, 0, s);
+  else if (d.wtype == DTB_W_BF16) launch_gather_as<1, kSumBF16, kFromEvents>(d, cb, nullptr, 0, s);
+  else launch_gather_as<1, kSumF32, kFromEvents>(d, cb, nullptr, 0, s);
+  return hipGetLastError();
+}
+
 hipError_t gather_set_lds_limit() {
   const int bytes = kHitWords * 4;
-  hipError_t e = hipSuccess;
-  for (hipError_t x : {set_lds_limit_one<1, kHitsOut>(bytes), set_lds_limit_one<2, kHitsOut>(bytes),
-                       set_lds_limit_one<3, kHitsOut>(bytes), set_lds_limit_one<1, kSumF32>(bytes),
-                       set_lds_limit_one<2, kSumF32>(bytes), set_lds_limit_one<3, kSumF32>(bytes),
-                       set_lds_limit_one<1, kSumBF16>(bytes), set_lds_limit_one<2, kSumBF16>(bytes),
-                       set_lds_limit_one<3, kSumBF16>(bytes)})
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_events),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (2 * kEvStage + 3 * kEventMaxBundles) * 4);
+  for (hipError_t x : {set_lds_limit_one<1, kHitsOut, kFromSweep>(bytes), set_lds_limit_one<2, kHitsOut, kFromSweep>(bytes),
+                       set_lds_limit_one<3, kHitsOut, kFromSweep>(bytes), set_lds_limit_one<1, kSumF32, kFromSweep>(bytes),
+                       set_lds_limit_one<2, kSumF32, kFromSweep>(bytes), set_lds_limit_one<3, kSumF32, kFromSweep>(bytes),
+                       set_lds_limit_one<1, kSumBF16, kFromSweep>(bytes), set_lds_limit_one<2, kSumBF16, kFromSweep>(bytes),
+                       set_lds_limit_one<3, kSumBF16, kFromSweep>(bytes), set_lds_limit_one<1, kHitsOut, kFromEvents>(bytes),
+                       set_lds_limit_one<1, kSumF32, kFromEvents>(bytes), set_lds_limit_one<1, kSumBF16, kFromEvents>(bytes)})
     if (e == hipSuccess) e = x;
   return e;
 }

@@ -55,18 +55,18 @@ class Net:
     """
 
     def __init__(self, network, wtype: str = "f32", record_steps: int = 1024, stream=None, _members=None,
-                 bundle_syn: int = 0, unroll: int = 0, fuse: int = 0):
+                 bundle_syn: int = 0, unroll: int = 0, fuse: int = 0, events: int = 0):
         lib = load()
         self._lib = lib
         h = ctypes.c_void_p()
         if _members is None:
-            d, keep = _make_desc(network, wtype, record_steps, bundle_syn, unroll, fuse)
+            d, keep = _make_desc(network, wtype, record_steps, bundle_syn, unroll, fuse, events)
             check(lib.dtb_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)))
         else:
             descs = (Desc * len(_members))()
             keep = []
             for m, nw in enumerate(_members):
-                d, k = _make_desc(nw, wtype, record_steps, bundle_syn, unroll, fuse)
+                d, k = _make_desc(nw, wtype, record_steps, bundle_syn, unroll, fuse, events)
                 descs[m] = d
                 keep.append(k)
             check(lib.dtb_create_batch(descs, len(_members), _stream_handle(stream), ctypes.byref(h)))
@@ -89,10 +89,10 @@ class Net:
 
     @classmethod
     def batch(cls, members, wtype: str = "f32", record_steps: int = 1024, stream=None, bundle_syn: int = 0,
-              unroll: int = 0, fuse: int = 0) -> "Net":
+              unroll: int = 0, fuse: int = 0, events: int = 0) -> "Net":
         """One handle advancing several independent networks together."""
         return cls(None, wtype=wtype, record_steps=record_steps, stream=stream, _members=list(members),
-                   bundle_syn=bundle_syn, unroll=unroll, fuse=fuse)
+                   bundle_syn=bundle_syn, unroll=unroll, fuse=fuse, events=events)
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -201,10 +201,10 @@ class Net:
 
     def read_timing(self) -> dict:
         """Summed kernel durations (ms) and launch counts since the last read."""
-        ms = np.zeros(6, dtype=np.float64)
-        n = np.zeros(6, dtype=np.int64)
+        ms = np.zeros(7, dtype=np.float64)
+        n = np.zeros(7, dtype=np.int64)
         check(self._lib.dtb_read_timing(self._h, _ptr(ms), _ptr(n)))
-        names = ("neuron_update", "compact", "gather", "sums", "finalize", "remote_gather")
+        names = ("neuron_update", "compact", "gather", "sums", "finalize", "remote_gather", "events")
         return {k: {"ms": float(ms[q]), "launches": int(n[q])} for q, k in enumerate(names)}
 
     def sync(self) -> None:
@@ -262,7 +262,7 @@ class Net:
         return {"steps": v[0].value, "spikes": v[1].value, "ev_rec": v[2].value, "ev_bg": v[3].value}
 
 
-def _make_desc(nw, wtype, record_steps, bundle_syn=0, unroll=0, fuse=0):
+def _make_desc(nw, wtype, record_steps, bundle_syn=0, unroll=0, fuse=0, events=0):
     keep = []
 
     def arr(a, dt):
@@ -304,6 +304,7 @@ def _make_desc(nw, wtype, record_steps, bundle_syn=0, unroll=0, fuse=0):
     d.gather_bundle_syn = int(bundle_syn)
     d.gather_unroll = int(unroll)
     d.gather_fuse = int(fuse)
+    d.gather_events = int(events)
     return d, keep
 
 

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_bitmap_words(lib):
-    assert lib.dtb_abi_version() == 12
+    assert lib.dtb_abi_version() == 13
     assert [lib.dtb_bitmap_words(n) for n in (0, 1, 32, 33, 64)] == [0, 1, 1, 2, 2]
     assert isinstance(lib.dtb_last_error(), bytes)
 
@@ -89,7 +89,7 @@ def _mutations():
 
 
 @pytest.mark.parametrize("kw", [{"unroll": 4}, {"unroll": -1}, {"bundle_syn": 100}, {"bundle_syn": 1 << 20},
-                                {"fuse": 3}, {"fuse": -1}],
+                                {"fuse": 3}, {"fuse": -1}, {"events": 3}, {"events": -1}],
                          ids=lambda k: "_".join(f"{a}{b}" for a, b in k.items()))
 def test_invalid_launch_shapes_are_rejected(lib, kw):
     from paper_2308_01241_amd import DtbError, Net

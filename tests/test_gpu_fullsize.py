@@ -41,8 +41,8 @@ def big():
 def _gpu(dtb, net, **kw):
     import torch
     from paper_2308_01241_amd import autotune
-    b, u, f = autotune.lookup(net.n, net.nnz, 1, kw.get("wtype", "f32"), net.max_delay)
-    return dtb.Net(net, stream=torch.cuda.current_stream(), bundle_syn=b, unroll=u, fuse=f, **kw)
+    b, u, f, v = autotune.lookup(net.n, net.nnz, 1, kw.get("wtype", "f32"), net.max_delay)
+    return dtb.Net(net, stream=torch.cuda.current_stream(), bundle_syn=b, unroll=u, fuse=f, events=v, **kw)
 
 
 @pytest.mark.timeout(900)

@@ -265,16 +265,18 @@ def test_many_bundles_teacher_forced(dtb):
 
 
 def test_launch_shapes_give_identical_results(dtb):
-    """Bundle size, tiles per round and where the row sums run change only
-    the schedule: every shape produces the same raster, state and counters
-    bit for bit (and the raster matches the reference), also under graph
+    """Bundle size, tiles per round, where the row sums run and how the
+    delivery tests are found (sweep or spike-driven) change only the
+    schedule: every shape produces the same raster, state and counters bit
+    for bit (and the raster matches the reference), also under graph
     replay."""
     net = netgen.make_network(netgen.small_net(seed_offset=5))
     T = 80
     ref = oracle.OracleNet(net).run(T, want_margin=True)
     runs = []
-    for bs, u, f in [(0, 0, 0), (4096, 1, 2), (4096, 2, 1), (4096, 3, 2), (20000, 1, 1), (65536, 3, 2)]:
-        g = _gpu(dtb, net, bundle_syn=bs, unroll=u, fuse=f)
+    for bs, u, f, v in [(0, 0, 0, 0), (4096, 1, 2, 1), (4096, 2, 1, 1), (4096, 3, 2, 1), (20000, 1, 1, 1),
+                        (65536, 3, 2, 1), (0, 0, 1, 2), (4096, 0, 2, 2), (65536, 0, 1, 2)]:
+        g = _gpu(dtb, net, bundle_syn=bs, unroll=u, fuse=f, events=v)
         if f == 2:
             g.run(T // 2)  # graph replay of the separate-sums launch sequence
             g.step(T - T // 2)

@@ -20,8 +20,8 @@ def small():
     S = A.Setup(members=16, lo=15_000, hi=30_000, regions=20, window=200, rate_hz=15, target_n=25_000)
     net = dtb.Net.batch(A.member_networks(S, seed=5), record_steps=2 * S.window,
                         stream=torch.cuda.current_stream())
-    X, Y = A.generate(net, S, 48, np.random.default_rng(1))
-    Xt, Yt = A.generate(net, S, 16, np.random.default_rng(2))
+    X, Y = A.generate(net, S, 48, np.random.default_rng(1), segments=3)
+    Xt, Yt = A.generate(net, S, 16, np.random.default_rng(2), segments=3)
     net.close()
     m, sx, sy = A.train(X, Y, epochs=60, batch=128, seed=3)
     target = netgen.make_network(netgen.ensemble_member_spec(41, S.target_n, rate_hz=S.rate_hz,
