@@ -23,6 +23,7 @@
 // multiply-add below is written out, so the arithmetic is the source's.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "dtb_internal.h"
@@ -339,17 +340,20 @@ __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
 // delay d, entries [soff[m (D+1) + d - 1], soff[m (D+1) + d]) of the event
 // table, each naming (bundle, position in the bundle).  The (delay, spike)
 // pairs are cut into equal shares, one per workgroup.  A workgroup works in
-// rounds: its threads take the next pairs, a block prefix sum of their run
-// lengths places the runs' entries one after another, and up to kEvStage
-// of them are staged in LDS (entry k read by thread k mod T, so the loads
-// of a run are adjacent); they are counted per bundle, sorted by bundle in
+// rounds: each thread takes the next kEvRuns pairs, a block prefix sum of
+// their run lengths places the runs' entries one after another, and up to
+// kEvStage of them are staged in LDS (entry k read by thread k mod T, so
+// the loads of a run are adjacent, and all of a thread's loads issued
+// before any is used); they are counted per bundle, sorted by bundle in
 // LDS, each bundle's share reserved in its bucket with one global atomic,
 // and written out bundle by bundle, so a bucket receives contiguous pieces.
 // A run that does not fit continues in the next round.  The order inside a
 // bucket is free: a bucket only sets bits, and every synapse delivers at
 // most once per step, so a bundle's bucket (room for all its synapses)
 // never overflows.
-constexpr int kEvStage = 10240;
+constexpr int kEvStage = 10240;  // entries staged per round
+constexpr int kEvRuns = 2;       // (delay, spike) pairs a thread takes per round
+constexpr int kEvJ = kEvStage / kEventThreads;  // staged entries per thread per round, at most
 
 __device__ inline uint32_t block_incl_scan(uint32_t x, uint32_t* s_w, uint32_t& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -368,11 +372,24 @@ __device__ inline uint32_t block_incl_scan(uint32_t x, uint32_t* s_w, uint32_t& 
   return v + add;
 }
 
+// the last index p in [0, n) with a[p] <= k (a non-decreasing, a[0] <= k)
+template <typename T>
+__device__ inline int last_at_most(const T* a, int n, T k) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kEventThreads) void k_events(
     const int64_t* __restrict__ step, const int32_t* __restrict__ ids, const int32_t* __restrict__ id_count,
     int32_t id_slots, int64_t id_stride, int32_t D, const uint32_t* __restrict__ soff,
     const uint32_t* __restrict__ ent, const Bundle* __restrict__ bundles, int32_t n_bundles,
     int32_t* __restrict__ cursor, uint32_t* __restrict__ evbuf) {
+  constexpr int kRuns = kEventThreads * kEvRuns;  // pairs per round
   extern __shared__ uint32_t s_dyn[];
   uint32_t* s_stage = s_dyn;                    // [kEvStage] the round's entries, in run order
   uint32_t* s_sorted = s_stage + kEvStage;      // [kEvStage] the same, by bundle
@@ -381,8 +398,8 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
   uint32_t* s_gb = s_off + n_bundles;           // [n_bundles] their first place in the bucket
   __shared__ int64_t s_pre[kMaxDelay + 1];      // first pair of each delay
   __shared__ int64_t s_base[kMaxDelay];         // its id list
-  __shared__ uint32_t s_ex[kEventThreads];      // staged entries before each thread's run
-  __shared__ uint32_t s_a[kEventThreads];       // table index of each thread's next entry
+  __shared__ uint32_t s_ex[kRuns];              // staged entries before each pair's run
+  __shared__ uint32_t s_a[kRuns];               // table index of each pair's next entry
   __shared__ uint32_t s_w[kEventThreads / 64];
   __shared__ int64_t s_cur;                     // next pair of the share
   __shared__ uint32_t s_coff;                   // entries of that pair already done
@@ -413,61 +430,69 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
     const int64_t cur = s_cur;
     const uint32_t coff = s_coff;
     if (cur >= r1) break;  // the same for every thread
-    // this thread's pair and its run of entries
-    const int64_t i = cur + tid;
-    uint32_t a = 0, len = 0;
-    if (i < r1) {
-      int lo = 0, hi = D - 1;  // the delay: the last d with s_pre[d] <= i
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] <= i) lo = mid;
-        else hi = mid - 1;
-      }
-      const int64_t m = ids[s_base[lo] + (i - s_pre[lo])];
-      a = soff[m * (D + 1) + lo];
-      len = soff[m * (D + 1) + lo + 1] - a;
-      if (tid == 0) {
-        a += coff;
-        len -= coff;
+    // this thread's pairs cur + kEvRuns tid + h and their runs of entries
+    uint32_t a[kEvRuns], len[kEvRuns];
+#pragma unroll
+    for (int h = 0; h < kEvRuns; ++h) {
+      const int64_t i = cur + kEvRuns * tid + h;
+      a[h] = len[h] = 0u;
+      if (i < r1) {
+        const int d = last_at_most(s_pre, D, i);  // delay d + 1
+        const int64_t m = ids[s_base[d] + (i - s_pre[d])];
+        a[h] = soff[m * (D + 1) + d];
+        len[h] = soff[m * (D + 1) + d + 1] - a[h];
       }
     }
-    uint32_t total = 0;
-    const uint32_t incl = block_incl_scan(len, s_w, total);
-    s_ex[tid] = incl - len;
-    s_a[tid] = a;
+    if (tid == 0) {
+      a[0] += coff;
+      len[0] -= coff;
+    }
+    uint32_t total = 0, mine = 0;
+#pragma unroll
+    for (int h = 0; h < kEvRuns; ++h) mine += len[h];
+    uint32_t ex = block_incl_scan(mine, s_w, total) - mine;
+#pragma unroll
+    for (int h = 0; h < kEvRuns; ++h) {
+      s_ex[kEvRuns * tid + h] = ex;
+      s_a[kEvRuns * tid + h] = a[h];
+      ex += len[h];
+    }
     const uint32_t K = min(total, uint32_t(kEvStage));
     __syncthreads();
-    // stage entries [0, K): entry k belongs to the last run starting at or before k
-    for (uint32_t k = tid; k < K; k += kEventThreads) {
-      int lo = 0, hi = kEventThreads - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_ex[mid] <= k) lo = mid;
-        else hi = mid - 1;
+    // stage entries [0, K): entry k belongs to the last run starting at or
+    // before k; all of a thread's loads are issued before any is used
+    uint32_t ev[kEvJ];
+#pragma unroll
+    for (int j = 0; j < kEvJ; ++j) {
+      const uint32_t k = tid + uint32_t(j) * kEventThreads;
+      ev[j] = 0u;
+      if (k < K) {
+        const int o = last_at_most(s_ex, kRuns, k);
+        ev[j] = ent[s_a[o] + (k - s_ex[o])];
       }
-      const uint32_t e = ent[s_a[lo] + (k - s_ex[lo])];
-      s_stage[k] = e;
-      atomicAdd(&s_cnt[e >> kPosBits], 1u);
+    }
+#pragma unroll
+    for (int j = 0; j < kEvJ; ++j) {
+      const uint32_t k = tid + uint32_t(j) * kEventThreads;
+      if (k < K) {
+        s_stage[k] = ev[j];
+        atomicAdd(&s_cnt[ev[j] >> kPosBits], 1u);
+      }
     }
     if (tid == 0) {
       if (total <= uint32_t(kEvStage)) {
-        s_cur = cur + min(int64_t(kEventThreads), r1 - cur);
+        s_cur = cur + min(int64_t(kRuns), r1 - cur);
         s_coff = 0u;
       } else {  // the run holding entry K - 1 continues in the next round
-        int lo = 0, hi = kEventThreads - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_ex[mid] <= K - 1) lo = mid;
-          else hi = mid - 1;
-        }
-        const uint32_t run_len = (lo + 1 < kEventThreads ? s_ex[lo + 1] : total) - s_ex[lo];
-        const uint32_t done = K - s_ex[lo];
+        const int o = last_at_most(s_ex, kRuns, K - 1);
+        const uint32_t run_len = (o + 1 < kRuns ? s_ex[o + 1] : total) - s_ex[o];
+        const uint32_t done = K - s_ex[o];
         if (done == run_len) {
-          s_cur = cur + lo + 1;
+          s_cur = cur + o + 1;
           s_coff = 0u;
         } else {
-          s_cur = cur + lo;
-          s_coff = (lo == 0 ? coff : 0u) + done;
+          s_cur = cur + o;
+          s_coff = (o == 0 ? coff : 0u) + done;
         }
       }
     }
