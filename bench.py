@@ -82,6 +82,68 @@ def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) ->
     return 5.0 * nnz + w_bytes * events + n * (2 * 21 + 2) + n * (max_delay + 1) / 8.0
 
 
+def events_bytes(events: float, spikes: float, max_delay: int) -> float:
+    """Algorithmic bytes of the spike-driven bucketing: per delivered event
+    its table entry read and its bucket entry written (4 B each); per spike
+    and delay the two offsets of its run in the table, and its id."""
+    return 8.0 * events + spikes * max_delay * 12.0
+
+
+def step_bytes_events(n: int, max_delay: int, events: float, spikes: float, w_bytes: int) -> float:
+    """Algorithmic bytes of one whole step as spike-driven delivery needs
+    them: per delivered event its table entry and weight, per spike and
+    delay its run offsets and id, the neuron state read and written with its
+    parameter index, and the row pointers of the fixed-order row sums."""
+    return (4.0 + w_bytes) * events + spikes * max_delay * 12.0 + n * (2 * 21 + 2) + 8.0 * n
+
+
+def roofline(per, ms_step, n_syn, n_neu, n_del, ev_step, spk_step, wb):
+    """The roofline object of the dominant kernel (the consumer of the
+    gather stage: k_gather), with the step as a whole beside it.
+
+    Sweep mode: the delivery tests stream every synapse's index and delay
+    (5 B) and the D+1 spike bitmaps; with the row sums fused in the same
+    workgroups (fuse 1) their bytes are added, with separate sums (fuse 2)
+    k_sums gets its own line.  Spike-driven mode: k_events buckets each
+    delivered event (its own line); k_gather reads the buckets (4 B per
+    event) and, fused, does the row sums; the step is priced both by its own
+    method's bytes and by the pull method's (the time the pull method would
+    need at peak bandwidth)."""
+    spike_driven = per.get("events", 0.0) > 0.0
+    fused = per.get("sums", 0.0) == 0.0
+    Br = rows_bytes(n_neu, ev_step, wb)
+    if spike_driven:
+        Bg = 4.0 * ev_step
+        Bt = step_bytes_events(n_neu, n_del, ev_step, spk_step, wb)
+    else:
+        Bg = gather_bytes(n_syn, n_neu, n_del)
+        Bt = step_bytes(n_syn, n_neu, n_del, ev_step, wb)
+    B = Bg + Br if fused else Bg + n_syn / 8.0
+    achieved = B / (per["gather"] * 1e-3) / 1e9
+    step_gbs = Bt / (ms_step * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_gather",
+            "delivery": "spike-driven" if spike_driven else "sweep", "row_sums_in_gather": fused,
+            "algorithmic_bytes_per_launch": B, "avg_launch_ms": per["gather"],
+            "step": {"algorithmic_bytes": Bt, "ms": ms_step, "achieved": round(step_gbs, 1),
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4)}}
+    if spike_driven:
+        Be = events_bytes(ev_step, spk_step, n_del)
+        roof["bucketing"] = {"kernel": "k_events", "algorithmic_bytes_per_launch": Be, "avg_launch_ms": per["events"],
+                             "achieved": round(Be / (per["events"] * 1e-3) / 1e9, 1)}
+        Bp = step_bytes(n_syn, n_neu, n_del, ev_step, wb)
+        roof["step"]["pull_method_bytes"] = Bp
+        roof["step"]["pull_method_ms_at_peak"] = round(Bp / (HBM_PEAK_GBS * 1e9) * 1e3, 4)
+    if fused:
+        roof["parts"] = {("bucket_reads" if spike_driven else "delivery_tests"): Bg, "row_sums": Br}
+    else:
+        Bs = Br + n_syn / 8.0  # the sums read one hit bit per synapse
+        roof["hit_bits_written_per_launch"] = n_syn / 8.0
+        roof["sums"] = {"kernel": "k_sums", "algorithmic_bytes_per_launch": Bs, "avg_launch_ms": per["sums"],
+                        "achieved": round(Bs / (per["sums"] * 1e-3) / 1e9, 1)}
+    return roof
+
+
 def _shape_dict(shape):
     """The gather's launch shape as reported (None = library default)."""
     return {k: (v or None) for k, v in zip(("bundle_syn", "unroll", "fuse", "events"), shape)}
@@ -142,7 +204,7 @@ def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0,
     mean_rate = spikes / (net.n * steps * net.dt_ms * 1e-3)
     return {"rate_target_hz": rate, "bg_lambda": lam, "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
             "ms_per_step_reps": _spread([1e3 * w / steps for w in walls]),
-            "events": ev, "events_per_s": ev / wall, "rtf": wall / (steps * net.dt_ms * 1e-3),
+            "events": ev, "spikes": spikes, "events_per_s": ev / wall, "rtf": wall / (steps * net.dt_ms * 1e-3),
             "mean_rate_hz": mean_rate, "on_target": abs(mean_rate - rate) <= RATE_TOLERANCE * rate,
             "region_rate_spread": [float(np.min(rates)), float(np.max(rates))],
             "bg_events_per_s": evb / wall,
@@ -441,30 +503,7 @@ def main():
     wb = 2 if args.wtype == "bf16" else 4
     per = {k: v["ms"] / max(1, v["launches"]) for k, v in head["kernels"].items()}
     ev_step = head["events"] / args.steps
-    # the dominant kernel: the gather - its delivery tests, plus the row sums
-    # when they run in its workgroups (fuse 1); with separate sums (fuse 2)
-    # k_sums gets its own line (it reads the hit bits the gather wrote)
-    fused = per.get("sums", 0.0) == 0.0
-    Bg = gather_bytes(n_syn, n_neu, n_del)
-    Br = rows_bytes(n_neu, ev_step, wb)
-    B = Bg + Br if fused else Bg
-    achieved = B / (per["gather"] * 1e-3) / 1e9
-    Bt = step_bytes(n_syn, n_neu, n_del, ev_step, wb)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_gather",
-            "row_sums_in_gather": fused,
-            "algorithmic_bytes_per_launch": B,
-            "avg_launch_ms": per["gather"],
-            "step": {"algorithmic_bytes": Bt, "ms": head["ms_per_step"],
-                     "achieved": round(Bt / (head["ms_per_step"] * 1e-3) / 1e9, 1),
-                     "frac": round(Bt / (head["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
-    if fused:
-        roof["parts"] = {"delivery_tests": Bg, "row_sums": Br}
-    else:
-        Bs = Br + n_syn / 8.0  # the sums also read one hit bit per synapse
-        roof["hit_bits_written_per_launch"] = n_syn / 8.0
-        roof["sums"] = {"kernel": "k_sums", "algorithmic_bytes_per_launch": Bs, "avg_launch_ms": per["sums"],
-                        "achieved": round(Bs / (per["sums"] * 1e-3) / 1e9, 1)}
+    roof = roofline(per, head["ms_per_step"], n_syn, n_neu, n_del, ev_step, head["spikes"] / args.steps, wb)
     forms = {}
     if not args.no_forms and args.wtype == "f32":
         bf = {}
