@@ -117,11 +117,16 @@ typedef struct dtb_desc {
                                 sweep of each bundle's (delay, source)-sorted synapses over the
                                 delayed spike bitmaps; 2 = spike-driven: the step's spikes of
                                 the last D steps (their id lists) each deliver through their
-                                out-synapses of the matching delay, bucketed per bundle, which
-                                then sets the same hit bits (needs at most 4096 bundles;
-                                DTB_ERR_UNSUPPORTED otherwise); 0 = library default, 1.  A
-                                tuning knob: both find the same hits, so the results are
-                                identical */
+                                out-synapses of the matching delay, bucketed per bundle with
+                                the synapse's weight, which then sets the same hit bits; with
+                                the row sums fused, a bundle whose bucket fits the LDS beside
+                                its hit bitmap sums the carried weights (ordered by position),
+                                a larger one loads them from the CSR (needs at most 4096
+                                bundles, DTB_ERR_UNSUPPORTED otherwise; costs 16 B of device
+                                memory per synapse: the event table and the buckets); 0 =
+                                library default, 1.  A tuning knob: both find the same hits
+                                and add the same weights in the same order, so the results
+                                are identical */
 } dtb_desc;
 
 /* ------------------------------------------------------------ library */
@@ -312,7 +317,9 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps);
  * `steps` steps with hipEvents for each lookup-tiles-per-round value 1..3
  * (gather_unroll) and each placement of the row sums 1..2 (gather_fuse) of
  * the sweep, and for each placement with spike-driven delivery
- * (gather_events = 2, when the bundles fit it), and reports the fastest.  Every timing starts from the
+ * (gather_events = 2, when the bundles fit it; with the library's list also
+ * at up to three sizes of at most 2^19 - 1 synapses, whose buckets' weights
+ * fit the LDS), and reports the fastest.  Every timing starts from the
  * same state - the first candidate's state after `burnin` steps, saved once
  * and loaded before each timing - so all candidates time the same steps
  * (the shapes change only the schedule, never a result).  The members'
@@ -332,7 +339,8 @@ typedef struct dtb_tune_result {
   int32_t bundle_syn, unroll, fuse, events; /* the fastest shape (unroll 0 with events 2) */
   float ms_per_step;            /* its time per step (from the cache when from_cache) */
   int32_t from_cache;           /* 1: taken from cache_path without timing */
-  int32_t n_tried;              /* shapes timed: per candidate 3 x 2 sweeps + 2 spike-driven */
+  int32_t n_tried;              /* shapes timed: per candidate 3 x 2 sweeps + 2 spike-driven,
+                                   per extra spike-driven size 2 */
   int32_t tried_bundle[8 * DTB_TUNE_MAX_BUNDLES];
   int32_t tried_unroll[8 * DTB_TUNE_MAX_BUNDLES];
   int32_t tried_fuse[8 * DTB_TUNE_MAX_BUNDLES];

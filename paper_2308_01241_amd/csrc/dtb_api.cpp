@@ -268,14 +268,26 @@ struct BlockInput {
   int64_t n_src;    // sources (the event table's rows)
 };
 
-// The spike-driven delivery table of a block: every synapse as (bundle <<
-// kPosBits | position in its bundle), grouped by source and, inside a
-// source, by delay, otherwise in CSR order (a stable counting sort on host
-// threads): the deliveries of source m through delay d are entries
-// [soff[m (D+1) + d - 1], soff[m (D+1) + d]).  Plus the per-bundle buckets
-// the step's deliveries are sorted into.
+// Synapse k's stored weight as the row sums take it: |w| with the sign bit
+// marking an inhibitory source, as FP32 bits, or as BF16 bits (w rounded
+// to nearest even) in the high half.
+uint32_t weight_bits(const BlockInput* s, int64_t k, bool bf16) {
+  const bool inh = s->src_inh[s->col[k]] != 0;
+  if (bf16) return uint32_t((f32_to_bf16_rne(s->w[k]) & 0x7FFFu) | (inh ? 0x8000u : 0u)) << 16;
+  uint32_t u;
+  std::memcpy(&u, &s->w[k], 4);
+  return (u & 0x7FFFFFFFu) | (inh ? 0x80000000u : 0u);
+}
+
+// The spike-driven delivery table of a block: every synapse as the pair
+// (bundle << kPosBits | position in its bundle, its weight bits), grouped by
+// source and, inside a source, by delay, otherwise in CSR order (a stable
+// counting sort on host threads): the deliveries of source m through delay
+// d are entries [soff[m (D+1) + d - 1], soff[m (D+1) + d]).  Plus the
+// per-bundle buckets the step's deliveries are sorted into.
 dtb_status build_events(dtb_net* net, ConnBlock& cb, const BlockInput* s, const std::vector<Bundle>& bl) {
   const int D = net->d.max_delay;
+  const bool bf16 = net->d.wtype == DTB_W_BF16;
   const int64_t nb = int64_t(bl.size()), nnz = s->nnz, ns = s->n_src;
   if (nb > kEventMaxBundles)
     return fail(DTB_ERR_UNSUPPORTED, "spike-driven delivery takes at most " + std::to_string(kEventMaxBundles) +
@@ -323,13 +335,15 @@ dtb_status build_events(dtb_net* net, ConnBlock& cb, const BlockInput* s, const 
       }
     }
   });
-  std::vector<uint32_t> ent(size_t(std::max<int64_t>(1, nnz)));
+  // entry (low word) and weight bits (high word) of each pair
+  std::vector<uint64_t> ent(size_t(std::max<int64_t>(1, nnz)));
   std::vector<uint8_t> dl(size_t(std::max<int64_t>(1, nnz)));
   on_threads([&](unsigned q) {
     for (int64_t b = cut[q]; b < cut[q + 1]; ++b)
       for (int64_t k = bl[b].syn0; k < bl[b].syn0 + bl[b].nsyn; ++k) {
         const uint32_t o = hist[q][s->col[k]]++;
-        ent[o] = (uint32_t(b) << kPosBits) | uint32_t(k - bl[b].syn0);
+        ent[o] = uint64_t((uint32_t(b) << kPosBits) | uint32_t(k - bl[b].syn0)) |
+                 (uint64_t(weight_bits(s, k, bf16)) << 32);
         dl[o] = s->delay[k];
       }
   });
@@ -337,7 +351,7 @@ dtb_status build_events(dtb_net* net, ConnBlock& cb, const BlockInput* s, const 
   // inside each source's run: stable by delay, and the (source, delay) runs
   std::vector<uint32_t> soff(size_t(ns) * (D + 1));
   parallel_for(ns, [&](int64_t a, int64_t b) {
-    std::vector<uint32_t> tmp;
+    std::vector<uint64_t> tmp;
     uint32_t c[kMaxDelay + 2];
     for (int64_t m = a; m < b; ++m) {
       const uint32_t r0 = start[m], r1 = start[m + 1];
@@ -354,11 +368,11 @@ dtb_status build_events(dtb_net* net, ConnBlock& cb, const BlockInput* s, const 
   });
   std::vector<uint8_t>().swap(dl);
   dtb_status st;
-  if ((st = dalloc(net, &cb.ev_ent, std::max<int64_t>(1, nnz))) ||
+  if ((st = dalloc(net, &cb.ev_ent, 2 * std::max<int64_t>(1, nnz))) ||
       (st = dalloc(net, &cb.ev_soff, std::max<int64_t>(1, ns * (D + 1)))) ||
-      (st = dalloc(net, &cb.evbuf, std::max<int64_t>(1, nnz))) || (st = dalloc(net, &cb.ev_cursor, nb)))
+      (st = dalloc(net, &cb.evbuf, 2 * std::max<int64_t>(1, nnz))) || (st = dalloc(net, &cb.ev_cursor, nb)))
     return st;
-  if ((st = upload(net, cb.ev_ent, ent.data(), size_t(nnz) * 4)) ||
+  if ((st = upload(net, cb.ev_ent, ent.data(), size_t(nnz) * 8)) ||
       (st = upload(net, cb.ev_soff, soff.data(), soff.size() * 4)))
     return st;
   hipError_t e = hipMemsetAsync(cb.ev_cursor, 0, size_t(nb) * 4, net->stream);
@@ -533,17 +547,12 @@ dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {
     hwt.assign(size_t(k1 - k0) * wsz, 0);
     parallel_for(k1 - k0, [&](int64_t a, int64_t b) {
       for (int64_t q = a; q < b; ++q) {
-        const int64_t k = k0 + q;
-        const bool inh = s->src_inh[s->col[k]] != 0;
+        const uint32_t u = weight_bits(s, k0 + q, wsz == 2);
         if (wsz == 4) {
-          uint32_t u;
-          std::memcpy(&u, &s->w[k], 4);
-          u = (u & 0x7FFFFFFFu) | (inh ? 0x80000000u : 0u);
           std::memcpy(&hwt[q * 4], &u, 4);
         } else {
-          uint16_t u = uint16_t(f32_to_bf16_rne(s->w[k]) & 0x7FFFu);
-          u = uint16_t(u | (inh ? 0x8000u : 0u));
-          std::memcpy(&hwt[q * 2], &u, 2);
+          const uint16_t h = uint16_t(u >> 16);
+          std::memcpy(&hwt[q * 2], &h, 2);
         }
       }
     });
@@ -1647,6 +1656,21 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
         cands.push_back(int32_t(b));
     }
   }
+  // the spike-driven delivery also tries sizes whose bundles leave room in
+  // the LDS for their carried weights (hit bitmaps of at most 2^19 bits)
+  std::vector<int32_t> ev_cands = cands;
+  if (n_cands == 0) {
+    constexpr int64_t kCarrySyn = (int64_t(1) << 19) - 1;
+    const double L = n > 0 ? double(nnz) / double(n) : 1.0;
+    const int64_t ncu = std::max(1, prop.multiProcessorCount);
+    const int64_t k0 = std::max<int64_t>(1, (nnz + kCarrySyn * ncu - 1) / (kCarrySyn * ncu));
+    for (int64_t k = k0; k < k0 + 3; ++k) {
+      const int64_t rows = (n + k * ncu - 1) / (k * ncu);
+      const int64_t b = int64_t(double(rows) * L + 0.5);
+      if (b >= 4096 && b <= kCarrySyn && std::find(ev_cands.begin(), ev_cands.end(), int32_t(b)) == ev_cands.end())
+        ev_cands.push_back(int32_t(b));
+    }
+  }
   std::vector<dtb_desc> ds(members, members + n_members);
   std::vector<uint8_t> saved;
   hipEvent_t ea = nullptr, eb = nullptr;
@@ -1660,10 +1684,10 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
   // per candidate bundle size: the sweep with 1..3 tiles per round and either
   // placement of the row sums, then the spike-driven delivery with either
   // placement (when the bundles fit its 4096 ids)
-  for (size_t c = 0; c < cands.size() && st == DTB_OK; ++c) {
-    for (int32_t mode = 1; mode <= 2 && st == DTB_OK; ++mode) {
+  for (size_t c = 0; c < ev_cands.size() && st == DTB_OK; ++c) {
+    for (int32_t mode = c < cands.size() ? 1 : 2; mode <= 2 && st == DTB_OK; ++mode) {
       for (auto& x : ds) {
-        x.gather_bundle_syn = cands[c];
+        x.gather_bundle_syn = ev_cands[c];
         x.gather_unroll = 0;
         x.gather_fuse = 0;
         x.gather_events = mode;
@@ -1702,13 +1726,13 @@ dtb_status dtb_autotune(const dtb_desc* members, int32_t n_members, void* hip_st
           break;
         }
         const int q = out->n_tried++;
-        out->tried_bundle[q] = cands[c];
+        out->tried_bundle[q] = ev_cands[c];
         out->tried_unroll[q] = u;
         out->tried_fuse[q] = fz;
         out->tried_events[q] = mode;
         out->tried_ms[q] = ms / float(steps);
         if (q == 0 || out->tried_ms[q] < out->ms_per_step) {
-          out->bundle_syn = cands[c];
+          out->bundle_syn = ev_cands[c];
           out->unroll = u;
           out->fuse = fz;
           out->events = mode;

@@ -118,19 +118,31 @@ struct ConnBlock {
   int64_t* row_ptr = nullptr;       // [n + 1]
   void* wts = nullptr;              // [nnz] float or bf16, sign bit = inhibitory source
   // spike-driven delivery (gather_events = 2; local block only): the
-  // synapses grouped by source and, within a source, by delay, each as
-  // (bundle << kPosBits | position in the bundle); a step's deliveries are
-  // bucketed per bundle into evbuf (bundle b's bucket at its syn0, room for
-  // all its synapses), ev_cursor[b] entries long
-  uint32_t* ev_ent = nullptr;       // [nnz]
+  // synapses grouped by source and, within a source, by delay, each as the
+  // pair (bundle << kPosBits | position in the bundle, weight bits as the
+  // row sums take them: FP32 bits or BF16 bits << 16, sign = inhibitory);
+  // a step's deliveries are bucketed per bundle into evbuf as pairs
+  // (position, weight bits) (bundle b's bucket at its syn0, room for all
+  // its synapses), ev_cursor[b] pairs long
+  uint32_t* ev_ent = nullptr;       // [nnz][2]
   uint32_t* ev_soff = nullptr;      // [n_src][D + 1]: (m, d) = [soff[m (D+1) + d - 1], soff[m (D+1) + d])
-  uint32_t* evbuf = nullptr;        // [nnz]
+  uint32_t* evbuf = nullptr;        // [nnz][2]
   int32_t* ev_cursor = nullptr;     // [n_bundles]
 };
 
 constexpr int kEventMaxBundles = 1 << (32 - kPosBits);  // bundle ids fit the 12 high bits of an entry
 constexpr int kEventThreads = 1024;  // threads of the bucketing kernel
 constexpr int kEventGrid = 256;      // its workgroups (one per CU: its LDS staging takes most of a CU's)
+// LDS of the spike-driven row sums: a bundle's hit bitmap, the hit counts
+// before every group of kEvGroupWords bitmap words, and the delivered
+// weights in position order (as many as fit the rest)
+constexpr int kEvLdsBytes = 160 * 1024 - 1024;
+constexpr int kEvGroupWords = 4;
+__host__ __device__ constexpr int ev_groups(int hit_words) { return (hit_words + kEvGroupWords - 1) / kEvGroupWords; }
+__host__ __device__ constexpr int ev_weight_cap(int hit_words) {
+  return kEvLdsBytes / 4 - hit_words - ev_groups(hit_words) > 0 ? kEvLdsBytes / 4 - hit_words - ev_groups(hit_words)
+                                                                  : 0;
+}
 
 // Derived per-type constants in the order the neuron update reads them.
 struct PType {

@@ -338,7 +338,8 @@ __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
 // The deliveries of step t through every delay d = 1..D: each spike m of
 // step t - d + 1 (that step's id list) delivers through its synapses of
 // delay d, entries [soff[m (D+1) + d - 1], soff[m (D+1) + d]) of the event
-// table, each naming (bundle, position in the bundle).  The (delay, spike)
+// table, each naming (bundle, position in the bundle) and carrying the
+// synapse's weight.  The (delay, spike)
 // pairs are cut into equal shares, one per workgroup.  A workgroup works in
 // rounds: each thread takes the next kEvRuns pairs, a block prefix sum of
 // their run lengths places the runs' entries one after another, and up to
@@ -346,14 +347,20 @@ __device__ inline uint32_t wave_incl_scan_dpp(uint32_t x) {
 // the loads of a run are adjacent, and all of a thread's loads issued
 // before any is used); they are counted per bundle, sorted by bundle in
 // LDS, each bundle's share reserved in its bucket with one global atomic,
-// and written out bundle by bundle, so a bucket receives contiguous pieces.
-// A run that does not fit continues in the next round.  The order inside a
-// bucket is free: a bucket only sets bits, and every synapse delivers at
-// most once per step, so a bundle's bucket (room for all its synapses)
-// never overflows.
-constexpr int kEvStage = 10240;  // entries staged per round
+// and written out bundle by bundle as (position, weight) pairs, so a bucket
+// receives contiguous pieces.  A run that does not fit continues in the
+// next round.  The order inside a bucket is free: its consumer orders the
+// deliveries by position itself, and every synapse delivers at most once
+// per step, so a bundle's bucket (room for all its synapses) never
+// overflows.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));  // an event-table or bucket pair
+
+constexpr int kEvStage = 5120;   // entries staged per round
 constexpr int kEvRuns = 2;       // (delay, spike) pairs a thread takes per round
 constexpr int kEvJ = kEvStage / kEventThreads;  // staged entries per thread per round, at most
+static_assert(kEvStage % kEventThreads == 0, "every staged entry has its thread");
+static_assert(2 * kEvStage * 8 + 3 * kEventMaxBundles * 4 + 2 * kEventThreads * kEvRuns * 4 + 1024 <= 160 * 1024,
+              "the bucketing kernel's LDS fits a CU");
 
 __device__ inline uint32_t block_incl_scan(uint32_t x, uint32_t* s_w, uint32_t& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -387,13 +394,13 @@ __device__ inline int last_at_most(const T* a, int n, T k) {
 __global__ __launch_bounds__(kEventThreads) void k_events(
     const int64_t* __restrict__ step, const int32_t* __restrict__ ids, const int32_t* __restrict__ id_count,
     int32_t id_slots, int64_t id_stride, int32_t D, const uint32_t* __restrict__ soff,
-    const uint32_t* __restrict__ ent, const Bundle* __restrict__ bundles, int32_t n_bundles,
-    int32_t* __restrict__ cursor, uint32_t* __restrict__ evbuf) {
+    const u32x2* __restrict__ ent, const Bundle* __restrict__ bundles, int32_t n_bundles,
+    int32_t* __restrict__ cursor, u32x2* __restrict__ evbuf) {
   constexpr int kRuns = kEventThreads * kEvRuns;  // pairs per round
-  extern __shared__ uint32_t s_dyn[];
-  uint32_t* s_stage = s_dyn;                    // [kEvStage] the round's entries, in run order
-  uint32_t* s_sorted = s_stage + kEvStage;      // [kEvStage] the same, by bundle
-  uint32_t* s_cnt = s_sorted + kEvStage;        // [n_bundles] entries per bundle this round
+  extern __shared__ u32x2 s_dyn2[];
+  u32x2* s_stage = s_dyn2;                      // [kEvStage] the round's entries, in run order
+  u32x2* s_sorted = s_stage + kEvStage;         // [kEvStage] the same, by bundle
+  uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_sorted + kEvStage);  // [n_bundles] entries per bundle this round
   uint32_t* s_off = s_cnt + n_bundles;          // [n_bundles] their places in s_sorted
   uint32_t* s_gb = s_off + n_bundles;           // [n_bundles] their first place in the bucket
   __shared__ int64_t s_pre[kMaxDelay + 1];      // first pair of each delay
@@ -461,11 +468,11 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
     __syncthreads();
     // stage entries [0, K): entry k belongs to the last run starting at or
     // before k; all of a thread's loads are issued before any is used
-    uint32_t ev[kEvJ];
+    u32x2 ev[kEvJ];
 #pragma unroll
     for (int j = 0; j < kEvJ; ++j) {
       const uint32_t k = tid + uint32_t(j) * kEventThreads;
-      ev[j] = 0u;
+      ev[j] = u32x2{0u, 0u};
       if (k < K) {
         const int o = last_at_most(s_ex, kRuns, k);
         ev[j] = ent[s_a[o] + (k - s_ex[o])];
@@ -476,7 +483,7 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
       const uint32_t k = tid + uint32_t(j) * kEventThreads;
       if (k < K) {
         s_stage[k] = ev[j];
-        atomicAdd(&s_cnt[ev[j] >> kPosBits], 1u);
+        atomicAdd(&s_cnt[ev[j].x >> kPosBits], 1u);
       }
     }
     if (tid == 0) {
@@ -513,15 +520,15 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
     }
     __syncthreads();
     for (uint32_t k = tid; k < K; k += kEventThreads) {
-      const uint32_t e = s_stage[k];
-      s_sorted[atomicAdd(&s_off[e >> kPosBits], 1u)] = e;
+      const u32x2 e = s_stage[k];
+      s_sorted[atomicAdd(&s_off[e.x >> kPosBits], 1u)] = e;
     }
     __syncthreads();
     // written bundle by bundle: consecutive places of a bundle are adjacent in its bucket
     for (uint32_t k = tid; k < K; k += kEventThreads) {
-      const uint32_t e = s_sorted[k];
-      const uint32_t b = e >> kPosBits;
-      evbuf[s_gb[b] + (k - (s_off[b] - s_cnt[b]))] = e & kPosMask;
+      const u32x2 e = s_sorted[k];
+      const uint32_t b = e.x >> kPosBits;
+      evbuf[s_gb[b] + (k - (s_off[b] - s_cnt[b]))] = u32x2{e.x & kPosMask, e.y};
     }
     __syncthreads();
     for (int b = b0; b < b1; ++b) s_cnt[b] = 0u;
@@ -799,11 +806,76 @@ __device__ inline void fused_rows(const uint32_t* s_hits, const Bundle& B, const
 // bucket of the step's spike-driven deliveries (k_events)
 constexpr int kFromSweep = 0, kFromEvents = 1;
 
-// a bundle's bucket of deliveries: bundle b's at evbuf + syn0, cursor[b] long
+// a bundle's bucket of deliveries: bundle b's (position, weight bits) pairs
+// at evbuf + syn0, cursor[b] long; with the row sums fused, the LDS after
+// the hit bitmap (hit_words words, the largest bundle's) holds the group
+// prefix counts and up to weight_cap delivered weights (0: no room)
 struct EventSrc {
-  const uint32_t* evbuf;
+  const u32x2* evbuf;
   int32_t* cursor;
+  int32_t hit_words, weight_cap;
 };
+
+// the number of set hit bits below position p of a bundle's bitmap: the
+// count before p's group of kEvGroupWords words, then the words of the
+// group before p's, then p's word below p
+__device__ inline uint32_t hit_rank(const uint32_t* s_hits, const uint32_t* s_pre, uint32_t p) {
+  const uint32_t w = p >> 5, g = w / kEvGroupWords;
+  uint32_t r = s_pre[g];
+  for (uint32_t q = g * kEvGroupWords; q < w; ++q) r += uint32_t(__popc(s_hits[q]));
+  return r + uint32_t(__popc(s_hits[w] & ((1u << (p & 31u)) - 1u)));
+}
+
+// Rows of a bundle summed from its bucket's carried weights (phase 1 has
+// set the bucket's hit bits): every delivery's weight is put at its rank
+// among the set bits, which orders the bundle's delivered weights by
+// position, so row r's are places [rank(p0), rank(p1)) with [p0, p1) its
+// CSR positions, added in its CSR order as the bitmap walk adds them (the
+// same sums, bit for bit) - without fetching a weight line per delivery.
+// Then each row's background and gates.  Every thread of the block calls
+// this (block scans inside).
+__device__ inline void carried_rows(uint32_t* s_hits, uint32_t* s_scan, const Bundle& B, const RowsCsr& rows,
+                                    const RowTail& A, const EventSrc& E, int cnt, int64_t t, int tid, uint32_t& ev,
+                                    uint32_t& evb) {
+  static_assert(kGatherThreads == kEventThreads, "block_incl_scan takes kEventThreads threads");
+  uint32_t* s_pre = s_hits + E.hit_words;
+  uint32_t* s_wt = s_pre + ev_groups(E.hit_words);
+  const int hw = (B.nsyn >> 5) + 1;
+  const int ng = ev_groups(hw);
+  // exclusive prefix of the groups' counts (thread tid sums a stripe of groups)
+  const int per = (ng + kGatherThreads - 1) / kGatherThreads;
+  const int g0 = min(ng, tid * per), g1 = min(ng, g0 + per);
+  uint32_t sum = 0;
+  for (int q = g0 * kEvGroupWords; q < min(hw, g1 * kEvGroupWords); ++q) sum += uint32_t(__popc(s_hits[q]));
+  uint32_t all = 0;
+  uint32_t run = block_incl_scan(sum, s_scan, all) - sum;
+  for (int g = g0; g < g1; ++g) {
+    s_pre[g] = run;
+    for (int q = g * kEvGroupWords; q < min(hw, (g + 1) * kEvGroupWords); ++q) run += uint32_t(__popc(s_hits[q]));
+  }
+  __syncthreads();
+  const u32x2* __restrict__ bk = E.evbuf + B.syn0;
+  for (int q = tid; q < cnt; q += kGatherThreads) {
+    const u32x2 e = stream_load(bk + q);
+    s_wt[hit_rank(s_hits, s_pre, e.x)] = e.y;
+  }
+  __syncthreads();
+  for (int64_t r = B.row0 + tid; r < B.row1; r += kGatherThreads) {
+    const int64_t k0 = rows.row_ptr[r], k1 = rows.row_ptr[r + 1];
+    const float jv[4] = {A.j[r], A.j[A.n_pad + r], A.j[2 * A.n_pad + r], A.j[3 * A.n_pad + r]};
+    const uint32_t a = hit_rank(s_hits, s_pre, uint32_t(k0 - B.syn0));
+    const uint32_t b = hit_rank(s_hits, s_pre, uint32_t(k1 - B.syn0));
+    float dE = 0.f, dI = 0.f;
+    for (uint32_t k = a; k < b; ++k) {
+      const uint32_t x = s_wt[k];
+      const float wv = __uint_as_float(x & 0x7FFFFFFFu);
+      if (x >> 31) dI += wv;
+      else dE += wv;
+    }
+    ev += b - a;
+    evb += row_finish(A, t, r, B.member_row0, B.member, B.seed, dE, dI, jv);
+  }
+}
 
 template <int kU, int kMode, int kSrc>
 __global__ __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(kU == 1 && kMode == kHitsOut ? 8 : 4)))
@@ -832,9 +904,9 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
     // (positions < nsyn, each at most once per step); the bucket is emptied
     // for the next step once every thread has read its count
     const int cnt = s_count;
-    const uint32_t* __restrict__ bk = E.evbuf + B.syn0;
+    const u32x2* __restrict__ bk = E.evbuf + B.syn0;
     for (int q = tid; q < cnt; q += kGatherThreads) {
-      const uint32_t p = stream_load(bk + q);
+      const uint32_t p = stream_load(bk + q).x;
       atomicOr(&s_hits[p >> 5], 1u << (p & 31u));
     }
     if (tid == 0) E.cursor[bi] = 0;
@@ -923,7 +995,12 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
     // in LDS (row r's CSR positions [row_ptr[r] - syn0, row_ptr[r+1] -
     // syn0)), then their background and gates.  The delivered events are
     // the hits the rows visit.
-    fused_rows<kMode == kSumBF16>(s_hits, B, rows, A, step[0], tid, ev, evb);
+    // With a bucket whose weights fit the LDS, its carried weights; else
+    // (a larger bucket, or no room) the weight of each hit from the CSR.
+    if (kSrc == kFromEvents && E.weight_cap > 0 && s_count <= E.weight_cap)
+      carried_rows(s_hits, s_red[0], B, rows, A, E, s_count, step[0], tid, ev, evb);
+    else
+      fused_rows<kMode == kSumBF16>(s_hits, B, rows, A, step[0], tid, ev, evb);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -1222,10 +1299,13 @@ template <int kU, int kMode, int kSrc>
 void launch_gather_as(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
                       hipStream_t s) {
   const unsigned grid = unsigned(cb.xcd_max * 8);
-  const size_t lds = size_t(cb.hit_words) * 4;
+  // the fused spike-driven sums take the carried weights when they fit
+  const int cap = kSrc == kFromEvents && kMode != kHitsOut ? ev_weight_cap(cb.hit_words) : 0;
+  const size_t lds = cap > 0 ? size_t(kEvLdsBytes) : size_t(cb.hit_words) * 4;
   hipLaunchKernelGGL((k_gather<kU, kMode, kSrc>), dim3(grid), dim3(kGatherThreads), lds, s, cb.xcd_first, d.step,
                      cb.bundles, cb.tiles, cb.theads, bitmaps, words_pad, d.slots, cb.hitbuf, d.ev,
-                     RowsCsr{cb.row_ptr, cb.wts}, row_tail(d), EventSrc{cb.evbuf, cb.ev_cursor});
+                     RowsCsr{cb.row_ptr, cb.wts}, row_tail(d),
+                     EventSrc{reinterpret_cast<const u32x2*>(cb.evbuf), cb.ev_cursor, cb.hit_words, cap});
 }
 
 template <int kMode>
@@ -1258,10 +1338,11 @@ hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t
 hipError_t launch_events(const DeviceNet& d, hipStream_t s) {
   const ConnBlock& cb = d.loc;
   if (cb.n_bundles == 0) return hipSuccess;
-  const size_t lds = (2 * size_t(kEvStage) + 3 * size_t(cb.n_bundles)) * 4;
+  const size_t lds = 2 * size_t(kEvStage) * 8 + 3 * size_t(cb.n_bundles) * 4;
   hipLaunchKernelGGL(k_events, dim3(kEventGrid), dim3(kEventThreads), lds, s, d.step, d.ids,
-                     d.id_count, d.id_slots, d.n_pad, d.max_delay, cb.ev_soff, cb.ev_ent, cb.bundles,
-                     int32_t(cb.n_bundles), cb.ev_cursor, cb.evbuf);
+                     d.id_count, d.id_slots, d.n_pad, d.max_delay, cb.ev_soff,
+                     reinterpret_cast<const u32x2*>(cb.ev_ent), cb.bundles, int32_t(cb.n_bundles), cb.ev_cursor,
+                     reinterpret_cast<u32x2*>(cb.evbuf));
   return hipGetLastError();
 }
 
@@ -1278,13 +1359,14 @@ hipError_t gather_set_lds_limit() {
   const int bytes = kHitWords * 4;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_events),
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (2 * kEvStage + 3 * kEventMaxBundles) * 4);
+                                     2 * kEvStage * 8 + 3 * kEventMaxBundles * 4);
   for (hipError_t x : {set_lds_limit_one<1, kHitsOut, kFromSweep>(bytes), set_lds_limit_one<2, kHitsOut, kFromSweep>(bytes),
                        set_lds_limit_one<3, kHitsOut, kFromSweep>(bytes), set_lds_limit_one<1, kSumF32, kFromSweep>(bytes),
                        set_lds_limit_one<2, kSumF32, kFromSweep>(bytes), set_lds_limit_one<3, kSumF32, kFromSweep>(bytes),
                        set_lds_limit_one<1, kSumBF16, kFromSweep>(bytes), set_lds_limit_one<2, kSumBF16, kFromSweep>(bytes),
                        set_lds_limit_one<3, kSumBF16, kFromSweep>(bytes), set_lds_limit_one<1, kHitsOut, kFromEvents>(bytes),
-                       set_lds_limit_one<1, kSumF32, kFromEvents>(bytes), set_lds_limit_one<1, kSumBF16, kFromEvents>(bytes)})
+                       set_lds_limit_one<1, kSumF32, kFromEvents>(std::max(bytes, kEvLdsBytes)),
+                       set_lds_limit_one<1, kSumBF16, kFromEvents>(std::max(bytes, kEvLdsBytes))})
     if (e == hipSuccess) e = x;
   return e;
 }

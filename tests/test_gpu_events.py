@@ -55,18 +55,24 @@ def _same(a, b):
 
 @pytest.mark.parametrize("lam", [0.27346, 1.52745])
 def test_spike_driven_equals_sweep_on_a_partition_net(dtb, lam):
-    """60,000 neurons, 90 populations, delays 1-20, hundreds of bundles: the
-    7 Hz and 30 Hz drives, both row-sum placements, FP32 and BF16, with and
-    without graph replay."""
+    """60,000 neurons, 90 populations, delays 1-20: the 7 Hz and 30 Hz
+    drives, both row-sum placements, FP32 and BF16, with and without graph
+    replay.  With the row sums fused, three bundle sizes: 20,000 synapses
+    (hundreds of bundles, every bucket's weights fit the LDS and are summed
+    from it), 880,000 (seven bundles with room for about 6,300 carried
+    weights each: at 7 Hz the buckets hold about that many, so a launch
+    mixes bundles summed from carried weights and bundles that fetch them
+    from the CSR) and 1,048,575 (no room: every weight from the CSR)."""
     net = netgen.make_network(netgen.partition_spec(n=60_000, bg_lambda=lam))
     T = 120
     print(f"partition n={net.n} lambda={lam}", flush=True)
     for wt in ("f32", "bf16"):
         ref, ids_ref = _run(dtb, net, T, wtype=wt, bundle_syn=20_000, events=1)
         assert ref[4]["spikes"] > 0 and ref[4]["ev_rec"] > 0
-        for fuse in (1, 2):
+        for bs, fuse in ((20_000, 1), (20_000, 2), (880_000, 1), (1_048_575, 1)):
             for graph in (False, True):
-                got, ids = _run(dtb, net, T, graph=graph, wtype=wt, bundle_syn=20_000, fuse=fuse, events=2)
+                print(f"  {wt} bundle_syn={bs} fuse={fuse} graph={graph}", flush=True)
+                got, ids = _run(dtb, net, T, graph=graph, wtype=wt, bundle_syn=bs, fuse=fuse, events=2)
                 _same(got, ref)
                 np.testing.assert_array_equal(ids, ids_ref)
 
