@@ -375,10 +375,10 @@ dtb_status build_events(dtb_net* net, ConnBlock& cb, const BlockInput* s, const 
   if ((st = upload(net, cb.ev_ent, ent.data(), size_t(nnz) * 8)) ||
       (st = upload(net, cb.ev_soff, soff.data(), soff.size() * 4)))
     return st;
-  hipError_t e = hipMemsetAsync(cb.ev_cursor, 0, size_t(nb) * 4, net->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
-  if (e != hipSuccess) return hip_fail(net, e, "event buckets");
-  return DTB_OK;
+  // every bucket starts empty: its cursor at the bundle's first synapse
+  std::vector<uint32_t> cur(static_cast<size_t>(nb));
+  for (int64_t b = 0; b < nb; ++b) cur[size_t(b)] = uint32_t(bl[size_t(b)].syn0);
+  return upload(net, cb.ev_cursor, cur.data(), cur.size() * 4);
 }
 
 dtb_status build_block(dtb_net* net, ConnBlock& cb, const BlockInput* s) {

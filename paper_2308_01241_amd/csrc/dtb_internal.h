@@ -123,11 +123,11 @@ struct ConnBlock {
   // row sums take them: FP32 bits or BF16 bits << 16, sign = inhibitory);
   // a step's deliveries are bucketed per bundle into evbuf as pairs
   // (position, weight bits) (bundle b's bucket at its syn0, room for all
-  // its synapses), ev_cursor[b] pairs long
+  // its synapses), filled up to ev_cursor[b] (syn0 while empty)
   uint32_t* ev_ent = nullptr;       // [nnz][2]
   uint32_t* ev_soff = nullptr;      // [n_src][D + 1]: (m, d) = [soff[m (D+1) + d - 1], soff[m (D+1) + d])
   uint32_t* evbuf = nullptr;        // [nnz][2]
-  int32_t* ev_cursor = nullptr;     // [n_bundles]
+  uint32_t* ev_cursor = nullptr;    // [n_bundles]
 };
 
 constexpr int kEventMaxBundles = 1 << (32 - kPosBits);  // bundle ids fit the 12 high bits of an entry

@@ -394,8 +394,8 @@ __device__ inline int last_at_most(const T* a, int n, T k) {
 __global__ __launch_bounds__(kEventThreads) void k_events(
     const int64_t* __restrict__ step, const int32_t* __restrict__ ids, const int32_t* __restrict__ id_count,
     int32_t id_slots, int64_t id_stride, int32_t D, const uint32_t* __restrict__ soff,
-    const u32x2* __restrict__ ent, const Bundle* __restrict__ bundles, int32_t n_bundles,
-    int32_t* __restrict__ cursor, u32x2* __restrict__ evbuf) {
+    const u32x2* __restrict__ ent, int32_t n_bundles, uint32_t* __restrict__ cursor,
+    u32x2* __restrict__ evbuf) {
   constexpr int kRuns = kEventThreads * kEvRuns;  // pairs per round
   extern __shared__ u32x2 s_dyn2[];
   u32x2* s_stage = s_dyn2;                      // [kEvStage] the round's entries, in run order
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
       const uint32_t c = s_cnt[b];
       s_off[b] = run;
       run += c;
-      if (c) s_gb[b] = uint32_t(bundles[b].syn0) + uint32_t(atomicAdd(&cursor[b], int32_t(c)));
+      if (c) s_gb[b] = atomicAdd(&cursor[b], c);
     }
     __syncthreads();
     for (uint32_t k = tid; k < K; k += kEventThreads) {
@@ -806,13 +806,17 @@ __device__ inline void fused_rows(const uint32_t* s_hits, const Bundle& B, const
 // bucket of the step's spike-driven deliveries (k_events)
 constexpr int kFromSweep = 0, kFromEvents = 1;
 
+// pairs of its bucket a thread of the fused spike-driven sums keeps in
+// registers between setting their hit bits and placing their weights
+constexpr int kEvKeep = 16;
+
 // a bundle's bucket of deliveries: bundle b's (position, weight bits) pairs
-// at evbuf + syn0, cursor[b] long; with the row sums fused, the LDS after
+// at evbuf + syn0, up to cursor[b]; with the row sums fused, the LDS after
 // the hit bitmap (hit_words words, the largest bundle's) holds the group
 // prefix counts and up to weight_cap delivered weights (0: no room)
 struct EventSrc {
   const u32x2* evbuf;
-  int32_t* cursor;
+  uint32_t* cursor;
   int32_t hit_words, weight_cap;
 };
 
@@ -834,9 +838,10 @@ __device__ inline uint32_t hit_rank(const uint32_t* s_hits, const uint32_t* s_pr
 // same sums, bit for bit) - without fetching a weight line per delivery.
 // Then each row's background and gates.  Every thread of the block calls
 // this (block scans inside).
-__device__ inline void carried_rows(uint32_t* s_hits, uint32_t* s_scan, const Bundle& B, const RowsCsr& rows,
-                                    const RowTail& A, const EventSrc& E, int cnt, int64_t t, int tid, uint32_t& ev,
-                                    uint32_t& evb) {
+template <int kKeep>
+__device__ inline void carried_rows(uint32_t* s_hits, uint32_t* s_scan, const u32x2 (&kept)[kKeep], const Bundle& B,
+                                    const RowsCsr& rows, const RowTail& A, const EventSrc& E, int cnt, int64_t t,
+                                    int tid, uint32_t& ev, uint32_t& evb) {
   static_assert(kGatherThreads == kEventThreads, "block_incl_scan takes kEventThreads threads");
   uint32_t* s_pre = s_hits + E.hit_words;
   uint32_t* s_wt = s_pre + ev_groups(E.hit_words);
@@ -854,8 +859,11 @@ __device__ inline void carried_rows(uint32_t* s_hits, uint32_t* s_scan, const Bu
     for (int q = g * kEvGroupWords; q < min(hw, (g + 1) * kEvGroupWords); ++q) run += uint32_t(__popc(s_hits[q]));
   }
   __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kKeep; ++j)
+    if (tid + j * kGatherThreads < cnt) s_wt[hit_rank(s_hits, s_pre, kept[j].x)] = kept[j].y;
   const u32x2* __restrict__ bk = E.evbuf + B.syn0;
-  for (int q = tid; q < cnt; q += kGatherThreads) {
+  for (int q = tid + kKeep * kGatherThreads; q < cnt; q += kGatherThreads) {
     const u32x2 e = stream_load(bk + q);
     s_wt[hit_rank(s_hits, s_pre, e.x)] = e.y;
   }
@@ -896,20 +904,36 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
   const Bundle B = bundles[bi];
   const int hw = (B.nsyn >> 5) + 1;  // includes the padding bit at position nsyn
   for (int q = tid; q < hw; q += kGatherThreads) s_hits[q] = 0u;
-  if (kSrc == kFromEvents && tid == 0) s_count = E.cursor[bi];
+  if (kSrc == kFromEvents && tid == 0) s_count = int32_t(E.cursor[bi] - uint32_t(B.syn0));
   __syncthreads();
 
+  u32x2 kept[kSrc == kFromEvents && kMode != kHitsOut ? kEvKeep : 1];
   if constexpr (kSrc == kFromEvents) {
     // ---- phase 1 from the bucket: each delivery sets its synapse's bit
     // (positions < nsyn, each at most once per step); the bucket is emptied
     // for the next step once every thread has read its count
     const int cnt = s_count;
     const u32x2* __restrict__ bk = E.evbuf + B.syn0;
-    for (int q = tid; q < cnt; q += kGatherThreads) {
+    int q0 = tid;
+    if constexpr (kMode != kHitsOut) {
+      // the thread's first kEvKeep pairs stay in registers for the carried weights
+#pragma unroll
+      for (int j = 0; j < kEvKeep; ++j) {
+        const int q = tid + j * kGatherThreads;
+        kept[j] = q < cnt ? stream_load(bk + q) : u32x2{0u, 0u};
+      }
+#pragma unroll
+      for (int j = 0; j < kEvKeep; ++j) {
+        const uint32_t p = kept[j].x;
+        if (tid + j * kGatherThreads < cnt) atomicOr(&s_hits[p >> 5], 1u << (p & 31u));
+      }
+      q0 = tid + kEvKeep * kGatherThreads;
+    }
+    for (int q = q0; q < cnt; q += kGatherThreads) {
       const uint32_t p = stream_load(bk + q).x;
       atomicOr(&s_hits[p >> 5], 1u << (p & 31u));
     }
-    if (tid == 0) E.cursor[bi] = 0;
+    if (tid == 0) E.cursor[bi] = uint32_t(B.syn0);
   } else {
   // ---- phase 1: delivery tests in (delay, source) order
   // Software pipeline over rounds of kU tiles per wavefront.  In the stage
@@ -998,7 +1022,7 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
     // With a bucket whose weights fit the LDS, its carried weights; else
     // (a larger bucket, or no room) the weight of each hit from the CSR.
     if (kSrc == kFromEvents && E.weight_cap > 0 && s_count <= E.weight_cap)
-      carried_rows(s_hits, s_red[0], B, rows, A, E, s_count, step[0], tid, ev, evb);
+      carried_rows(s_hits, s_red[0], kept, B, rows, A, E, s_count, step[0], tid, ev, evb);
     else
       fused_rows<kMode == kSumBF16>(s_hits, B, rows, A, step[0], tid, ev, evb);
   }
@@ -1341,7 +1365,7 @@ hipError_t launch_events(const DeviceNet& d, hipStream_t s) {
   const size_t lds = 2 * size_t(kEvStage) * 8 + 3 * size_t(cb.n_bundles) * 4;
   hipLaunchKernelGGL(k_events, dim3(kEventGrid), dim3(kEventThreads), lds, s, d.step, d.ids,
                      d.id_count, d.id_slots, d.n_pad, d.max_delay, cb.ev_soff,
-                     reinterpret_cast<const u32x2*>(cb.ev_ent), cb.bundles, int32_t(cb.n_bundles), cb.ev_cursor,
+                     reinterpret_cast<const u32x2*>(cb.ev_ent), int32_t(cb.n_bundles), cb.ev_cursor,
                      reinterpret_cast<u32x2*>(cb.evbuf));
   return hipGetLastError();
 }
