@@ -38,6 +38,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _tuned_shape(members) -> dict:
+    """The gather launch shape cached for this batch's shape by the
+    autotuner, as Net keyword arguments (the library defaults if none)."""
+    from . import autotune
+    b, u, f, v = autotune.lookup(sum(m.n for m in members), sum(m.nnz for m in members), len(members), "f32",
+                                 max(m.max_delay for m in members))
+    return {"bundle_syn": b, "unroll": u, "fuse": f, "events": v}
+
+
 def _stream():
     import torch
     return torch.cuda.current_stream()
@@ -173,7 +182,7 @@ class Resim:
             cp.member = c
             copies.append(cp)
         self.k, self.S = k, S
-        self.net = Net.batch(copies, record_steps=2 * S.window, stream=_stream())
+        self.net = Net.batch(copies, record_steps=2 * S.window, stream=_stream(), **_tuned_shape(copies))
 
     def __call__(self, G, twin_gains=None):
         S, k = self.S, self.k
@@ -276,7 +285,7 @@ def main(argv=None):
     S = Setup(members=a.members, window=a.window, target_n=a.target_n, rate_hz=a.rate_hz)
     t0 = time.time()
     members = member_networks(S)
-    net = Net.batch(members, record_steps=2 * S.window, stream=_stream())
+    net = Net.batch(members, record_steps=2 * S.window, stream=_stream(), **_tuned_shape(members))
     del members
     log(f"[data] ensemble: {net.n} neurons, {net.n_members} members, built in {time.time() - t0:.1f}s")
     tic = time.perf_counter()

@@ -714,6 +714,15 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
     dtb_destroy(net);
     return st;
   }
+  if (d.events) {
+    // gathered run offsets for up to an eighth of the neurons spiking in a step
+    d.run_cap = std::max<int64_t>(64, (d.n_pad / 8 + 63) / 64 * 64);
+    if ((st = dalloc(net, &d.run_off, int64_t(d.id_slots) * (d.max_delay + 1) * d.run_cap)) ||
+        (st = dalloc(net, &d.run_n, d.id_slots))) {
+      dtb_destroy(net);
+      return st;
+    }
+  }
   auto zero = [&](void* p, size_t bytes) { return hipMemsetAsync(p, 0, bytes, net->stream); };
   hipError_t e = hipSuccess;
   for (auto pr : std::vector<std::pair<void*, size_t>>{
@@ -722,8 +731,9 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
            {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32}, {d.id_count, size_t(d.id_slots) * 4},
            {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4}, {d.ptype, d.n_pad * 2},
            {d.region, d.n_pad * 4}, {d.V, d.n_pad * 4}, {d.step, 16}, {d.bold, size_t(d.n_regions) * 16},
-           {d.bold_y, size_t(d.n_regions) * 4}, {d.rd_status, d.compact_blocks * 8}, {d.rd_count, 4}}) {
-    if (e == hipSuccess) e = zero(pr.first, pr.second);
+           {d.bold_y, size_t(d.n_regions) * 4}, {d.rd_status, d.compact_blocks * 8}, {d.rd_count, 4},
+           {d.run_n, d.run_n ? size_t(d.id_slots) * 4 : 0}}) {
+    if (e == hipSuccess && pr.second) e = zero(pr.first, pr.second);
   }
   if (e != hipSuccess) {
     st = fail(DTB_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
@@ -1054,8 +1064,9 @@ dtb_status dtb_reset(dtb_net* net) {
            {d.counts, slots * d.n_regions * 4}, {d.ev, slots * kStripes * 2 * 8}, {d.totals, 32},
            {d.id_count, size_t(d.id_slots) * 4}, {d.cstatus, d.compact_blocks * 8}, {d.cticket, 4}, {d.bad, 4},
            {d.step, 16},
-           {d.bold, size_t(d.n_regions) * 16}, {d.bold_y, size_t(d.n_regions) * 4}}) {
-    if (e == hipSuccess) e = hipMemsetAsync(pr.first, 0, pr.second, net->stream);
+           {d.bold, size_t(d.n_regions) * 16}, {d.bold_y, size_t(d.n_regions) * 4},
+           {d.run_n, d.run_n ? size_t(d.id_slots) * 4 : 0}}) {
+    if (e == hipSuccess && pr.second) e = hipMemsetAsync(pr.first, 0, pr.second, net->stream);
   }
   if (e == hipSuccess && d.ou_on) e = launch_fill(d.ou, d.n_pad, d.ou_mu, net->stream);
   if (e == hipSuccess && net->remote) e = launch_copy_words(d.rraster, nullptr, slots * d.rwords_pad, net->stream);
@@ -1514,6 +1525,9 @@ dtb_status dtb_load(dtb_net* net, const void* host_buf, size_t len) {
   if (e == hipSuccess) e = hipMemsetAsync(d.cticket, 0, 4, net->stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.bad, 0, 4, net->stream);
   if (e == hipSuccess) e = hipMemsetAsync(d.id_count, 0, size_t(d.id_slots) * 4, net->stream);
+  // the rebuilt lists have no gathered run offsets: their spikes' runs are
+  // read from the table directly
+  if (e == hipSuccess && d.run_n) e = hipMemsetAsync(d.run_n, 0, size_t(d.id_slots) * 4, net->stream);
   // the spike-id lists still needed (the last step's; with spike-driven
   // delivery the last D steps') are rebuilt from the restored bitmaps
   const int64_t keep = d.id_slots == 1 ? 1 : int64_t(d.max_delay);

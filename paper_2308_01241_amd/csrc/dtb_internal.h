@@ -139,9 +139,10 @@ constexpr int kEventGrid = 256;      // its workgroups (one per CU: its LDS stag
 constexpr int kEvLdsBytes = 160 * 1024 - 1024;
 constexpr int kEvGroupWords = 4;
 __host__ __device__ constexpr int ev_groups(int hit_words) { return (hit_words + kEvGroupWords - 1) / kEvGroupWords; }
+// (-1: not even the bitmap and the prefix counts fit)
 __host__ __device__ constexpr int ev_weight_cap(int hit_words) {
-  return kEvLdsBytes / 4 - hit_words - ev_groups(hit_words) > 0 ? kEvLdsBytes / 4 - hit_words - ev_groups(hit_words)
-                                                                  : 0;
+  return kEvLdsBytes / 4 - hit_words - ev_groups(hit_words) >= 0 ? kEvLdsBytes / 4 - hit_words - ev_groups(hit_words)
+                                                                   : -1;
 }
 
 // Derived per-type constants in the order the neuron update reads them.
@@ -195,6 +196,11 @@ struct DeviceNet {
   int64_t* totals = nullptr;        // [4]: spikes, ev_rec, ev_bg, steps
   int32_t* ids = nullptr;           // [id_slots][n_pad] ascending spike ids: step t's list in slot t mod id_slots
   int32_t* id_count = nullptr;      // [id_slots]
+  // spike-driven delivery: the event-table run offsets of each listed spike
+  // (its soff row), delay-major per slot, for the first run_n[slot] spikes
+  int64_t run_cap = 0;              // spikes per slot with gathered offsets
+  uint32_t* run_off = nullptr;      // [id_slots][D + 1][run_cap]
+  int32_t* run_n = nullptr;         // [id_slots]
   // spike list of an earlier recorded step, rebuilt on request from its
   // ring slot: [0] epoch - 1, [1] slot | ids | count | look-back status words,
   // ticket, spike-total sink

@@ -391,9 +391,34 @@ __device__ inline int last_at_most(const T* a, int n, T k) {
   return lo;
 }
 
+// The run offsets of the step's spikes, gathered once: spike k of step t's
+// id list gets soff[m (D+1) + d], d = 0..D, at run_off[slot][d][k] (for
+// k < cap), so the bucketing of the next D steps reads them as coalesced
+// rows instead of a scattered cache line per (spike, delay).
+constexpr int kRunThreads = 256;
+__global__ __launch_bounds__(kRunThreads) void k_spike_runs(const int64_t* __restrict__ step,
+                                                           const int32_t* __restrict__ ids,
+                                                           const int32_t* __restrict__ id_count, int32_t id_slots,
+                                                           int64_t id_stride, int32_t D,
+                                                           const uint32_t* __restrict__ soff,
+                                                           uint32_t* __restrict__ run_off,
+                                                           int32_t* __restrict__ run_n, int64_t cap) {
+  const int64_t sl = step[0] % id_slots;
+  const int64_t cnt = min(int64_t(id_count[sl]), cap);
+  const int32_t* __restrict__ li = ids + sl * id_stride;
+  uint32_t* __restrict__ out = run_off + sl * int64_t(D + 1) * cap;
+  for (int64_t k = int64_t(blockIdx.x) * kRunThreads + threadIdx.x; k < cnt;
+       k += int64_t(gridDim.x) * kRunThreads) {
+    const uint32_t* __restrict__ row = soff + int64_t(li[k]) * (D + 1);
+    for (int d = 0; d <= D; ++d) out[int64_t(d) * cap + k] = row[d];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) run_n[sl] = int32_t(cnt);
+}
+
 __global__ __launch_bounds__(kEventThreads) void k_events(
     const int64_t* __restrict__ step, const int32_t* __restrict__ ids, const int32_t* __restrict__ id_count,
     int32_t id_slots, int64_t id_stride, int32_t D, const uint32_t* __restrict__ soff,
+    const uint32_t* __restrict__ run_off, const int32_t* __restrict__ run_n, int64_t run_cap,
     const u32x2* __restrict__ ent, int32_t n_bundles, uint32_t* __restrict__ cursor,
     u32x2* __restrict__ evbuf) {
   constexpr int kRuns = kEventThreads * kEvRuns;  // pairs per round
@@ -405,6 +430,8 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
   uint32_t* s_gb = s_off + n_bundles;           // [n_bundles] their first place in the bucket
   __shared__ int64_t s_pre[kMaxDelay + 1];      // first pair of each delay
   __shared__ int64_t s_base[kMaxDelay];         // its id list
+  __shared__ int64_t s_roff[kMaxDelay];         // its gathered run offsets (delay d's row)
+  __shared__ int32_t s_rn[kMaxDelay];           // how many of its spikes have them
   __shared__ uint32_t s_ex[kRuns];              // staged entries before each pair's run
   __shared__ uint32_t s_a[kRuns];               // table index of each pair's next entry
   __shared__ uint32_t s_w[kEventThreads / 64];
@@ -419,6 +446,8 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
       const int64_t sl = e >= 0 ? e % id_slots : 0;
       s_pre[d - 1] = acc;
       s_base[d - 1] = sl * id_stride;
+      s_roff[d - 1] = (sl * (D + 1) + (d - 1)) * run_cap;
+      s_rn[d - 1] = e >= 0 ? run_n[sl] : 0;
       acc += e >= 0 ? int64_t(id_count[sl]) : 0;
     }
     s_pre[D] = acc;
@@ -445,9 +474,15 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
       a[h] = len[h] = 0u;
       if (i < r1) {
         const int d = last_at_most(s_pre, D, i);  // delay d + 1
-        const int64_t m = ids[s_base[d] + (i - s_pre[d])];
-        a[h] = soff[m * (D + 1) + d];
-        len[h] = soff[m * (D + 1) + d + 1] - a[h];
+        const int64_t k = i - s_pre[d];           // the spike's place in its list
+        if (k < s_rn[d]) {
+          a[h] = run_off[s_roff[d] + k];
+          len[h] = run_off[s_roff[d] + run_cap + k] - a[h];
+        } else {
+          const int64_t m = ids[s_base[d] + k];
+          a[h] = soff[m * (D + 1) + d];
+          len[h] = soff[m * (D + 1) + d + 1] - a[h];
+        }
       }
     }
     if (tid == 0) {
@@ -813,9 +848,10 @@ constexpr int kEvKeep = 16;
 // a bundle's bucket of deliveries: bundle b's (position, weight bits) pairs
 // at evbuf + syn0, up to cursor[b]; with the row sums fused, the LDS after
 // the hit bitmap (hit_words words, the largest bundle's) holds the group
-// prefix counts and up to weight_cap delivered weights (0: no room)
+// prefix counts and up to weight_cap delivered weights (-1: no room even
+// for the prefix counts)
 struct EventSrc {
-  const u32x2* evbuf;
+  u32x2* evbuf;
   uint32_t* cursor;
   int32_t hit_words, weight_cap;
 };
@@ -836,15 +872,20 @@ __device__ inline uint32_t hit_rank(const uint32_t* s_hits, const uint32_t* s_pr
 // position, so row r's are places [rank(p0), rank(p1)) with [p0, p1) its
 // CSR positions, added in its CSR order as the bitmap walk adds them (the
 // same sums, bit for bit) - without fetching a weight line per delivery.
-// Then each row's background and gates.  Every thread of the block calls
-// this (block scans inside).
+// The places are LDS or, for a bucket larger than the LDS holds (glob), the
+// unused part of the bundle's bucket right after its pairs (a few hundred
+// KB per bundle, so it stays in L2).  Then each
+// row's background and gates.  Every thread of the block calls this (block
+// scan and barriers inside).
 template <int kKeep>
 __device__ inline void carried_rows(uint32_t* s_hits, uint32_t* s_scan, const u32x2 (&kept)[kKeep], const Bundle& B,
-                                    const RowsCsr& rows, const RowTail& A, const EventSrc& E, int cnt, int64_t t,
-                                    int tid, uint32_t& ev, uint32_t& evb) {
+                                    const RowsCsr& rows, const RowTail& A, const EventSrc& E, int cnt, bool glob,
+                                    int64_t t, int tid, uint32_t& ev, uint32_t& evb) {
   static_assert(kGatherThreads == kEventThreads, "block_incl_scan takes kEventThreads threads");
   uint32_t* s_pre = s_hits + E.hit_words;
-  uint32_t* s_wt = s_pre + ev_groups(E.hit_words);
+  const u32x2* __restrict__ bk = E.evbuf + B.syn0;
+  uint32_t* const wt_glob = reinterpret_cast<uint32_t*>(E.evbuf + B.syn0 + cnt);
+  uint32_t* const wt_lds = s_pre + ev_groups(E.hit_words);
   const int hw = (B.nsyn >> 5) + 1;
   const int ng = ev_groups(hw);
   // exclusive prefix of the groups' counts (thread tid sums a stripe of groups)
@@ -859,27 +900,51 @@ __device__ inline void carried_rows(uint32_t* s_hits, uint32_t* s_scan, const u3
     for (int q = g * kEvGroupWords; q < min(hw, (g + 1) * kEvGroupWords); ++q) run += uint32_t(__popc(s_hits[q]));
   }
   __syncthreads();
+  // every delivery's weight at its rank: the pairs kept in registers, then
+  // the rest (each loop written for one memory, so LDS stays LDS)
+  auto place = [&](uint32_t* wt) {
 #pragma unroll
-  for (int j = 0; j < kKeep; ++j)
-    if (tid + j * kGatherThreads < cnt) s_wt[hit_rank(s_hits, s_pre, kept[j].x)] = kept[j].y;
-  const u32x2* __restrict__ bk = E.evbuf + B.syn0;
-  for (int q = tid + kKeep * kGatherThreads; q < cnt; q += kGatherThreads) {
-    const u32x2 e = stream_load(bk + q);
-    s_wt[hit_rank(s_hits, s_pre, e.x)] = e.y;
-  }
+    for (int j = 0; j < kKeep; ++j)
+      if (tid + j * kGatherThreads < cnt) wt[hit_rank(s_hits, s_pre, kept[j].x)] = kept[j].y;
+    for (int q = tid + kKeep * kGatherThreads; q < cnt; q += kGatherThreads) {
+      const u32x2 e = bk[q];
+      wt[hit_rank(s_hits, s_pre, e.x)] = e.y;
+    }
+  };
+  if (glob) place(wt_glob);
+  else place(wt_lds);
   __syncthreads();
+  // the rows; each row's pointers and gates are requested one row ahead
+  int64_t k0n = 0, k1n = 0;
+  float jn[4] = {0.f, 0.f, 0.f, 0.f};
+  auto fetch = [&](int64_t r) {
+    if (r < B.row1) {
+      k0n = rows.row_ptr[r];
+      k1n = rows.row_ptr[r + 1];
+      jn[0] = A.j[r];
+      jn[1] = A.j[A.n_pad + r];
+      jn[2] = A.j[2 * A.n_pad + r];
+      jn[3] = A.j[3 * A.n_pad + r];
+    }
+  };
+  fetch(B.row0 + tid);
   for (int64_t r = B.row0 + tid; r < B.row1; r += kGatherThreads) {
-    const int64_t k0 = rows.row_ptr[r], k1 = rows.row_ptr[r + 1];
-    const float jv[4] = {A.j[r], A.j[A.n_pad + r], A.j[2 * A.n_pad + r], A.j[3 * A.n_pad + r]};
+    const int64_t k0 = k0n, k1 = k1n;
+    const float jv[4] = {jn[0], jn[1], jn[2], jn[3]};
+    fetch(r + kGatherThreads);
     const uint32_t a = hit_rank(s_hits, s_pre, uint32_t(k0 - B.syn0));
     const uint32_t b = hit_rank(s_hits, s_pre, uint32_t(k1 - B.syn0));
     float dE = 0.f, dI = 0.f;
-    for (uint32_t k = a; k < b; ++k) {
-      const uint32_t x = s_wt[k];
-      const float wv = __uint_as_float(x & 0x7FFFFFFFu);
-      if (x >> 31) dI += wv;
-      else dE += wv;
-    }
+    auto add = [&](const uint32_t* wt) {
+      for (uint32_t k = a; k < b; ++k) {
+        const uint32_t x = wt[k];
+        const float wv = __uint_as_float(x & 0x7FFFFFFFu);
+        if (x >> 31) dI += wv;
+        else dE += wv;
+      }
+    };
+    if (glob) add(wt_glob);
+    else add(wt_lds);
     ev += b - a;
     evb += row_finish(A, t, r, B.member_row0, B.member, B.seed, dE, dI, jv);
   }
@@ -916,7 +981,8 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
     const u32x2* __restrict__ bk = E.evbuf + B.syn0;
     int q0 = tid;
     if constexpr (kMode != kHitsOut) {
-      // the thread's first kEvKeep pairs stay in registers for the carried weights
+      // the thread's first kEvKeep pairs stay in registers for the carried
+      // weights; the loads of the rest stay cacheable (read again there)
 #pragma unroll
       for (int j = 0; j < kEvKeep; ++j) {
         const int q = tid + j * kGatherThreads;
@@ -930,7 +996,7 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
       q0 = tid + kEvKeep * kGatherThreads;
     }
     for (int q = q0; q < cnt; q += kGatherThreads) {
-      const uint32_t p = stream_load(bk + q).x;
+      const uint32_t p = kMode != kHitsOut ? bk[q].x : stream_load(bk + q).x;
       atomicOr(&s_hits[p >> 5], 1u << (p & 31u));
     }
     if (tid == 0) E.cursor[bi] = uint32_t(B.syn0);
@@ -1019,10 +1085,13 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
     // in LDS (row r's CSR positions [row_ptr[r] - syn0, row_ptr[r+1] -
     // syn0)), then their background and gates.  The delivered events are
     // the hits the rows visit.
-    // With a bucket whose weights fit the LDS, its carried weights; else
-    // (a larger bucket, or no room) the weight of each hit from the CSR.
-    if (kSrc == kFromEvents && E.weight_cap > 0 && s_count <= E.weight_cap)
-      carried_rows(s_hits, s_red[0], kept, B, rows, A, E, s_count, step[0], tid, ev, evb);
+    // The carried weights, placed in LDS when they fit, else in the free
+    // part of the bucket (room for them when the bucket is at most 2/3
+    // full); the weight of each hit from the CSR when the LDS cannot even
+    // hold the prefix counts or the bucket is fuller than that.
+    if (kSrc == kFromEvents && E.weight_cap >= 0 &&
+        (s_count <= E.weight_cap || 3 * int64_t(s_count) <= 2 * int64_t(B.nsyn)))
+      carried_rows(s_hits, s_red[0], kept, B, rows, A, E, s_count, s_count > E.weight_cap, step[0], tid, ev, evb);
     else
       fused_rows<kMode == kSumBF16>(s_hits, B, rows, A, step[0], tid, ev, evb);
   }
@@ -1324,12 +1393,12 @@ void launch_gather_as(const DeviceNet& d, const ConnBlock& cb, const uint32_t* b
                       hipStream_t s) {
   const unsigned grid = unsigned(cb.xcd_max * 8);
   // the fused spike-driven sums take the carried weights when they fit
-  const int cap = kSrc == kFromEvents && kMode != kHitsOut ? ev_weight_cap(cb.hit_words) : 0;
-  const size_t lds = cap > 0 ? size_t(kEvLdsBytes) : size_t(cb.hit_words) * 4;
+  const int cap = kSrc == kFromEvents && kMode != kHitsOut ? ev_weight_cap(cb.hit_words) : -1;
+  const size_t lds = cap >= 0 ? size_t(kEvLdsBytes) : size_t(cb.hit_words) * 4;
   hipLaunchKernelGGL((k_gather<kU, kMode, kSrc>), dim3(grid), dim3(kGatherThreads), lds, s, cb.xcd_first, d.step,
                      cb.bundles, cb.tiles, cb.theads, bitmaps, words_pad, d.slots, cb.hitbuf, d.ev,
                      RowsCsr{cb.row_ptr, cb.wts}, row_tail(d),
-                     EventSrc{reinterpret_cast<const u32x2*>(cb.evbuf), cb.ev_cursor, cb.hit_words, cap});
+                     EventSrc{reinterpret_cast<u32x2*>(cb.evbuf), cb.ev_cursor, cb.hit_words, cap});
 }
 
 template <int kMode>
@@ -1362,9 +1431,12 @@ hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t
 hipError_t launch_events(const DeviceNet& d, hipStream_t s) {
   const ConnBlock& cb = d.loc;
   if (cb.n_bundles == 0) return hipSuccess;
+  const unsigned rgrid = unsigned(std::min<int64_t>(2048, std::max<int64_t>(1, (d.run_cap + kRunThreads - 1) / kRunThreads)));
+  hipLaunchKernelGGL(k_spike_runs, dim3(rgrid), dim3(kRunThreads), 0, s, d.step, d.ids, d.id_count, d.id_slots,
+                     d.n_pad, d.max_delay, cb.ev_soff, d.run_off, d.run_n, d.run_cap);
   const size_t lds = 2 * size_t(kEvStage) * 8 + 3 * size_t(cb.n_bundles) * 4;
   hipLaunchKernelGGL(k_events, dim3(kEventGrid), dim3(kEventThreads), lds, s, d.step, d.ids,
-                     d.id_count, d.id_slots, d.n_pad, d.max_delay, cb.ev_soff,
+                     d.id_count, d.id_slots, d.n_pad, d.max_delay, cb.ev_soff, d.run_off, d.run_n, d.run_cap,
                      reinterpret_cast<const u32x2*>(cb.ev_ent), int32_t(cb.n_bundles), cb.ev_cursor,
                      reinterpret_cast<u32x2*>(cb.evbuf));
   return hipGetLastError();

@@ -58,11 +58,13 @@ def test_spike_driven_equals_sweep_on_a_partition_net(dtb, lam):
     """60,000 neurons, 90 populations, delays 1-20: the 7 Hz and 30 Hz
     drives, both row-sum placements, FP32 and BF16, with and without graph
     replay.  With the row sums fused, three bundle sizes: 20,000 synapses
-    (hundreds of bundles, every bucket's weights fit the LDS and are summed
-    from it), 880,000 (seven bundles with room for about 6,300 carried
-    weights each: at 7 Hz the buckets hold about that many, so a launch
-    mixes bundles summed from carried weights and bundles that fetch them
-    from the CSR) and 1,048,575 (no room: every weight from the CSR)."""
+    (hundreds of bundles, every bucket's weights fit the LDS at once),
+    880,000 (seven bundles with LDS room for about 6,300 carried weights
+    each: at 7 Hz the buckets hold about that many, so a launch mixes
+    bundles that order their weights in LDS and bundles that order them in
+    the free part of their bucket; at 30 Hz every bundle does the latter)
+    and 1,048,575 (the LDS cannot hold the bitmap's prefix counts: every
+    weight from the CSR)."""
     net = netgen.make_network(netgen.partition_spec(n=60_000, bg_lambda=lam))
     T = 120
     print(f"partition n={net.n} lambda={lam}", flush=True)
