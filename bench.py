@@ -34,19 +34,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "synaptic events/s & realtime factor, plain vs BF16/batched; surrogate err"
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "gather_traffic_partition20M_7hz.json")
+TRAFFIC_JSON = {"sweep": os.path.join(ROOT, "profiles", "gather_traffic_partition20M_7hz.json"),
+                "spike-driven": os.path.join(ROOT, "profiles", "gather_events_traffic_partition20M_7hz.json")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2308_01241_amd", "csrc", "dtb_kernels.hip")
 HBM_PEAK_GBS = 8000.0
 RATE_TOLERANCE = 0.15
 OU_BACKGROUND = (0.6, 0.4, 8.0)  # mu, sigma (units of Iext), tau (ms)
 
 
-def measured_traffic(kernel: str = "k_gather"):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since those counters were taken."""
+def measured_traffic(kernel: str = "k_gather", delivery: str = "sweep"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    that delivery mode, or None when the kernel source changed since those
+    counters were taken."""
     import hashlib
     try:
-        with open(TRAFFIC_JSON) as f:
+        with open(TRAFFIC_JSON[delivery]) as f:
             tj = json.load(f)
         with open(KERNEL_SRC, "rb") as f:
             h = hashlib.sha256(f.read()).hexdigest()
@@ -122,7 +124,8 @@ def roofline(per, ms_step, n_syn, n_neu, n_del, ev_step, spk_step, wb):
     achieved = B / (per["gather"] * 1e-3) / 1e9
     step_gbs = Bt / (ms_step * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_gather",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("k_gather", "spike-driven" if spike_driven else "sweep"), "kernel": "k_gather",
             "delivery": "spike-driven" if spike_driven else "sweep", "row_sums_in_gather": fused,
             "algorithmic_bytes_per_launch": B, "avg_launch_ms": per["gather"],
             "step": {"algorithmic_bytes": Bt, "ms": ms_step, "achieved": round(step_gbs, 1),
@@ -320,10 +323,12 @@ def run_batched(steps: int, warmup: int, n_members: int = 64, per_member_steps: 
                "bold_finite": bool(np.isfinite(bold).all())}
     if not members_too:
         return {"workload": f"ensemble: {n_members} members, {n_tot} neurons, {s_tot} synapses", "batched": batched}
-    # the plain path, one member at a time, same gains, graph replays too
+    # the plain path, one member at a time, same gains, same launch shape,
+    # graph replays too
     ev_m, ms_m = 0, 0.0
     for m, nw in enumerate(members):
-        h = dtb.Net(nw, record_steps=64, stream=stream)
+        h = dtb.Net(nw, record_steps=64, stream=stream, bundle_syn=shape[0], unroll=shape[1], fuse=shape[2],
+                    events=shape[3])
         h.set_gains(gains[m])
         h.run(warmup)
         h.sync()

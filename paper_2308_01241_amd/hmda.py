@@ -17,7 +17,17 @@ measured one; the filter itself is in its companion work.  Here:
 * every window of `window` steps (the BOLD sampling interval) the ensemble
   advances as one captured HIP graph, its BOLD is read on the device, and
   one stochastic-EnKF analysis (`dtb_enkf_analysis`, a stand-in for the
-  companion work's filter) updates the gains in place on the device.
+  companion work's filter) updates the gains in place on the device;
+* with surrogate screening (`screen`), a small MLP (the `dtb_mlp` kernels)
+  is first trained on windows of this network run at random gains, mapping
+  (a sample's gains in a window, its population rates over the window
+  before, its hemodynamic state at the window's start) to its BOLD at the
+  window's end; before each window's simulation every sample draws
+  `proposals` candidate gain vectors around its own, the surrogate predicts
+  their BOLD, and the sample takes the candidate that best fits the
+  window's observation (its own gains among them), so the ensemble the
+  batched path simulates and the filter updates has been moved by the
+  cheap model first.
 
 The estimate is checked by re-simulation: one batch of three fresh-noise
 copies of the network, at the estimated gains (ensemble mean), at the prior
@@ -52,6 +62,11 @@ class HmdaSetup:
     lo: float = 0.3
     hi: float = 3.0
     seed: int = 5
+    screen: int = 1            # surrogate screening of proposals before each window (0: EnKF alone)
+    proposals: int = 64        # candidate gain vectors per sample per window
+    step_sd: float = 1.0       # candidate spread, in units of the ensemble's spread per population
+    train_windows: int = 48    # windows of the training data (x members samples)
+    epochs: int = 80
 
 
 def log(*a):
@@ -71,6 +86,66 @@ def _tied_gains(g_exc: np.ndarray) -> np.ndarray:
     out[..., 0] = g_exc
     out[..., 1] = g_exc
     return out
+
+
+def _state_features(ens, t0: int, t1: int, M: int, R: int):
+    """[M, R] population rates over [t0, t1) and [M, 4 R] hemodynamic state
+    (s, f - 1, v - 1, q - 1) now, per sample."""
+    rates = ens.region_rates(t0, t1).reshape(M, R)
+    _, st = ens.bold(state=True)
+    hemo = (st.astype(np.float64) - np.array([0.0, 1.0, 1.0, 1.0])).reshape(M, 4 * R)
+    return rates.astype(np.float32), hemo.astype(np.float32)
+
+
+def train_surrogate(S: HmdaSetup, net, stream):
+    """The screening model: samples of this network at gains ~ 1 + 0.2 N(0, 1)
+    (clipped to [lo, hi]), chained windows from rest, each sample mapping
+    (gains R, rates of the window before R, hemodynamic state 4 R) to the
+    BOLD at the window's end (1e-3 units).  Returns (mlp, x scaler, y
+    scaler, seconds of simulation, seconds of training)."""
+    import paper_2308_01241_amd as dtb
+    from .assimilate import train
+    R, M = S.regions, S.members
+    rng = np.random.default_rng(S.seed + 1000)
+    ens = dtb.Net.batch([dataclasses.replace(net, member=2 * M + 10 + m) for m in range(M)], stream=stream,
+                        record_steps=S.window)
+    X, Y = [], []
+    t0 = time.perf_counter()
+    ens.set_gains(np.ones((M * R, 4), np.float32))
+    ens.run(S.window)
+    prev, hemo = _state_features(ens, ens.t - S.window, ens.t, M, R)
+    for _ in range(S.train_windows):
+        g = np.clip(1.0 + S.prior_sd * rng.standard_normal((M, R)), S.lo, S.hi).astype(np.float32)
+        ens.set_gains(_tied_gains(g).reshape(M * R, 4))
+        ens.run(S.window)
+        y = ens.bold().reshape(M, R)
+        X.append(np.concatenate([g, prev, hemo], axis=1))
+        Y.append(1e3 * y)
+        prev, hemo = _state_features(ens, ens.t - S.window, ens.t, M, R)
+    ens.close()
+    sim_s = time.perf_counter() - t0
+    X, Y = np.concatenate(X).astype(np.float32), np.concatenate(Y).astype(np.float32)
+    t1 = time.perf_counter()
+    m, sx, sy = train(X, Y, epochs=S.epochs, seed=S.seed)
+    return m, sx, sy, sim_s, time.perf_counter() - t1
+
+
+def screen_step(m, sx, sy, g, prev, hemo, y_obs, r_var, S: HmdaSetup, rng):
+    """Each sample's best of its own gains and S.proposals - 1 candidates
+    around them (spread: step_sd x the ensemble's spread per population),
+    by the surrogate's predicted BOLD misfit to the observation.  Returns
+    the new [M, R] gains and how many samples moved."""
+    M, R = g.shape
+    P = S.proposals
+    sd = S.step_sd * np.maximum(g.std(axis=0), 0.02)
+    cand = g[:, None, :] + sd * rng.standard_normal((M, P, R))
+    cand[:, 0, :] = g
+    cand = np.clip(cand, S.lo, S.hi).astype(np.float32)
+    Xc = np.concatenate([cand.reshape(M * P, R), np.repeat(prev, P, axis=0), np.repeat(hemo, P, axis=0)], axis=1)
+    pred = sy.inv(m.forward(sx.f(Xc))).reshape(M, P, R) * 1e-3
+    miss = np.mean((pred - y_obs[None, None, :]) ** 2, axis=2) / r_var
+    best = np.argmin(miss, axis=1)
+    return cand[np.arange(M), best], int(np.count_nonzero(best))
 
 
 def run(S: HmdaSetup):
@@ -98,6 +173,11 @@ def run(S: HmdaSetup):
     yo = y_obs.cpu().numpy()
     r_var = (S.obs_rel * np.sqrt(np.mean(yo ** 2, axis=1)) + 1e-9) ** 2   # [windows]
 
+    sur = None
+    if S.screen:
+        sur = train_surrogate(S, net, stream)
+        log(f"[hmda] surrogate: {S.train_windows * M} samples, {sur[3]:.1f} s simulation, {sur[4]:.1f} s training")
+    srng = np.random.default_rng(S.seed + 2000)
     members = [dataclasses.replace(net, member=m) for m in range(M)]
     ens = dtb.Net.batch(members, stream=stream, record_steps=S.window)
     X = torch.from_numpy(_tied_gains(prior)).cuda()                       # [M, R, 4]
@@ -106,7 +186,18 @@ def run(S: HmdaSetup):
     hist = []
     sim_ms = ana_ms = 0.0
     c_prev = ens.counters()
+    screen_ms, moved = 0.0, []
     for k in range(S.windows):
+        if sur is not None and k > 0:
+            # screened from the state the window starts from (the first
+            # window, from the initial state, has no window before it)
+            prev, hemo = _state_features(ens, ens.t - S.window, ens.t, M, R)
+            tic = time.perf_counter()
+            g_new, n_moved = screen_step(sur[0], sur[1], sur[2], X[:, :, 0].cpu().numpy(), prev, hemo, yo[k],
+                                         r_var[k], S, srng)
+            screen_ms += 1e3 * (time.perf_counter() - tic)
+            moved.append(n_moved)
+            X.copy_(torch.from_numpy(_tied_gains(g_new)).cuda())
         ev[0].record(stream)
         ens.set_gains_from(X.view(M * R, 4))
         ens.run(S.window)
@@ -151,6 +242,12 @@ def run(S: HmdaSetup):
            "bold_rms": float(np.sqrt(np.mean(yo ** 2))),
            "sim_ms_per_window": sim_ms / S.windows, "analysis_ms_per_window": ana_ms / S.windows,
            "history": hist}
+    if sur is not None:
+        out["screening"] = {"training_samples": S.train_windows * M, "training_sim_s": sur[3], "training_s": sur[4],
+                            "proposals_per_window": M * S.proposals,
+                            "screen_ms_per_window": screen_ms / max(1, len(moved)),
+                            "samples_moved_per_window": float(np.mean(moved)) if moved else 0.0}
+        sur[0].close()
     return out
 
 
@@ -159,10 +256,16 @@ def main():
     for f in dataclasses.fields(HmdaSetup):
         ap.add_argument("--" + f.name.replace("_", "-"), type=type(f.default), default=f.default)
     ap.add_argument("--out", type=str, default="")
+    ap.add_argument("--compare", action="store_true", help="also run the EnKF alone (screen 0) and report both")
     a = vars(ap.parse_args())
     out_path = a.pop("out")
+    compare = a.pop("compare")
     S = HmdaSetup(**a)
     rep = run(S)
+    if compare:
+        base = run(dataclasses.replace(S, screen=0))
+        rep["enkf_alone"] = {k: base[k] for k in ("final_gain_rmse", "bold_fit_rmse", "sim_ms_per_window",
+                                                  "analysis_ms_per_window", "history")}
     txt = json.dumps(rep, indent=1)
     if out_path:
         with open(out_path, "w") as f:

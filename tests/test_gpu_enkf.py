@@ -99,10 +99,31 @@ def test_assimilation_loop_recovers_hidden_gains_on_a_small_twin(dtb):
     re-simulated at the estimate the BOLD fits the twin's better than at the
     prior mean."""
     from paper_2308_01241_amd import hmda
-    S = hmda.HmdaSetup(members=32, n=20_000, regions=8, windows=12, window=400)
+    S = hmda.HmdaSetup(members=32, n=20_000, regions=8, windows=12, window=400, screen=0)
     print("hmda small twin", flush=True)
     rep = hmda.run(S)
     assert rep["final_gain_rmse"] < 0.7 * rep["prior_gain_rmse"], rep
     fit = rep["bold_fit_rmse"]
     assert fit["estimated"] < fit["prior_mean"], fit
     assert rep["analysis_ms_per_window"] < 5.0
+
+
+def test_assimilation_loop_with_surrogate_screening(dtb):
+    """The same small twin with surrogate screening before every window:
+    the surrogate (trained on this network's windows at random gains) moves
+    samples to their best-predicted proposals, then the batched path and the
+    EnKF run as before; the estimate still beats the prior mean in gains
+    and in re-simulated BOLD fit, and screening costs far less than the
+    window's simulation."""
+    from paper_2308_01241_amd import hmda
+    S = hmda.HmdaSetup(members=32, n=20_000, regions=8, windows=12, window=400, screen=1, train_windows=24,
+                       epochs=60, proposals=32)
+    print("hmda small twin, screened", flush=True)
+    rep = hmda.run(S)
+    sc = rep["screening"]
+    assert sc["training_samples"] == 24 * 32 and sc["proposals_per_window"] == 32 * 32
+    assert 0 < sc["samples_moved_per_window"] <= 32
+    assert sc["screen_ms_per_window"] < rep["sim_ms_per_window"]
+    assert rep["final_gain_rmse"] < 0.7 * rep["prior_gain_rmse"], rep
+    fit = rep["bold_fit_rmse"]
+    assert fit["estimated"] < fit["prior_mean"], fit
