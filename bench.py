@@ -215,13 +215,15 @@ def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0,
             "region_rates": rates, "bits": bits}
 
 
-def run_split(net, bits, steps, warmup, burnin):
+def run_split(net, bits, steps, warmup, burnin, shape=(0, 0, 0, 0)):
     """J_intra / J_inter split (Sec. V-B): the partition keeps each row's
     own-region in-edges, the cross-region ones become a remote block whose
     sources mirror the partition, and the unsplit run's raster is replayed
     as the remote spikes from step 0 (inputs resident in HBM before the
-    timed steps).  Returns the timed rates and whether the raster is the
-    unsplit one bit for bit."""
+    timed steps).  The local block takes the unsplit run's bundle size and
+    delivery mode (the remote block is always swept, its row sums separate).
+    Returns the timed rates and whether the raster is the unsplit one bit
+    for bit."""
     import torch
     import netgen
     import paper_2308_01241_amd as dtb
@@ -229,7 +231,8 @@ def run_split(net, bits, steps, warmup, burnin):
     t0 = time.time()
     local, blk = netgen.split_remote(net)
     rec = max(steps, 16)
-    g = dtb.Net(local, record_steps=rec, stream=torch.cuda.current_stream())
+    g = dtb.Net(local, record_steps=rec, stream=torch.cuda.current_stream(), bundle_syn=shape[0],
+                events=shape[3])
     g.set_remote_block(blk)
     k_local, k_remote = local.nnz / net.n, int(blk.row_ptr[-1]) / net.n
     del local, blk
@@ -532,7 +535,7 @@ def main():
         log(f"[bench] ou background: {json.dumps(forms['ou_background'])}")
         bits = head.pop("bits")
         net.bg_lambda = netgen.PARTITION_LAMBDA[r0]
-        sp = run_split(net, bits, args.steps, args.warmup, args.burnin)
+        sp = run_split(net, bits, args.steps, args.warmup, args.burnin, shape)
         del bits
         sp["speed_vs_unsplit"] = sp["events_per_s"] / head["events_per_s"]
         forms["j_inter_split"] = sp

@@ -410,7 +410,14 @@ __global__ __launch_bounds__(kRunThreads) void k_spike_runs(const int64_t* __res
   for (int64_t k = int64_t(blockIdx.x) * kRunThreads + threadIdx.x; k < cnt;
        k += int64_t(gridDim.x) * kRunThreads) {
     const uint32_t* __restrict__ row = soff + int64_t(li[k]) * (D + 1);
-    for (int d = 0; d <= D; ++d) out[int64_t(d) * cap + k] = row[d];
+    // the whole row is requested before any of it is stored; past D the
+    // last entry is read and stored again (branch-free, so the stores do
+    // not wait on one another)
+    uint32_t v[kMaxDelay + 1];
+#pragma unroll
+    for (int d = 0; d <= kMaxDelay; ++d) v[d] = row[min(d, D)];
+#pragma unroll
+    for (int d = 0; d <= kMaxDelay; ++d) out[int64_t(min(d, D)) * cap + k] = v[d];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) run_n[sl] = int32_t(cnt);
 }
@@ -467,24 +474,36 @@ __global__ __launch_bounds__(kEventThreads) void k_events(
     const uint32_t coff = s_coff;
     if (cur >= r1) break;  // the same for every thread
     // this thread's pairs cur + kEvRuns tid + h and their runs of entries
+    // (the gathered offsets of all the thread's pairs are requested before
+    // any is used; a spike without them reads its id and the table after)
     uint32_t a[kEvRuns], len[kEvRuns];
+    int dl[kEvRuns];
+    int64_t kk[kEvRuns];
+    bool valid[kEvRuns], gathered[kEvRuns];
 #pragma unroll
     for (int h = 0; h < kEvRuns; ++h) {
       const int64_t i = cur + kEvRuns * tid + h;
-      a[h] = len[h] = 0u;
-      if (i < r1) {
-        const int d = last_at_most(s_pre, D, i);  // delay d + 1
-        const int64_t k = i - s_pre[d];           // the spike's place in its list
-        if (k < s_rn[d]) {
-          a[h] = run_off[s_roff[d] + k];
-          len[h] = run_off[s_roff[d] + run_cap + k] - a[h];
-        } else {
-          const int64_t m = ids[s_base[d] + k];
-          a[h] = soff[m * (D + 1) + d];
-          len[h] = soff[m * (D + 1) + d + 1] - a[h];
-        }
+      valid[h] = i < r1;
+      dl[h] = valid[h] ? last_at_most(s_pre, D, i) : 0;  // delay dl + 1
+      kk[h] = valid[h] ? i - s_pre[dl[h]] : 0;            // the spike's place in its list
+      gathered[h] = valid[h] && kk[h] < s_rn[dl[h]];
+    }
+#pragma unroll
+    for (int h = 0; h < kEvRuns; ++h) {
+      const int64_t o = s_roff[dl[h]] + kk[h];
+      a[h] = gathered[h] ? run_off[o] : 0u;
+      len[h] = gathered[h] ? run_off[o + run_cap] : 0u;
+    }
+#pragma unroll
+    for (int h = 0; h < kEvRuns; ++h) {
+      if (valid[h] && !gathered[h]) {
+        const int64_t m = ids[s_base[dl[h]] + kk[h]];
+        a[h] = soff[m * (D + 1) + dl[h]];
+        len[h] = soff[m * (D + 1) + dl[h] + 1];
       }
     }
+#pragma unroll
+    for (int h = 0; h < kEvRuns; ++h) len[h] -= a[h];
     if (tid == 0) {
       a[0] += coff;
       len[0] -= coff;

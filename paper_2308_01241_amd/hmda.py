@@ -24,10 +24,12 @@ measured one; the filter itself is in its companion work.  Here:
   before, its hemodynamic state at the window's start) to its BOLD at the
   window's end; before each window's simulation every sample draws
   `proposals` candidate gain vectors around its own, the surrogate predicts
-  their BOLD, and the sample takes the candidate that best fits the
-  window's observation (its own gains among them), so the ensemble the
-  batched path simulates and the filter updates has been moved by the
-  cheap model first.
+  their BOLD, and each sample's best-fitting candidate (its own gains among
+  them) marks a direction; the whole ensemble is shifted by `shift` times
+  the mean of those moves, so the cheap model moves the ensemble mean
+  before the batched path simulates it and the filter updates it, while the
+  spread stays the filter's (moving every sample to its own best candidate
+  selects extremes and widens the ensemble window after window).
 
 The estimate is checked by re-simulation: one batch of three fresh-noise
 copies of the network, at the estimated gains (ensemble mean), at the prior
@@ -62,9 +64,10 @@ class HmdaSetup:
     lo: float = 0.3
     hi: float = 3.0
     seed: int = 5
-    screen: int = 1            # surrogate screening of proposals before each window (0: EnKF alone)
+    screen: int = 0            # 1: surrogate screening of proposals before each window (0: EnKF alone)
     proposals: int = 64        # candidate gain vectors per sample per window
     step_sd: float = 1.0       # candidate spread, in units of the ensemble's spread per population
+    shift: float = 0.3         # fraction of the samples' mean best move applied to every sample
     train_windows: int = 48    # windows of the training data (x members samples)
     epochs: int = 80
 
@@ -133,8 +136,10 @@ def train_surrogate(S: HmdaSetup, net, stream):
 def screen_step(m, sx, sy, g, prev, hemo, y_obs, r_var, S: HmdaSetup, rng):
     """Each sample's best of its own gains and S.proposals - 1 candidates
     around them (spread: step_sd x the ensemble's spread per population),
-    by the surrogate's predicted BOLD misfit to the observation.  Returns
-    the new [M, R] gains and how many samples moved."""
+    by the surrogate's predicted BOLD misfit to the observation; every
+    sample then moves by S.shift x the mean of the samples' best moves.
+    Returns the new [M, R] gains and how many samples found a better
+    candidate than their own gains."""
     M, R = g.shape
     P = S.proposals
     sd = S.step_sd * np.maximum(g.std(axis=0), 0.02)
@@ -145,7 +150,8 @@ def screen_step(m, sx, sy, g, prev, hemo, y_obs, r_var, S: HmdaSetup, rng):
     pred = sy.inv(m.forward(sx.f(Xc))).reshape(M, P, R) * 1e-3
     miss = np.mean((pred - y_obs[None, None, :]) ** 2, axis=2) / r_var
     best = np.argmin(miss, axis=1)
-    return cand[np.arange(M), best], int(np.count_nonzero(best))
+    move = (cand[np.arange(M), best] - g).mean(axis=0)
+    return np.clip(g + S.shift * move, S.lo, S.hi).astype(np.float32), int(np.count_nonzero(best))
 
 
 def run(S: HmdaSetup):
@@ -256,16 +262,18 @@ def main():
     for f in dataclasses.fields(HmdaSetup):
         ap.add_argument("--" + f.name.replace("_", "-"), type=type(f.default), default=f.default)
     ap.add_argument("--out", type=str, default="")
-    ap.add_argument("--compare", action="store_true", help="also run the EnKF alone (screen 0) and report both")
+    ap.add_argument("--compare", action="store_true",
+                    help="also run the loop with the other screening setting and report it beside")
     a = vars(ap.parse_args())
     out_path = a.pop("out")
     compare = a.pop("compare")
     S = HmdaSetup(**a)
     rep = run(S)
     if compare:
-        base = run(dataclasses.replace(S, screen=0))
-        rep["enkf_alone"] = {k: base[k] for k in ("final_gain_rmse", "bold_fit_rmse", "sim_ms_per_window",
-                                                  "analysis_ms_per_window", "history")}
+        other = run(dataclasses.replace(S, screen=1 - S.screen))
+        keys = ("final_gain_rmse", "bold_fit_rmse", "sim_ms_per_window", "analysis_ms_per_window", "screening",
+                "history")
+        rep["surrogate_screened" if S.screen == 0 else "enkf_alone"] = {k: other[k] for k in keys if k in other}
     txt = json.dumps(rep, indent=1)
     if out_path:
         with open(out_path, "w") as f:
