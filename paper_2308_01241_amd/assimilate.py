@@ -269,9 +269,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--window", type=int, default=200)
-    ap.add_argument("--runs", type=int, default=157)
-    ap.add_argument("--test-runs", type=int, default=16)
-    ap.add_argument("--segments", type=int, default=10, help="chained gain windows per run")
+    ap.add_argument("--runs", type=int, default=1408)
+    ap.add_argument("--test-runs", type=int, default=157)
+    ap.add_argument("--segments", type=int, default=1, help="chained gain windows per run")
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--iters", type=int, default=8)
     ap.add_argument("--seeds", type=str, default="0,1,2")
