@@ -19,14 +19,17 @@ import numpy as np
 import scipy.stats
 
 
-def _numpy_philox_hi32(seed: int, t: int, i: int, member: int) -> int:
+def _numpy_philox_u32(seed: int, t: int, i: int, member: int) -> int:
+    # one Philox block per eight neurons, counter (t, i // 8, member, 0);
     # numpy's Philox advances its 256-bit counter before producing a block,
-    # so counter c - 1 yields the block of counter c = (t, i, member, 0).
-    c = (t | (i << 64) | (member << 128)) - 1
+    # so counter c - 1 yields the block of counter c, as its four words
+    c = (t | ((i >> 3) << 64) | (member << 128)) - 1
     ctr = [(c >> (64 * k)) & 0xFFFFFFFFFFFFFFFF for k in range(4)]
     bg = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
                           counter=np.array(ctr, dtype=np.uint64))
-    return int(bg.random_raw(1)[0]) >> 32
+    w = int(bg.random_raw(4)[(i & 7) >> 1])
+    # value i mod 8: the word's high half, then its low half
+    return (w & 0xFFFFFFFF) if (i & 1) else (w >> 32)
 
 
 def _thresholds(lam: float) -> np.ndarray:
@@ -94,7 +97,7 @@ def run(net, n_steps: int, forced=None, gain=None):
                 dE += WE[d] @ S[te]
                 dI += WI[d] @ S[te]
                 ev_rec[t] += int((adj[d] @ S[te].astype(np.int64)).sum())
-        c = np.array([_count(_numpy_philox_hi32(net.seed, t, i, net.member), thr)
+        c = np.array([_count(_numpy_philox_u32(net.seed, t, i, net.member), thr)
                       for i in range(n)])
         ev_bg[t] = int(c.sum())
         dE += net.bg_w * c

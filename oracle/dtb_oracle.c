@@ -31,8 +31,10 @@
  *   5. per-region spike counts of step t.
  *
  * Background draws: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), key
- * (seed, 0), counter (t, i, member, 0); the high 32 bits u of output word 0
- * are turned into a Poisson(lambda) count by inversion against the table
+ * (seed, 0), one block per eight neurons: counter (t, floor(i / 8), member,
+ * 0); its four output words give eight 32-bit values (word 0's high half,
+ * word 0's low half, word 1's high half, ...), and neuron i takes value
+ * i mod 8, u, which is turned into a Poisson(lambda) count by inversion against the table
  * T_k = floor(F(k) 2^32) (F the Poisson CDF, entries kept while below
  * 2^32 - 1): c = #{k : u >= T_k}.
  *
@@ -104,11 +106,13 @@ static inline int poisson_count(uint32_t u, const uint32_t* T, int K) {
 }
 
 uint32_t ora_bg_uniform(uint64_t seed, int64_t t, int64_t i, int64_t member) {
-  uint64_t ctr[4] = {(uint64_t)t, (uint64_t)i, (uint64_t)member, 0};
+  uint64_t ctr[4] = {(uint64_t)t, (uint64_t)(i >> 3), (uint64_t)member, 0};
   uint64_t key[2] = {seed, 0};
   uint64_t out[4];
   ora_philox4x64_10(ctr, key, out);
-  return (uint32_t)(out[0] >> 32);
+  const int j = (int)(i & 7);
+  const uint64_t w = out[j >> 1];
+  return (j & 1) ? (uint32_t)w : (uint32_t)(w >> 32);
 }
 
 /* standard normal draw of the OU background: Box-Muller on Philox stream 1 */

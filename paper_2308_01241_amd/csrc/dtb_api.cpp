@@ -694,7 +694,7 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
   }
   const int64_t slots = int64_t(d.slots);
   d.poisson_cap = std::max(1, d.poisson_K);
-  if ((st = dalloc(net, &d.V, d.n_pad)) || (st = dalloc(net, &d.V0, d.n_pad)) ||
+  if ((st = dalloc(net, &d.V, d.n_pad)) || (st = dalloc(net, &d.V0, d.n_pad)) || (st = dalloc(net, &d.bgc, d.n_pad)) ||
       (st = dalloc(net, &d.j, 4 * d.n_pad)) ||
       (st = dalloc(net, &d.ref, d.n_pad)) || (st = dalloc(net, &d.ptype, d.n_pad)) ||
       (st = dalloc(net, &d.region, d.n_pad)) ||

@@ -174,6 +174,7 @@ struct DeviceNet {
   int32_t ou_on = 0;
   float ou_mu = 0.f, ou_a = 0.f, ou_s = 0.f;  // mean, exp(-dt / tau), sigma sqrt(1 - a^2)
   float* ou = nullptr;              // [n_pad] I_ou
+  uint16_t* bgc = nullptr;          // [n_pad] the step's Poisson background count per neuron
   // neuron state (SoA) and tables
   float* V = nullptr;               // [n_pad]
   float* V0 = nullptr;              // [n_pad] initial potentials (for dtb_reset)

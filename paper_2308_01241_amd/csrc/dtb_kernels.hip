@@ -34,10 +34,9 @@ namespace {
 // ------------------------------------------------------------------ RNG
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
 // 64x64 -> 128-bit products, key bumped by the Weyl constants between rounds.
-// returns output word 0 (the high 32 bits of which are the background draw);
-// *w1 (if given) receives output word 1
-__device__ inline uint64_t philox_hi32_word0(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                             uint64_t k0, uint64_t k1, uint64_t* w1 = nullptr) {
+// the four output words of counter (c0, c1, c2, c3), key (k0, k1)
+__device__ inline void philox_block(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
+                                    uint64_t (&out)[4]) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
@@ -54,14 +53,53 @@ __device__ inline uint64_t philox_hi32_word0(uint64_t c0, uint64_t c1, uint64_t 
     c2 = y2;
     c3 = lo0;
   }
-  if (w1) *w1 = c1;
-  return c0 >> 32;
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// the high 32 bits of output word 0; *w1 (if given) receives output word 1
+__device__ inline uint64_t philox_hi32_word0(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                             uint64_t k0, uint64_t k1, uint64_t* w1 = nullptr) {
+  uint64_t out[4];
+  philox_block(c0, c1, c2, c3, k0, k1, out);
+  if (w1) *w1 = out[1];
+  return out[0] >> 32;
 }
 
 __device__ inline int poisson_count(uint32_t u, const uint32_t* __restrict__ T, int K) {
   int c = 0;
   while (c < K && u >= T[c]) ++c;
   return c;
+}
+
+// ------------------------------------------------------------- background
+// The step's Poisson background counts, eight neurons per Philox block:
+// group g of a member network's neurons (its neurons 8g .. 8g + 7) draws
+// counter (t, g, member, 0), key (the member's seed, 0); the block's four
+// words give eight 32-bit values (a word's high half, then its low half),
+// neuron 8g + j takes value j and inverts it against the table.  One
+// workgroup per bundle (a bundle lies inside one member); a group that
+// straddles two bundles is drawn by both, identically.
+constexpr int kBgThreads = 256;
+__global__ __launch_bounds__(kBgThreads) void k_background(const int64_t* __restrict__ step,
+                                                          const Bundle* __restrict__ bundles,
+                                                          const uint32_t* __restrict__ T, int K,
+                                                          uint16_t* __restrict__ bgc) {
+  const Bundle B = bundles[blockIdx.x];
+  const int64_t t = step[0];
+  const int64_t g0 = (B.row0 - B.member_row0) >> 3, g1 = (B.row1 - 1 - B.member_row0) >> 3;
+  for (int64_t g = g0 + threadIdx.x; g <= g1; g += kBgThreads) {
+    uint64_t w[4];
+    philox_block(uint64_t(t), uint64_t(g), uint64_t(B.member), 0ull, B.seed, 0ull, w);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t rr = B.member_row0 + 8 * g + j;
+      const uint32_t u = (j & 1) ? uint32_t(w[j >> 1]) : uint32_t(w[j >> 1] >> 32);
+      if (rr >= B.row0 && rr < B.row1) bgc[rr] = uint16_t(poisson_count(u, T, K));
+    }
+  }
 }
 
 // ----------------------------------------------------------- neuron update
@@ -684,8 +722,7 @@ struct RowTail {
   int64_t n_pad;
   float a0, a1, a2, a3;     // exp(-dt / tau_u)
   float bg_w;               // background weight
-  const uint32_t* poisson;  // inversion table of the background count
-  int K;                    // its entries
+  const uint16_t* bgc;      // the step's background count per row (Poisson background)
   float* ou;                // I_ou [n_pad], or null for the Poisson background
   float ou_mu, ou_a, ou_s;  // OU mean, exp(-dt / tau), sigma sqrt(1 - a^2)
   int32_t* bad;             // non-finite flag
@@ -721,16 +758,12 @@ __device__ inline void walk_add(const uint32_t (&x)[kWalkHits], int nh, float& d
 }
 
 // Row rr's tail at step t after its delivered sums dE / dI: the background
-// count (Philox4x64-10, counter (t, row within its member network, member, 0),
-// key the member's seed) joins the excitatory sum - or, with the OU
-// background, I_ou takes one exact OU step instead - then the four gates
+// count of the step (k_background) joins the excitatory sum - or, with the
+// OU background, I_ou takes one exact OU step instead - then the four gates
 // decay and jump.  Returns the row's background events.
 __device__ inline uint32_t row_finish(const RowTail& A, int64_t t, int64_t rr, int64_t mrow0, int32_t member,
                                       uint64_t seed, float dE, float dI, const float (&jv)[4]) {
-  const uint32_t u = A.ou ? 0u
-                          : uint32_t(philox_hi32_word0(uint64_t(t), uint64_t(rr - mrow0), uint64_t(member), 0ull,
-                                                       seed, 0ull));
-  const int c = poisson_count(u, A.poisson, A.K);
+  const int c = A.ou ? 0 : int(A.bgc[rr]);
   const float de = __fmaf_rn(float(c), A.bg_w, dE);
   const float ja = __fmaf_rn(A.a0, jv[0], de);
   const float jb = __fmaf_rn(A.a1, jv[1], de);
@@ -1380,6 +1413,10 @@ hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipS
                      d.ptype, d.region, d.ptab, d.gain, d.ou_on ? d.ou : nullptr, d.E[0], d.E[1], d.E[2], d.E[3],
                      forced, d.raster,
                      d.words_pad, d.counts, d.n_regions, d.cticket, d.bad);
+  // the step's background counts for the row sums (not with the OU current)
+  if (!d.ou_on && d.loc.n_bundles > 0)
+    hipLaunchKernelGGL(k_background, dim3(unsigned(d.loc.n_bundles)), dim3(kBgThreads), 0, s, d.step, d.loc.bundles,
+                       d.poisson, d.poisson_K, d.bgc);
   return hipGetLastError();
 }
 
@@ -1403,7 +1440,7 @@ hipError_t launch_compact_read(const DeviceNet& d, const int64_t* at, int32_t* i
 namespace {
 
 RowTail row_tail(const DeviceNet& d) {
-  return RowTail{d.j, d.n_pad, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.poisson, d.poisson_K,
+  return RowTail{d.j, d.n_pad, d.a[0], d.a[1], d.a[2], d.a[3], d.bg_w, d.bgc,
                  d.ou_on ? d.ou : nullptr, d.ou_mu, d.ou_a, d.ou_s, d.bad};
 }
 

@@ -1,5 +1,5 @@
 """The learned part end to end on a small ensemble: simulator-generated
-(gains, previous rates) -> (rates, BOLD) samples train the MFMA surrogate,
+(gains, previous rates, hemodynamic state) -> (rates, BOLD) samples train the MFMA surrogate,
 which then screens gain proposals for a twin target; the proposals it picks
 fit the target better, when simulated, than the same number picked at
 random (the method without the surrogate)."""
@@ -20,8 +20,11 @@ def small():
     S = A.Setup(members=16, lo=15_000, hi=30_000, regions=20, window=200, rate_hz=15, target_n=25_000)
     net = dtb.Net.batch(A.member_networks(S, seed=5), record_steps=2 * S.window,
                         stream=torch.cuda.current_stream())
-    X, Y = A.generate(net, S, 48, np.random.default_rng(1), segments=3)
-    Xt, Yt = A.generate(net, S, 16, np.random.default_rng(2), segments=3)
+    # one gain window per run after one at unit gains: how screening
+    # re-simulates a proposal (chained windows train a model whose picks
+    # start from histories the screened proposals never have)
+    X, Y = A.generate(net, S, 144, np.random.default_rng(1), segments=1)
+    Xt, Yt = A.generate(net, S, 48, np.random.default_rng(2), segments=1)
     net.close()
     m, sx, sy = A.train(X, Y, epochs=60, batch=128, seed=3)
     target = netgen.make_network(netgen.ensemble_member_spec(41, S.target_n, rate_hz=S.rate_hz,

@@ -49,6 +49,19 @@ def test_poisson_table_matches_scipy(lam):
     assert np.all(np.diff(T.astype(np.int64)) >= 0)
 
 
+def test_background_uniforms_are_numpy_philox_values():
+    """Neuron i's background value at step t is value i mod 8 of the Philox
+    block of counter (t, i // 8, member, 0) - word (i mod 8) // 2, high half
+    for even i, low half for odd - computed here with numpy's Philox."""
+    from oracle.brute import _numpy_philox_u32
+    for seed, t, member in ((99, 0, 0), (7, 13, 0), (123456789, 4, 3)):
+        for i in list(range(0, 20)) + [63, 64, 65, 1_000_003]:
+            assert oracle.bg_uniform(seed, t, i, member) == _numpy_philox_u32(seed, t, i, member), (seed, t, i)
+    # eight neurons share one block: neighbours in a group draw different values
+    vals = {oracle.bg_uniform(5, 2, i) for i in range(8)}
+    assert len(vals) == 8
+
+
 def test_background_counts_are_poisson():
     lam = 0.7
     T = oracle.poisson_table(lam)
