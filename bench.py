@@ -72,9 +72,10 @@ def gather_bytes(nnz: int, n: int, max_delay: int) -> float:
 
 def rows_bytes(n: int, events: float, w_bytes: int) -> float:
     """Algorithmic bytes of the row sums that follow the delivery tests:
-    row pointers (8 B per row), the weight of each delivered event and the
-    four gates read and written."""
-    return 8.0 * n + w_bytes * events + 32.0 * n
+    row pointers (8 B per row), the weight of each delivered event, the
+    step's Poisson background count (2 B per row, drawn by k_background) and
+    the four gates read and written."""
+    return 8.0 * n + w_bytes * events + 2.0 * n + 32.0 * n
 
 
 def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) -> float:
@@ -85,10 +86,11 @@ def step_bytes(nnz: int, n: int, max_delay: int, events: float, w_bytes: int) ->
 
 
 def events_bytes(events: float, spikes: float, max_delay: int) -> float:
-    """Algorithmic bytes of the spike-driven bucketing: per delivered event
-    its table entry read and its bucket entry written (4 B each); per spike
-    and delay the two offsets of its run in the table, and its id."""
-    return 8.0 * events + spikes * max_delay * 12.0
+    """Algorithmic bytes of the spike-driven bucketing (k_events): per
+    delivered event its table pair (target, weight) read and its bucket pair
+    written (8 B each); per spike and delay the two offsets of its run in the
+    table (gathered into rows by k_spike_runs)."""
+    return 16.0 * events + spikes * max_delay * 8.0
 
 
 def step_bytes_events(n: int, max_delay: int, events: float, spikes: float, w_bytes: int) -> float:
@@ -100,19 +102,21 @@ def step_bytes_events(n: int, max_delay: int, events: float, spikes: float, w_by
 
 
 def roofline(per, ms_step, n_syn, n_neu, n_del, ev_step, spk_step, wb):
-    """The roofline object of the dominant kernel (the consumer of the
-    gather stage: k_gather), with the step as a whole beside it.
+    """The roofline object of the dominant kernel of the gather stage, with
+    the other gather kernel and the step as a whole beside it.
 
-    Sweep mode: the delivery tests stream every synapse's index and delay
-    (5 B) and the D+1 spike bitmaps; with the row sums fused in the same
-    workgroups (fuse 1) their bytes are added, with separate sums (fuse 2)
-    k_sums gets its own line.  Spike-driven mode: k_events buckets each
-    delivered event (its own line); k_gather reads the buckets (4 B per
-    event) and, fused, does the row sums; the step is priced both by its own
-    method's bytes and by the pull method's (the time the pull method would
-    need at peak bandwidth)."""
+    Sweep mode: the delivery tests of k_gather stream every synapse's index
+    and delay (5 B) and the D+1 spike bitmaps; with the row sums fused in the
+    same workgroups (fuse 1) their bytes are added, with separate sums (fuse
+    2) k_sums gets its own line.  Spike-driven mode: k_events buckets each
+    delivered event, k_gather (the consumer) reads the bucket pairs (target
+    and weight, 8 B per event) and, fused, does the row sums; whichever of the
+    two took longer per launch is the dominant kernel.  The step is priced
+    both by its own method's bytes and by the pull method's (the time the
+    pull method would need at peak bandwidth)."""
     spike_driven = per.get("events", 0.0) > 0.0
     fused = per.get("sums", 0.0) == 0.0
+    delivery = "spike-driven" if spike_driven else "sweep"
     Br = rows_bytes(n_neu, ev_step, wb)
     if spike_driven:
         Bg = 4.0 * ev_step
@@ -121,24 +125,31 @@ def roofline(per, ms_step, n_syn, n_neu, n_del, ev_step, spk_step, wb):
         Bg = gather_bytes(n_syn, n_neu, n_del)
         Bt = step_bytes(n_syn, n_neu, n_del, ev_step, wb)
     B = Bg + Br if fused else Bg + n_syn / 8.0
-    achieved = B / (per["gather"] * 1e-3) / 1e9
     step_gbs = Bt / (ms_step * 1e-3) / 1e9
+    lines = {"k_gather": (B, per["gather"])}
+    if spike_driven:
+        lines["k_events"] = (events_bytes(ev_step, spk_step, n_del), per["events"])
+    main = max(lines, key=lambda k: lines[k][1])
+    Bm, tm = lines[main]
+    achieved = Bm / (tm * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("k_gather", "spike-driven" if spike_driven else "sweep"), "kernel": "k_gather",
-            "delivery": "spike-driven" if spike_driven else "sweep", "row_sums_in_gather": fused,
-            "algorithmic_bytes_per_launch": B, "avg_launch_ms": per["gather"],
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(main, delivery),
+            "kernel": main, "delivery": delivery, "row_sums_in_gather": fused,
+            "algorithmic_bytes_per_launch": Bm, "avg_launch_ms": tm,
             "step": {"algorithmic_bytes": Bt, "ms": ms_step, "achieved": round(step_gbs, 1),
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)}}
+    for k, (Bk, tk) in lines.items():
+        if k != main:
+            roof["consumer" if k == "k_gather" else "bucketing"] = {
+                "kernel": k, "algorithmic_bytes_per_launch": Bk, "avg_launch_ms": tk,
+                "achieved": round(Bk / (tk * 1e-3) / 1e9, 1), "frac": round(Bk / (tk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(k, delivery)}
     if spike_driven:
-        Be = events_bytes(ev_step, spk_step, n_del)
-        roof["bucketing"] = {"kernel": "k_events", "algorithmic_bytes_per_launch": Be, "avg_launch_ms": per["events"],
-                             "achieved": round(Be / (per["events"] * 1e-3) / 1e9, 1)}
         Bp = step_bytes(n_syn, n_neu, n_del, ev_step, wb)
         roof["step"]["pull_method_bytes"] = Bp
         roof["step"]["pull_method_ms_at_peak"] = round(Bp / (HBM_PEAK_GBS * 1e9) * 1e3, 4)
     if fused:
-        roof["parts"] = {("bucket_reads" if spike_driven else "delivery_tests"): Bg, "row_sums": Br}
+        roof["gather_parts"] = {("bucket_reads" if spike_driven else "delivery_tests"): Bg, "row_sums": Br}
     else:
         Bs = Br + n_syn / 8.0  # the sums read one hit bit per synapse
         roof["hit_bits_written_per_launch"] = n_syn / 8.0
@@ -159,7 +170,8 @@ def _spread(xs):
 
 def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0, 0), ou=None, keep_bits=False):
     """One rate point: burn in to the stationary rate, save, then `reps`
-    timed repetitions of `steps` steps from that same state."""
+    timed repetitions of `steps` steps from that same state, and one more
+    with per-kernel HIP event timing."""
     import torch
     import paper_2308_01241_amd as dtb
 
@@ -176,22 +188,30 @@ def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0,
     g.step(pre)
     g.sync()
     state = g.save()
-    walls, per_kernel, ev_rep = [], {}, []
-    for _ in range(reps):
+    walls, per_kernel, ev_rep, wall_timed = [], {}, [], None
+    # `reps` plain repetitions give the wall clock; one more, identical (same
+    # state, same steps), brackets every kernel with a pair of HIP events on
+    # the library's stream for the per-kernel durations (the event records
+    # themselves would add to the wall clock of the plain ones)
+    for q in range(reps + 1):
+        timing = q == reps
         g.load(state)
         c0 = g.counters()
-        g.read_timing()
-        g.set_timing(True)
+        if timing:
+            g.read_timing()
+            g.set_timing(True)
         torch.cuda.synchronize()
         tic = time.perf_counter()
         g.step(steps)
         torch.cuda.synchronize()
-        walls.append(time.perf_counter() - tic)
-        g.set_timing(False)
-        for k, v in g.read_timing().items():
-            a = per_kernel.setdefault(k, [0.0, 0])
-            a[0] += v["ms"]
-            a[1] += v["launches"]
+        w = time.perf_counter() - tic
+        if timing:
+            wall_timed = w
+            g.set_timing(False)
+            for k, v in g.read_timing().items():
+                per_kernel[k] = [v["ms"], v["launches"]]
+        else:
+            walls.append(w)
         c1 = g.counters()
         ev_rep.append((c1["ev_rec"] - c0["ev_rec"], c1["ev_bg"] - c0["ev_bg"], c1["spikes"] - c0["spikes"]))
     g.sync()
@@ -211,7 +231,8 @@ def run_rate(net, rate, lam, steps, warmup, burnin, reps, wtype, shape=(0, 0, 0,
             "mean_rate_hz": mean_rate, "on_target": abs(mean_rate - rate) <= RATE_TOLERANCE * rate,
             "region_rate_spread": [float(np.min(rates)), float(np.max(rates))],
             "bg_events_per_s": evb / wall,
-            "kernels": {k: {"ms": v[0] / reps, "launches": v[1] // reps} for k, v in per_kernel.items()},
+            "kernels": {k: {"ms": v[0], "launches": v[1]} for k, v in per_kernel.items()},
+            "ms_per_step_kernel_timing_rep": 1e3 * wall_timed / steps,
             "region_rates": rates, "bits": bits}
 
 
@@ -442,7 +463,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--burnin", type=int, default=300,
                     help="untimed steps that bring each point to its stationary rate before --warmup")
-    ap.add_argument("--reps", type=int, default=5, help="timed repetitions from one saved state")
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions from one saved state (plus one with per-kernel timing)")
     ap.add_argument("--n", type=int, default=20_000_000)
     ap.add_argument("--rates", type=str, default="7,15,30")
     ap.add_argument("--wtype", type=str, default="f32", choices=["f32", "bf16"])

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DTB_ABI_VERSION 13
+#define DTB_ABI_VERSION 14
 
 typedef enum {
   DTB_OK = 0,
@@ -269,8 +269,9 @@ dtb_status dtb_read_counters(dtb_net* net, int64_t* steps, int64_t* spikes, int6
  * (delivery tests, with the row sums when they run there), sums (per-row
  * sums, background, gates), finalize, remote gather (the remote block's
  * delivery tests, timed on the second stream), events (the bucketing of
- * spike-driven deliveries) (double [7], int64 [7]; either may be NULL), and
- * clears them. */
+ * spike-driven deliveries), spike runs (the gathering of the step's table run
+ * offsets for the bucketing), background (the step's Poisson background
+ * counts) (double [9], int64 [9]; either may be NULL), and clears them. */
 dtb_status dtb_set_timing(dtb_net* net, int enable);
 dtb_status dtb_read_timing(dtb_net* net, double* ms, int64_t* launches);
 

@@ -128,7 +128,7 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    if lib.dtb_abi_version() != 13:
+    if lib.dtb_abi_version() != 14:
         raise ImportError("libdtb.so ABI version mismatch")
     _lib = lib
     return lib

@@ -133,6 +133,7 @@ struct dtb_net {
   bool remote = false;
   hipStream_t comm = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t bg_fork = nullptr, bg_join = nullptr;  // the background counts on the second stream
   int64_t rq_head = 0;     // queue row of the first pending remote step
   int64_t rq_pending = 0;  // remote steps pushed and not yet consumed
   uint32_t read_epoch = 0; // spike-list rebuilds so far (their look-back epochs)
@@ -597,6 +598,27 @@ void drop_graph(dtb_net* net) {
   net->graph_steps = 0;
 }
 
+// The step's Poisson background counts go to the second stream: forked at
+// the step's start (the previous step's row sums, their only reader, are
+// done by then) and joined before this step's gather, so the ALU-bound draw
+// runs beside the memory-bound neuron update, compaction and bucketing.
+bool background_on(const DeviceNet& d) { return !d.ou_on && d.loc.n_bundles > 0; }
+
+hipError_t fork_background(dtb_net* net, bool capturing) {
+  if (!background_on(net->d)) return hipSuccess;
+  hipError_t e = hipEventRecord(net->bg_fork, net->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(net->comm, net->bg_fork, 0);
+  if (e == hipSuccess)
+    e = capturing ? launch_background(net->d, net->comm)
+                  : timed(net, 8, [&] { return launch_background(net->d, net->comm); }, net->comm);
+  if (e == hipSuccess) e = hipEventRecord(net->bg_join, net->comm);
+  return e;
+}
+
+hipError_t join_background(dtb_net* net) {
+  return background_on(net->d) ? hipStreamWaitEvent(net->stream, net->bg_join, 0) : hipSuccess;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -617,6 +639,8 @@ void dtb_destroy(dtb_net* net) {
   }
   if (net->fork_ev) (void)hipEventDestroy(net->fork_ev);
   if (net->join_ev) (void)hipEventDestroy(net->join_ev);
+  if (net->bg_fork) (void)hipEventDestroy(net->bg_fork);
+  if (net->bg_join) (void)hipEventDestroy(net->bg_join);
   for (auto& pool : net->ev_pool)
     for (auto& pr : pool) {
       (void)hipEventDestroy(pr.first);
@@ -655,6 +679,8 @@ static dtb_status create_impl(const dtb_desc* desc, dtb_net* net, void* hip_stre
     hipError_t e = hipStreamCreate(&net->comm);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&net->fork_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&net->join_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&net->bg_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&net->bg_join, hipEventDisableTiming);
     if (e != hipSuccess) {
       dtb_destroy(net);
       return fail(DTB_ERR_HIP, std::string("second stream: ") + hipGetErrorString(e));
@@ -981,6 +1007,7 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
       net->rq_head++;
       net->rq_pending--;
     }
+    if (e == hipSuccess) e = fork_background(net, false);
     if (e == hipSuccess) e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
     if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
     // the gather workgroups also sum their rows (fuse == 1) unless a remote
@@ -990,10 +1017,14 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
     if (d.events) {
       // spike-driven delivery: the step's deliveries into per-bundle buckets,
       // then each bundle's hit bitmap from its bucket
+      if (e == hipSuccess) e = timed(net, 7, [&] { return launch_spike_runs(d, net->stream); });
       if (e == hipSuccess) e = timed(net, 6, [&] { return launch_events(d, net->stream); });
+      if (e == hipSuccess) e = join_background(net);
       if (e == hipSuccess) e = timed(net, 2, [&] { return launch_gather_events(d, fuse, net->stream); });
-    } else if (e == hipSuccess) {
-      e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, fuse, net->stream); });
+    } else {
+      if (e == hipSuccess) e = join_background(net);
+      if (e == hipSuccess)
+        e = timed(net, 2, [&] { return launch_gather(d, d.loc, d.raster, d.words_pad, fuse, net->stream); });
     }
     if (e == hipSuccess && net->remote) {
       // J_inter after J_intra, once the remote spikes are in (the paper's
@@ -1028,13 +1059,17 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
     net->graph = nullptr;
     e = hipStreamBeginCapture(net->stream, hipStreamCaptureModeThreadLocal);
     for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
-      e = launch_neuron_update(d, nullptr, net->stream);
+      e = fork_background(net, true);
+      if (e == hipSuccess) e = launch_neuron_update(d, nullptr, net->stream);
       if (e == hipSuccess) e = launch_compact(d, net->stream);
       if (d.events) {
+        if (e == hipSuccess) e = launch_spike_runs(d, net->stream);
         if (e == hipSuccess) e = launch_events(d, net->stream);
-        if (e == hipSuccess) e = launch_gather_events(d, d.fuse == 1, net->stream);
-      } else if (e == hipSuccess) {
-        e = launch_gather(d, d.loc, d.raster, d.words_pad, d.fuse == 1, net->stream);
+      }
+      if (e == hipSuccess) e = join_background(net);
+      if (e == hipSuccess) {
+        e = d.events ? launch_gather_events(d, d.fuse == 1, net->stream)
+                     : launch_gather(d, d.loc, d.raster, d.words_pad, d.fuse == 1, net->stream);
       }
       if (e == hipSuccess && d.fuse != 1) e = launch_sums(d, net->stream);
       if (e == hipSuccess) e = launch_finalize(d, net->stream);

@@ -79,7 +79,8 @@ static_assert(kUpdateNpt == 1 || kUpdateNpt == 2 || kUpdateNpt == 4, "neurons pe
 #define DTB_GATHER_BUNDLE_SYN 1048575
 #endif
 constexpr int kGatherThreads = DTB_GATHER_THREADS;
-constexpr int kTimedKernels = 7;  // neuron update, compaction, gather, sums, finalize, remote gather, events
+constexpr int kTimedKernels = 9;  // neuron update, compaction, gather, sums, finalize, remote gather, events,
+                                  // spike runs, background
 constexpr int kGatherUnroll = DTB_GATHER_UNROLL;
 constexpr int64_t kBundleDefaultSyn = DTB_GATHER_BUNDLE_SYN;
 static_assert(kBundleDefaultSyn <= kBundleMaxSyn, "bundle positions are 20 bits");
@@ -226,6 +227,9 @@ struct DeviceNet {
 // Every kernel reads the step t from d.step, so a sequence of launches can be
 // captured once and replayed; k_finalize (last of a step) advances it.
 hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipStream_t s);
+// the step's Poisson background counts of the local rows (none with the OU
+// current); after the neuron update, before the row sums read them
+hipError_t launch_background(const DeviceNet& d, hipStream_t s);
 hipError_t launch_compact(const DeviceNet& d, hipStream_t s);
 hipError_t launch_compact_read(const DeviceNet& d, const int64_t* at, int32_t* ids, int32_t* count,
                                uint64_t* status, uint32_t* ticket, int64_t* total, hipStream_t s);
@@ -236,10 +240,12 @@ hipError_t launch_sums(const DeviceNet& d, hipStream_t s);
 // the block's hit buffer for launch_sums
 hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t* bitmaps, int64_t words_pad,
                          bool fuse_sums, hipStream_t s);
-// spike-driven delivery of the local block: the deliveries of the spikes of
-// steps t .. t-D+1 through their delays, bucketed per bundle (k_events),
-// then per bundle the hit bitmap from its bucket and, like launch_gather,
-// the row sums or the hit words (k_gather on the buckets)
+// spike-driven delivery of the local block: the table run offsets of the
+// step's spikes gathered once (k_spike_runs, after the compaction), the
+// deliveries of the spikes of steps t .. t-D+1 through their delays bucketed
+// per bundle (k_events), then per bundle the hit bitmap from its bucket and,
+// like launch_gather, the row sums or the hit words (k_gather on the buckets)
+hipError_t launch_spike_runs(const DeviceNet& d, hipStream_t s);
 hipError_t launch_events(const DeviceNet& d, hipStream_t s);
 hipError_t launch_gather_events(const DeviceNet& d, bool fuse_sums, hipStream_t s);
 // observation-error variances of one EnKF analysis, passed by value

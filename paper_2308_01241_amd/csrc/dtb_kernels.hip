@@ -79,25 +79,40 @@ __device__ inline int poisson_count(uint32_t u, const uint32_t* __restrict__ T, 
 // group g of a member network's neurons (its neurons 8g .. 8g + 7) draws
 // counter (t, g, member, 0), key (the member's seed, 0); the block's four
 // words give eight 32-bit values (a word's high half, then its low half),
-// neuron 8g + j takes value j and inverts it against the table.  One
-// workgroup per bundle (a bundle lies inside one member); a group that
-// straddles two bundles is drawn by both, identically.
+// neuron 8g + j takes value j and inverts it against the table (staged in
+// LDS).  One workgroup per bundle (a bundle lies inside one member); a group
+// that straddles two bundles is drawn by both, identically, and each writes
+// its own rows.  A group inside the bundle whose first row is a multiple of
+// eight writes its eight counts with one 16-byte store.
 constexpr int kBgThreads = 256;
 __global__ __launch_bounds__(kBgThreads) void k_background(const int64_t* __restrict__ step,
                                                           const Bundle* __restrict__ bundles,
                                                           const uint32_t* __restrict__ T, int K,
                                                           uint16_t* __restrict__ bgc) {
+  __shared__ uint32_t s_T[kMaxPoisson];
+  for (int c = threadIdx.x; c < K; c += kBgThreads) s_T[c] = T[c];
+  __syncthreads();
   const Bundle B = bundles[blockIdx.x];
   const int64_t t = step[0];
   const int64_t g0 = (B.row0 - B.member_row0) >> 3, g1 = (B.row1 - 1 - B.member_row0) >> 3;
   for (int64_t g = g0 + threadIdx.x; g <= g1; g += kBgThreads) {
     uint64_t w[4];
     philox_block(uint64_t(t), uint64_t(g), uint64_t(B.member), 0ull, B.seed, 0ull, w);
+    uint32_t c[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t rr = B.member_row0 + 8 * g + j;
-      const uint32_t u = (j & 1) ? uint32_t(w[j >> 1]) : uint32_t(w[j >> 1] >> 32);
-      if (rr >= B.row0 && rr < B.row1) bgc[rr] = uint16_t(poisson_count(u, T, K));
+    for (int j = 0; j < 8; ++j) c[j] = uint32_t(poisson_count((j & 1) ? uint32_t(w[j >> 1]) : uint32_t(w[j >> 1] >> 32), s_T, K));
+    const int64_t r0 = B.member_row0 + 8 * g;
+    if ((r0 & 7) == 0 && r0 >= B.row0 && r0 + 8 <= B.row1) {
+      uint4 q;
+      q.x = c[0] | (c[1] << 16);
+      q.y = c[2] | (c[3] << 16);
+      q.z = c[4] | (c[5] << 16);
+      q.w = c[6] | (c[7] << 16);
+      *reinterpret_cast<uint4*>(bgc + r0) = q;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (r0 + j >= B.row0 && r0 + j < B.row1) bgc[r0 + j] = uint16_t(c[j]);
     }
   }
 }
@@ -1413,10 +1428,13 @@ hipError_t launch_neuron_update(const DeviceNet& d, const uint32_t* forced, hipS
                      d.ptype, d.region, d.ptab, d.gain, d.ou_on ? d.ou : nullptr, d.E[0], d.E[1], d.E[2], d.E[3],
                      forced, d.raster,
                      d.words_pad, d.counts, d.n_regions, d.cticket, d.bad);
-  // the step's background counts for the row sums (not with the OU current)
-  if (!d.ou_on && d.loc.n_bundles > 0)
-    hipLaunchKernelGGL(k_background, dim3(unsigned(d.loc.n_bundles)), dim3(kBgThreads), 0, s, d.step, d.loc.bundles,
-                       d.poisson, d.poisson_K, d.bgc);
+  return hipGetLastError();
+}
+
+hipError_t launch_background(const DeviceNet& d, hipStream_t s) {
+  if (d.ou_on || d.loc.n_bundles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_background, dim3(unsigned(d.loc.n_bundles)), dim3(kBgThreads), 0, s, d.step, d.loc.bundles,
+                     d.poisson, d.poisson_K, d.bgc);
   return hipGetLastError();
 }
 
@@ -1484,12 +1502,18 @@ hipError_t launch_gather(const DeviceNet& d, const ConnBlock& cb, const uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_events(const DeviceNet& d, hipStream_t s) {
+hipError_t launch_spike_runs(const DeviceNet& d, hipStream_t s) {
   const ConnBlock& cb = d.loc;
   if (cb.n_bundles == 0) return hipSuccess;
   const unsigned rgrid = unsigned(std::min<int64_t>(2048, std::max<int64_t>(1, (d.run_cap + kRunThreads - 1) / kRunThreads)));
   hipLaunchKernelGGL(k_spike_runs, dim3(rgrid), dim3(kRunThreads), 0, s, d.step, d.ids, d.id_count, d.id_slots,
                      d.n_pad, d.max_delay, cb.ev_soff, d.run_off, d.run_n, d.run_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_events(const DeviceNet& d, hipStream_t s) {
+  const ConnBlock& cb = d.loc;
+  if (cb.n_bundles == 0) return hipSuccess;
   const size_t lds = 2 * size_t(kEvStage) * 8 + 3 * size_t(cb.n_bundles) * 4;
   hipLaunchKernelGGL(k_events, dim3(kEventGrid), dim3(kEventThreads), lds, s, d.step, d.ids,
                      d.id_count, d.id_slots, d.n_pad, d.max_delay, cb.ev_soff, d.run_off, d.run_n, d.run_cap,

@@ -201,10 +201,11 @@ class Net:
 
     def read_timing(self) -> dict:
         """Summed kernel durations (ms) and launch counts since the last read."""
-        ms = np.zeros(7, dtype=np.float64)
-        n = np.zeros(7, dtype=np.int64)
+        ms = np.zeros(9, dtype=np.float64)
+        n = np.zeros(9, dtype=np.int64)
         check(self._lib.dtb_read_timing(self._h, _ptr(ms), _ptr(n)))
-        names = ("neuron_update", "compact", "gather", "sums", "finalize", "remote_gather", "events")
+        names = ("neuron_update", "compact", "gather", "sums", "finalize", "remote_gather", "events",
+                 "spike_runs", "background")
         return {k: {"ms": float(ms[q]), "launches": int(n[q])} for q, k in enumerate(names)}
 
     def sync(self) -> None:

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_bitmap_words(lib):
-    assert lib.dtb_abi_version() == 13
+    assert lib.dtb_abi_version() == 14
     assert [lib.dtb_bitmap_words(n) for n in (0, 1, 32, 33, 64)] == [0, 1, 1, 2, 2]
     assert isinstance(lib.dtb_last_error(), bytes)
 
