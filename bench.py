@@ -36,7 +36,8 @@ sys.path.insert(0, ROOT)
 METRIC = "synaptic events/s & realtime factor, plain vs BF16/batched; surrogate err"
 TRAFFIC_JSON = {"sweep": os.path.join(ROOT, "profiles", "gather_traffic_partition20M_7hz.json"),
                 "spike-driven": os.path.join(ROOT, "profiles", "gather_events_traffic_partition20M_7hz.json")}
-KERNEL_SRC = os.path.join(ROOT, "paper_2308_01241_amd", "csrc", "dtb_kernels.hip")
+# the kernels and the constants that shape them (LDS layout, tile sizes)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2308_01241_amd", "csrc", f) for f in ("dtb_kernels.hip", "dtb_internal.h")]
 HBM_PEAK_GBS = 8000.0
 RATE_TOLERANCE = 0.15
 OU_BACKGROUND = (0.6, 0.4, 8.0)  # mu, sigma (units of Iext), tau (ms)
@@ -45,13 +46,17 @@ OU_BACKGROUND = (0.6, 0.4, 8.0)  # mu, sigma (units of Iext), tau (ms)
 def measured_traffic(kernel: str = "k_gather", delivery: str = "sweep"):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     that delivery mode, or None when the kernel source changed since those
-    counters were taken."""
+    counters were taken (the summary stores the SHA-256 of the kernel
+    sources, concatenated in KERNEL_SRCS order)."""
     import hashlib
     try:
         with open(TRAFFIC_JSON[delivery]) as f:
             tj = json.load(f)
-        with open(KERNEL_SRC, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in KERNEL_SRCS:
+            with open(src, "rb") as f:
+                h.update(f.read())
+        h = h.hexdigest()
     except OSError:
         return None
     if tj.get("kernel_source_sha256") != h or kernel not in tj.get("per_launch", {}):

@@ -598,10 +598,11 @@ void drop_graph(dtb_net* net) {
   net->graph_steps = 0;
 }
 
-// The step's Poisson background counts go to the second stream: forked at
-// the step's start (the previous step's row sums, their only reader, are
-// done by then) and joined before this step's gather, so the ALU-bound draw
-// runs beside the memory-bound neuron update, compaction and bucketing.
+// The step's Poisson background counts go to the second stream: forked
+// after the neuron update is enqueued (the previous step's row sums, their
+// only reader, are done by then) and joined before this step's gather, so
+// the ALU-bound draw shares the CUs with the latency-bound compaction and
+// bucketing (one bucketing workgroup per CU leaves room beside it).
 bool background_on(const DeviceNet& d) { return !d.ou_on && d.loc.n_bundles > 0; }
 
 hipError_t fork_background(dtb_net* net, bool capturing) {
@@ -1007,8 +1008,8 @@ dtb_status dtb_step(dtb_net* net, int32_t n_steps) {
       net->rq_head++;
       net->rq_pending--;
     }
-    if (e == hipSuccess) e = fork_background(net, false);
     if (e == hipSuccess) e = timed(net, 0, [&] { return launch_neuron_update(d, forced, net->stream); });
+    if (e == hipSuccess) e = fork_background(net, false);
     if (e == hipSuccess) e = timed(net, 1, [&] { return launch_compact(d, net->stream); });
     // the gather workgroups also sum their rows (fuse == 1) unless a remote
     // block is set: then both blocks' hit bits go to k_sums (local, then
@@ -1059,8 +1060,8 @@ dtb_status dtb_run(dtb_net* net, int32_t n_steps) {
     net->graph = nullptr;
     e = hipStreamBeginCapture(net->stream, hipStreamCaptureModeThreadLocal);
     for (int32_t q = 0; q < n_steps && e == hipSuccess; ++q) {
-      e = fork_background(net, true);
-      if (e == hipSuccess) e = launch_neuron_update(d, nullptr, net->stream);
+      e = launch_neuron_update(d, nullptr, net->stream);
+      if (e == hipSuccess) e = fork_background(net, true);
       if (e == hipSuccess) e = launch_compact(d, net->stream);
       if (d.events) {
         if (e == hipSuccess) e = launch_spike_runs(d, net->stream);
