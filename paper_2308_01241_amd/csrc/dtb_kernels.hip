@@ -5,15 +5,21 @@
 //                    threshold / reset / refractory, wavefront ballot into
 //                    the step's spike bitmap (a slot of the delay ring of
 //                    bitmaps), per-population spike counts;
+//   k_background     (on the library's second stream, joined before the
+//                    gather) the step's Poisson counts that stand in for the
+//                    spikes of other partitions (J_inter), one Philox block
+//                    per eight neurons;
 //   k_compact        ascending spike-id list from the bitmap (ballot
 //                    popcounts, block scan, decoupled look-back);
-//   k_gather         delivery tests of the pull over each row's in-edges
-//                    through the delay ring (J_intra), in (delay, source)
-//                    order, into a hit bitmap per bundle; then, in the same
-//                    workgroup, per row: delivered weights in CSR order,
-//                    the Poisson count that stands in for the spikes of
-//                    other partitions (J_inter), the gate update (jump +
-//                    exact decay);
+//   k_spike_runs,    spike-driven delivery only: the table run offsets of
+//   k_events         the step's spikes, then the deliveries of the spikes of
+//                    the last D steps bucketed per bundle;
+//   k_gather         the hit bitmap per bundle of J_intra - from the pull
+//                    over each row's in-edges through the delay ring, in
+//                    (delay, source) order, or from the bundle's bucket;
+//                    then, in the same workgroup, per row: delivered weights
+//                    in CSR order, the background count, the gate update
+//                    (jump + exact decay);
 //   k_sums           the per-row part alone, when a remote in-edge block
 //                    is gathered too (local, then remote, then background);
 //   k_finalize       per-step event totals, BOLD, ring slot, step counter.
@@ -1187,9 +1193,8 @@ void k_gather(const int64_t* __restrict__ xcd_first, const int64_t* __restrict__
 // ------------------------------------------------------------------- sums
 // One thread per neuron (row): the delivered weights in the row's CSR order
 // (the fixed per-neuron summation order) - the local block, then the remote
-// block if there is one - then the background count (Philox4x64-10, counter
-// (t, i, member, 0) with i the neuron's index inside its member network),
-// then the four gates (exact decay + jump).  A row's delivery tests are the
+// block if there is one - then the step's background count (drawn by
+// k_background), then the four gates (exact decay + jump).  A row's delivery tests are the
 // bits hbit0 + (k - syn0) of its bundle in the block's hit buffer.
 constexpr int kSumsRowsPerBlock = 1024;  // rows per workgroup (the block table's granularity)
 
