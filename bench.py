@@ -4,16 +4,19 @@
 Workload (default): 20,000,000 neurons in 90 log-normally sized regions,
 in-degree 100 (2e9 synapses), delays 1-20 steps, dt = 1 ms, background
 drive tuned to ~7 / 15 / 30 Hz.  A "step" is one pass of the whole hot path
-(membrane update + spike bitmap + compaction + pull gather through the delay
-ring + background + gate update + counters).  Inputs are synthetic and
-seeded (netgen), resident in HBM before timing starts.
+(membrane update + spike bitmap + compaction + delivery through the delay
+ring, spike-driven or by the pull sweep as the tuned launch shape says +
+background + gate update + counters).  Inputs are synthetic and seeded
+(netgen), resident in HBM before timing starts.
 
 Each rate's network is first run to its stationary firing (`--burnin` steps,
 untimed, whatever `--warmup` is), then `--warmup` more steps; that state is
 saved, and every one of `--reps` repetitions loads it and times exactly
 `--steps` steps, so all repetitions do the same work (median, min and max
-reported).  The run fails (exit status 3, after the JSON line) when the
-measured mean rate of a point is more than 15 % from its target.
+reported); one more identical repetition times every kernel with HIP events
+(the per-kernel durations and the roofline).  The run fails (exit status 3,
+after the JSON line) when the measured mean rate of a point is more than
+15 % from its target.
 
 Prints one JSON line.  `value` is synaptic events/s of the plain FP32 path
 at the 7 Hz point; the other rates, the realtime factor, the gather roofline,
