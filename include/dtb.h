@@ -18,9 +18,13 @@
  *    failure of the calling thread.
  *  - Input arrays are borrowed only for the duration of the call that takes
  *    them and are deep-copied; the library never keeps or frees caller memory.
- *  - All GPU work is enqueued on the hipStream_t given at creation (a
- *    void* here; NULL = the legacy default stream).  Reads into device
- *    memory are stream-ordered; reads into host memory synchronize the stream.
+ *  - All GPU work is ordered on the hipStream_t given at creation (a
+ *    void* here; NULL = the legacy default stream).  Parts of a step (the
+ *    background draw, a remote block's landing) run on a private second
+ *    stream of the handle, forked from that stream and joined back into it
+ *    within the same step, so its order and its synchronization cover them.
+ *    Reads into device memory are stream-ordered; reads into host memory
+ *    synchronize the stream.
  *  - Neuron ids are 0..n-1.  Spike bitmaps hold neuron i at bit (i & 31) of
  *    32-bit word (i >> 5); a step's bitmap has dtb_bitmap_words(n) words.
  *  - Errors found while validating inputs return DTB_ERR_INVALID with a
