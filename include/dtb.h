@@ -19,7 +19,8 @@
  *  - Input arrays are borrowed only for the duration of the call that takes
  *    them and are deep-copied; the library never keeps or frees caller memory.
  *  - All GPU work is ordered on the hipStream_t given at creation (a
- *    void* here; NULL = the legacy default stream).  Parts of a step (the
+ *    void* here; NULL = a private blocking stream of the handle, which the
+ *    legacy default stream orders against).  Parts of a step (the
  *    background draw, a remote block's landing) run on a private second
  *    stream of the handle, forked from that stream and joined back into it
  *    within the same step, so its order and its synchronization cover them.
